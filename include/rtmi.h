@@ -1,0 +1,160 @@
+/*
+ * rtmi.h -- C ABI of the MI355X (gfx950) emission-absorption ray march.
+ *
+ * The method is the time-dependent ray tracer of Ray-trax (arXiv 2511.09389), Sec. 2:
+ * from each source, N_Omega rays on a Fibonacci (golden-angle) lattice march
+ * N_s = ceil(c dt / ds) substeps. At substep k a ray at x_k reads j by trilinear
+ * interpolation and kappa from the nearest voxel, applies Eq. (2)
+ *     x_{k+1} = x_k + n ds,  tau_{k+1} = tau_k + kappa ds,
+ *     I_{k+1} = I_k exp(-kappa ds) + j exp(-tau_k) ds,
+ * and deposits the post-attenuation I_{k+1} back onto the grid with the same trilinear
+ * weights, scaled by 4 pi / N_Omega. Indexing is clamped to the box: rays that leave it
+ * keep marching and deposit on the nearest boundary voxels.
+ *
+ * Conventions shared by every entry point:
+ *  - Maps and fields are DEVICE memory owned by the caller: contiguous float32, C order
+ *    [nx][ny][nz] (z fastest). Voxel (a, b, c) sits at grid coordinate (a, b, c), and
+ *    source positions are given in these grid coordinates (Appendix A, "source_pos").
+ *    The library never frees or retains caller memory beyond the call's stream work.
+ *  - Per-source arrays (source_pos, num_rays, substep_cap) and kappa_scale are HOST
+ *    memory; they are read during the call and may be reused as soon as it returns.
+ *  - All device work is enqueued on `stream` (a hipStream_t; NULL = the default stream).
+ *    Calls return without synchronising the stream.
+ *  - Output fields are OVERWRITTEN: zeroed, then accumulated, in stream order.
+ *  - Directions: the FP64 lattice rounded to binary32, cached per (device, N_Omega) in
+ *    device memory the library owns for the life of the process. The first call with a
+ *    new N_Omega on a device allocates and uploads that table; call rtmi_prepare() first
+ *    to keep later calls free of allocation (e.g. under stream capture).
+ *  - Sample points: x_k = fl(src + fl(fl(k ds) n)) in binary32, computed without fused
+ *    multiply-add, so that floor/round index decisions are reproducible by an
+ *    independent implementation.
+ *  - Status: RTMI_OK (0) or a negative RTMI_ERR_* code. Arguments are validated before
+ *    any work is enqueued; on error nothing is enqueued and rtmi_last_error() returns a
+ *    message for the calling thread. Map contents are not scanned for NaN/Inf.
+ *  - Limits: 1 <= nx, ny, nz and nx*ny*nz < 2^31; 1 <= num_rays <= 2^24; N_s <= 2^24.
+ */
+#ifndef RTMI_H
+#define RTMI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  RTMI_OK = 0,
+  RTMI_ERR_INVALID_ARG = -1, /* null pointer, count <= 0, ds <= 0, c < 0 or dt < 0 */
+  RTMI_ERR_SHAPE = -2,       /* a grid dimension < 1 or nx*ny*nz >= 2^31 */
+  RTMI_ERR_NONFINITE = -3,   /* a scalar argument or source position is NaN or Inf */
+  RTMI_ERR_HIP = -4,         /* a HIP runtime call failed (message names it) */
+  RTMI_ERR_UNSUPPORTED = -5, /* a combination this build does not implement */
+  RTMI_ERR_RANGE = -6        /* N_s or num_rays beyond 2^24 */
+};
+
+/* Accumulation modes (rtmi_options.accum_mode). */
+enum {
+  /* Float32 atomic adds; results agree with the FP64 oracle to the tolerances of the
+   * tests, but the last bits depend on the order the hardware performs the adds. */
+  RTMI_ACCUM_ATOMIC = 0,
+  /* Each deposit is rounded to a 64-bit fixed-point number (a power-of-two scale chosen
+   * on the device from max|j| and the worst-case sum) and added with integer atomics,
+   * so the field is bitwise reproducible across runs and launch shapes. */
+  RTMI_ACCUM_DETERMINISTIC = 1
+};
+
+/* Optional settings; pass NULL for the defaults (all fields zero). */
+typedef struct rtmi_options {
+  int32_t accum_mode;       /* RTMI_ACCUM_ATOMIC or RTMI_ACCUM_DETERMINISTIC */
+  /* Explicit HOST direction table [num_rays][3] (unit vectors, any order) replacing the
+   * Fibonacci lattice for every source; then every source must use the same num_rays.
+   * Uploaded per call (allocates): a test hook for closed forms and symmetry checks. */
+  const float* directions;
+  float ray_weight;         /* weight per ray with explicit directions; <= 0: 4 pi/num_rays */
+  int32_t reserved;
+} rtmi_options;
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* rtmi_last_error(void);
+
+/* ABI version of this library (major * 100 + minor). */
+int32_t rtmi_version(void);
+
+/* N_s = ceil(c dt / ds) (Sec. 2 after Eq. (2)), the quotient taken in binary64 on the
+ * binary32 arguments; when cap > 0 the result is min(N_s, cap). Returns N_s >= 0, or a
+ * negative RTMI_ERR_* code for ds <= 0, c < 0, dt < 0, non-finite input, or N_s > 2^24. */
+int64_t rtmi_num_substeps(float step_size, float radiation_velocity, float time_step,
+                          int32_t cap);
+
+/* Fibonacci (golden-angle) lattice of Sec. 2, written to HOST memory host_xyz[n][3] in
+ * lattice order: z_i = 1 - (2i+1)/n, r_i = sqrt(1 - z_i^2), phi_i = 2 pi frac(i g) with
+ * g = (3 - sqrt(5))/2, n_i = (r_i cos phi_i, r_i sin phi_i, z_i) on array axes (0,1,2),
+ * evaluated in binary64 and rounded to binary32. This is the table the march uses. */
+int32_t rtmi_fibonacci_directions(int32_t n, float* host_xyz);
+
+/* Build (once) the device direction table for n rays on the current device, so that
+ * later calls with this N_Omega allocate nothing. */
+int32_t rtmi_prepare(int32_t num_rays);
+
+/* The single-source kernel of Sec. 2: advance the field over one dt for one source.
+ * Arguments mirror the paper's (j_map, kappa_map, source_pos, num_rays, step_size,
+ * radiation_velocity, time_step). source_pos: HOST float[3]. out_field: DEVICE
+ * float[nx][ny][nz], overwritten with J = sum over rays of the deposits. */
+int32_t rtmi_trace_single(const float* j_map, const float* kappa_map,
+                          int32_t nx, int32_t ny, int32_t nz,
+                          const float* source_pos, int32_t num_rays, float step_size,
+                          float radiation_velocity, float time_step,
+                          float* out_field, void* stream);
+
+/* The multi-source routine of Sec. 2 ("loop-and-sum"): out_field = sum over sources of
+ * rtmi_trace_single with a shared j_map, each source with its own N_Omega and, if
+ * substep_cap is not NULL, its own cap (cap <= 0: none). source_pos: HOST
+ * float[n_src][3]; num_rays, substep_cap: HOST int32[n_src]. Work for all sources is
+ * one pass over the device; the order of the sum over sources is not specified. */
+int32_t rtmi_trace_multi(const float* j_map, const float* kappa_map,
+                         int32_t nx, int32_t ny, int32_t nz, int32_t n_src,
+                         const float* source_pos, const int32_t* num_rays,
+                         const int32_t* substep_cap, float step_size,
+                         float radiation_velocity, float time_step,
+                         float* out_field, void* stream);
+
+/* Frequency bins as a batch axis (Sec. 2, "Frequency-bin agnosticism"): bin b is an
+ * independent multi-source problem with emissivity j_b and opacity kappa_b, written to
+ * out_fields + b * nx*ny*nz.
+ *   j_b     = j_maps + b * j_bin_stride          (stride 0: one j shared by all bins)
+ *   kappa_b = kappa_maps + b * kappa_bin_stride  (stride > 0: per-bin maps), or, with
+ *             stride 0, kappa_maps * kappa_scale[b] (kappa_scale HOST float[n_bins];
+ *             NULL means all ones), the product rounded to binary32.
+ * Strides are in elements. opts may be NULL. */
+int32_t rtmi_trace_bins(const float* j_maps, int64_t j_bin_stride,
+                        const float* kappa_maps, int64_t kappa_bin_stride,
+                        const float* kappa_scale, int32_t n_bins,
+                        int32_t nx, int32_t ny, int32_t nz, int32_t n_src,
+                        const float* source_pos, const int32_t* num_rays,
+                        const int32_t* substep_cap, float step_size,
+                        float radiation_velocity, float time_step,
+                        float* out_fields, const rtmi_options* opts, void* stream);
+
+/* Per-ray intensities of one source (a check of Eq. (2) on the device): writes
+ * I_{k+1} for ray i (lattice order) and substep k to out_rays[i * n_s + k] (DEVICE
+ * float[num_rays][n_s], n_s = rtmi_num_substeps(ds, c, dt, cap)) and, if out_tau is
+ * not NULL, tau_{k+1} to out_tau in the same layout. No field is written. */
+int32_t rtmi_debug_rays(const float* j_map, const float* kappa_map,
+                        int32_t nx, int32_t ny, int32_t nz, const float* source_pos,
+                        int32_t num_rays, float step_size, float radiation_velocity,
+                        float time_step, int32_t cap, float* out_rays, float* out_tau,
+                        void* stream);
+
+/* Measurement hooks. While enabled (on != 0), every march launch is bracketed by a pair
+ * of HIP events recorded on the launch stream. rtmi_timing_read() waits for the recorded
+ * events, returns the summed elapsed milliseconds and the number of launches since the
+ * last enable/reset, and resets the sums. Events are created outside any capture; do
+ * not enable timing while a stream is being captured. */
+int32_t rtmi_timing_enable(int32_t on);
+int32_t rtmi_timing_read(double* total_ms, int64_t* launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTMI_H */

@@ -1,0 +1,41 @@
+"""Compile librtmi.so for gfx950 with hipcc (in-tree, next to this file)."""
+
+import os
+import shutil
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(PKG, "librtmi.so")
+SOURCES = ["api.hip", "march.hip"]
+
+
+def hipcc():
+    for cand in (os.environ.get("HIPCC"), shutil.which("hipcc"), "/opt/rocm/bin/hipcc"):
+        if cand and os.path.exists(cand):
+            return cand
+    raise RuntimeError("hipcc not found; the HIP library cannot be built")
+
+
+def build(verbose=False):
+    """Build librtmi.so; always recompiles. Raises CalledProcessError on failure."""
+    tmp = LIB + ".tmp"
+    cmd = [hipcc(), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+           # packed FP32 instructions stay off in all device code
+           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+           # host code: no contraction into FMA (direction tables are binary64 -> binary32)
+           "-Xarch_host", "-ffp-contract=off",
+           "-Wall", "-Wno-unused-result",
+           "-I", INCLUDE, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True, cwd=PKG)
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

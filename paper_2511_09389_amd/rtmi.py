@@ -1,0 +1,239 @@
+"""Python binding of librtmi (ctypes): argument marshalling only.
+
+Every step of the march runs in the HIP library; this module checks tensor placement,
+dtype and layout, passes raw device pointers, host arrays and the current HIP stream,
+and turns non-zero status codes into exceptions. Importing it fails loudly when the
+library has not been built: there is no fallback implementation.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librtmi.so")
+
+OK = 0
+ERR_INVALID_ARG = -1
+ERR_SHAPE = -2
+ERR_NONFINITE = -3
+ERR_HIP = -4
+ERR_UNSUPPORTED = -5
+ERR_RANGE = -6
+ACCUM_ATOMIC = 0
+ACCUM_DETERMINISTIC = 1
+
+
+class RtmiError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"librtmi error {code}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("accum_mode", ctypes.c_int32), ("directions", ctypes.c_void_p),
+                ("ray_weight", ctypes.c_float), ("reserved", ctypes.c_int32)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2511_09389_amd.build` "
+                          "(or __graft_entry__.build()); there is no non-HIP fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, F32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+    sig = {
+        "rtmi_last_error": (ctypes.c_char_p, []),
+        "rtmi_version": (I32, []),
+        "rtmi_num_substeps": (I64, [F32, F32, F32, I32]),
+        "rtmi_fibonacci_directions": (I32, [I32, P]),
+        "rtmi_prepare": (I32, [I32]),
+        "rtmi_trace_single": (I32, [P, P, I32, I32, I32, P, I32, F32, F32, F32, P, P]),
+        "rtmi_trace_multi": (I32, [P, P, I32, I32, I32, I32, P, P, P, F32, F32, F32, P, P]),
+        "rtmi_trace_bins": (I32, [P, I64, P, I64, P, I32, I32, I32, I32, I32, P, P, P, F32, F32,
+                                  F32, P, ctypes.POINTER(Options), P]),
+        "rtmi_debug_rays": (I32, [P, P, I32, I32, I32, P, I32, F32, F32, F32, I32, P, P, P]),
+        "rtmi_timing_enable": (I32, [I32]),
+        "rtmi_timing_read": (I32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+def _check(code):
+    if code != OK:
+        raise RtmiError(int(code), lib.rtmi_last_error().decode())
+
+
+def _dev(t, name, ndim=None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a HIP device")
+    if t.dtype != torch.float32:
+        raise TypeError(f"{name} must be float32 (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (C order)")
+    if ndim is not None and t.dim() not in ((ndim,) if isinstance(ndim, int) else ndim):
+        raise ValueError(f"{name} has {t.dim()} dims, expected {ndim}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _host_f32(a, shape_last=None):
+    arr = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    if shape_last is not None:
+        arr = arr.reshape(-1, shape_last)
+    return arr
+
+
+def version():
+    return int(lib.rtmi_version())
+
+
+def num_substeps(step_size, radiation_velocity, time_step, cap=0):
+    n = int(lib.rtmi_num_substeps(step_size, radiation_velocity, time_step, int(cap)))
+    if n < 0:
+        raise RtmiError(n, lib.rtmi_last_error().decode())
+    return n
+
+
+def fibonacci_directions(n):
+    out = np.empty((int(n), 3), dtype=np.float32)
+    _check(lib.rtmi_fibonacci_directions(int(n), out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def prepare(num_rays, device=None):
+    with torch.cuda.device(device if device is not None else torch.cuda.current_device()):
+        _check(lib.rtmi_prepare(int(num_rays)))
+
+
+def _new_field(shape, like):
+    return torch.empty(shape, dtype=torch.float32, device=like.device)
+
+
+def trace_single(j_map, kappa_map, source_pos, num_rays, step_size, radiation_velocity,
+                 time_step, out=None):
+    """The single-source kernel; returns J as a float32 tensor shaped like j_map."""
+    if tuple(kappa_map.shape) != tuple(j_map.shape):
+        raise ValueError("j_map and kappa_map must have the same shape")
+    nx, ny, nz = j_map.shape
+    out = _new_field(j_map.shape, j_map) if out is None else out
+    src = _host_f32(source_pos).reshape(3)
+    with torch.cuda.device(j_map.device):
+        _check(lib.rtmi_trace_single(_dev(j_map, "j_map", 3), _dev(kappa_map, "kappa_map", 3),
+                                     nx, ny, nz, src.ctypes.data_as(ctypes.c_void_p), int(num_rays),
+                                     step_size, radiation_velocity, time_step,
+                                     _dev(out, "out", 3), _stream(j_map.device)))
+    return out
+
+
+def _per_source(source_pos, num_rays, substep_cap):
+    src = _host_f32(source_pos, 3)
+    n_src = src.shape[0]
+    nr = np.ascontiguousarray(np.broadcast_to(np.asarray(num_rays, np.int32), (n_src,)))
+    cap = None
+    if substep_cap is not None:
+        cap = np.ascontiguousarray(np.broadcast_to(np.asarray(substep_cap, np.int32), (n_src,)))
+    return src, nr, cap
+
+
+def trace_multi(j_map, kappa_map, source_pos, num_rays, step_size, radiation_velocity,
+                time_step, substep_cap=None, out=None):
+    """Sum over sources of the single-source kernel with a shared j_map."""
+    if tuple(kappa_map.shape) != tuple(j_map.shape):
+        raise ValueError("j_map and kappa_map must have the same shape")
+    nx, ny, nz = j_map.shape
+    src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
+    out = _new_field(j_map.shape, j_map) if out is None else out
+    with torch.cuda.device(j_map.device):
+        _check(lib.rtmi_trace_multi(_dev(j_map, "j_map", 3), _dev(kappa_map, "kappa_map", 3),
+                                    nx, ny, nz, src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
+                                    nr.ctypes.data_as(ctypes.c_void_p),
+                                    None if cap is None else cap.ctypes.data_as(ctypes.c_void_p),
+                                    step_size, radiation_velocity, time_step, _dev(out, "out", 3),
+                                    _stream(j_map.device)))
+    return out
+
+
+def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
+               time_step, kappa_scale=None, substep_cap=None, out=None, deterministic=False,
+               directions=None, ray_weight=0.0):
+    """Frequency bins as a batch axis. j_maps / kappa_maps are 3-D (shared by all bins) or
+    4-D [B][nx][ny][nz]; a 3-D kappa with kappa_scale gives kappa_b = kappa * scale[b].
+    Returns a [B][nx][ny][nz] float32 tensor."""
+    grid = tuple(j_maps.shape[-3:])
+    if tuple(kappa_maps.shape[-3:]) != grid:
+        raise ValueError("j and kappa grids differ")
+    cells = grid[0] * grid[1] * grid[2]
+    b_j = j_maps.shape[0] if j_maps.dim() == 4 else 1
+    b_k = kappa_maps.shape[0] if kappa_maps.dim() == 4 else 1
+    scale = None
+    if kappa_maps.dim() == 4:
+        if kappa_scale is not None:
+            raise ValueError("kappa_scale applies to a shared 3-D kappa only")
+    elif kappa_scale is not None:
+        scale = _host_f32(kappa_scale).ravel()
+    n_bins = max(b_j, b_k, 1 if scale is None else scale.size)
+    for nb, what in ((b_j, "j_maps"), (b_k, "kappa_maps")):
+        if nb not in (1, n_bins):
+            raise ValueError(f"{what} has {nb} bins, expected 1 or {n_bins}")
+    if scale is not None and scale.size != n_bins:
+        raise ValueError("kappa_scale must have one entry per bin")
+    src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
+    out = _new_field((n_bins,) + grid, j_maps) if out is None else out
+    opts = Options(ACCUM_DETERMINISTIC if deterministic else ACCUM_ATOMIC, None, float(ray_weight), 0)
+    dirs = None
+    if directions is not None:
+        dirs = _host_f32(directions, 3)
+        opts.directions = dirs.ctypes.data
+    with torch.cuda.device(j_maps.device):
+        _check(lib.rtmi_trace_bins(
+            _dev(j_maps, "j_maps", (3, 4)), cells if (j_maps.dim() == 4 and b_j > 1) else 0,
+            _dev(kappa_maps, "kappa_maps", (3, 4)), cells if (kappa_maps.dim() == 4 and b_k > 1) else 0,
+            None if scale is None else scale.ctypes.data_as(ctypes.c_void_p), n_bins,
+            grid[0], grid[1], grid[2], src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
+            nr.ctypes.data_as(ctypes.c_void_p),
+            None if cap is None else cap.ctypes.data_as(ctypes.c_void_p),
+            step_size, radiation_velocity, time_step, _dev(out, "out", 4), ctypes.byref(opts),
+            _stream(j_maps.device)))
+    return out
+
+
+def debug_rays(j_map, kappa_map, source_pos, num_rays, step_size, radiation_velocity,
+               time_step, cap=0):
+    """Per-ray I_{k+1} and tau_{k+1} of one source, lattice order: two [N][N_s] tensors."""
+    nx, ny, nz = j_map.shape
+    n_s = num_substeps(step_size, radiation_velocity, time_step, cap)
+    rays = torch.zeros((int(num_rays), n_s), dtype=torch.float32, device=j_map.device)
+    tau = torch.zeros_like(rays)
+    src = _host_f32(source_pos).reshape(3)
+    with torch.cuda.device(j_map.device):
+        _check(lib.rtmi_debug_rays(_dev(j_map, "j_map", 3), _dev(kappa_map, "kappa_map", 3),
+                                   nx, ny, nz, src.ctypes.data_as(ctypes.c_void_p), int(num_rays),
+                                   step_size, radiation_velocity, time_step, int(cap),
+                                   _dev(rays, "out_rays", 2), _dev(tau, "out_tau", 2),
+                                   _stream(j_map.device)))
+    return rays, tau
+
+
+def timing_enable(on=True):
+    """Bracket every march launch with HIP events on its stream (measurement only)."""
+    _check(lib.rtmi_timing_enable(1 if on else 0))
+
+
+def timing_read():
+    """(total milliseconds, launch count) of the march launches timed since the last read."""
+    ms = ctypes.c_double(0.0)
+    n = ctypes.c_int64(0)
+    _check(lib.rtmi_timing_read(ctypes.byref(ms), ctypes.byref(n)))
+    return ms.value, n.value

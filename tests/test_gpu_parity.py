@@ -1,0 +1,218 @@
+"""GPU parity: the HIP march (through the C ABI) against the FP64 oracle.
+
+Tolerance (binary32 field vs binary64 oracle): relative L2 error <= 1e-5 over the field,
+and per-voxel relative error <= 1e-4 wherever the oracle's field exceeds 1e-6 of its
+maximum. Index decisions (floor, round) are taken on the same binary32 sample points on
+both sides, so the remaining differences are binary32 rounding in the gathers, the
+exponentials, the recurrence and the atomic sums.
+"""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2511_09389_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+PER_VOXEL = 1e-4
+FLOOR = 1e-6
+
+
+def note(msg):
+    print(f"[gpu-parity] {msg}", file=sys.stderr, flush=True)
+
+
+def assert_parity(got, want, rel_l2=REL_L2, per_voxel=PER_VOXEL, floor=FLOOR):
+    got = np.asarray(got, dtype=np.float64)
+    want = np.asarray(want, dtype=np.float64)
+    assert got.shape == want.shape
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    mask = want > floor * want.max()
+    rel = np.abs(got[mask] - want[mask]) / want[mask]
+    assert err <= rel_l2, f"rel L2 {err:.3e} > {rel_l2}"
+    assert rel.max() <= per_voxel, f"max per-voxel rel {rel.max():.3e} > {per_voxel}"
+    return err, float(rel.max())
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch.device("cuda:0")
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
+
+
+def test_uniform_blob_parity(rt, dev):
+    w = inputs.uniform_blob()
+    note("uniform_blob 32^3, 256 rays, 32 substeps")
+    got = rt.trace_single(to_dev(w.j_map, dev), to_dev(w.kappa_map, dev), w.source_pos[0], 256,
+                          w.step_size, w.radiation_velocity, w.time_step).cpu().numpy()
+    want = oracle.trace_single(w.j_map, w.kappa_map, w.source_pos[0], 256, w.step_size,
+                               w.radiation_velocity, w.time_step)
+    assert_parity(got, want)
+
+
+@pytest.mark.parametrize("shape,rays,caps", [
+    ((40, 40, 40), [1, 100, 257, 300, 777], [0, 13, 0, 40, 7]),
+    ((37, 29, 45), [256, 511, 64], [0, 0, 21]),
+])
+def test_ragged_multi_source_parity(rt, dev, shape, rays, caps):
+    rng = np.random.default_rng(7)
+    n_src = len(rays)
+    kap = inputs.lognormal_kappa(max(shape), 0.05, 1.0, rng)[:shape[0], :shape[1], :shape[2]].copy()
+    centres = rng.uniform(-2.0, np.array(shape) + 1.0, size=(n_src, 3)).astype(np.float32)
+    j = np.zeros(shape, np.float32)
+    for ci, c in enumerate(centres):
+        j += (inputs.gaussian_blobs(max(shape), [c], [1.5], [1.0 + ci])[:shape[0], :shape[1], :shape[2]])
+    note(f"ragged multi-source {shape} rays={rays} caps={caps}")
+    got = rt.trace_multi(to_dev(j, dev), to_dev(kap, dev), centres, rays, 0.5, 30.0, 1.0,
+                         substep_cap=caps).cpu().numpy()
+    want = oracle.trace_multi(j, kap, centres, rays, 0.5, 30.0, 1.0, caps=caps)
+    assert_parity(got, want)
+
+
+def test_turbulent_full_size_parity(rt, dev):
+    """128^3, 16 sources, 4096 rays, 256 substeps: the benchmark workload, full field."""
+    w = inputs.turbulent()
+    note("turbulent 128^3 x 16 sources x 4096 rays x 256 substeps")
+    got = rt.trace_multi(to_dev(w.j_map, dev), to_dev(w.kappa_map, dev), w.source_pos, w.num_rays,
+                         w.step_size, w.radiation_velocity, w.time_step).cpu().numpy()
+    want = oracle.trace_multi(w.j_map, w.kappa_map, w.source_pos, w.num_rays, w.step_size,
+                              w.radiation_velocity, w.time_step)
+    err, mx = assert_parity(got, want)
+    note(f"turbulent full: rel L2 {err:.2e}, max per-voxel {mx:.2e}")
+
+
+def test_uneven_bins_full_grid_subset_parity(rt, dev):
+    """256^3 with 4 frequency bins and per-source N_Omega / caps; the oracle covers a
+    subset of the sources (fields add over sources), chosen to span the N_Omega range."""
+    w = inputs.uneven_bins()
+    cost = w.num_rays.astype(np.int64) * w.substep_cap
+    picks = []
+    for nr in sorted(set(w.num_rays.tolist())):
+        idx = np.flatnonzero(w.num_rays == nr)
+        picks.append(int(idx[np.argmin(cost[idx])]))
+    picks = [p for p in picks if cost[p] <= 2_000_000][:4]
+    src, nr, cap = w.source_pos[picks], w.num_rays[picks], w.substep_cap[picks]
+    note(f"uneven bins 256^3, sources {picks} rays {nr.tolist()} caps {cap.tolist()}")
+    got = rt.trace_bins(to_dev(w.j_map, dev), to_dev(w.kappa_map, dev), src, nr, w.step_size,
+                        w.radiation_velocity, w.time_step, kappa_scale=w.kappa_scale,
+                        substep_cap=cap).cpu().numpy()
+    want = oracle.trace_bins(w.j_map, w.kappa_map, w.kappa_scale, src, nr, w.step_size,
+                             w.radiation_velocity, w.time_step, caps=cap)
+    for b in range(w.n_bins):
+        assert_parity(got[b], want[b])
+
+
+def test_per_bin_maps_parity(rt, dev):
+    rng = np.random.default_rng(3)
+    shape = (20, 22, 18)
+    js = rng.random((3,) + shape).astype(np.float32)
+    ks = (0.2 * rng.random((3,) + shape)).astype(np.float32)
+    src = np.array([[10.2, 11.7, 8.4], [3.0, 20.0, 1.5]], np.float32)
+    note("per-bin j and kappa maps, 3 bins")
+    got = rt.trace_bins(to_dev(js, dev), to_dev(ks, dev), src, [300, 129], 0.5, 12.0, 1.0).cpu().numpy()
+    want = oracle.trace_bins(js, None, None, src, [300, 129], 0.5, 12.0, 1.0, kappa_maps=ks)
+    for b in range(3):
+        assert_parity(got[b], want[b])
+    # shared j with per-bin kappa, and five bins (two launches of bins)
+    ks5 = (0.2 * rng.random((5,) + shape)).astype(np.float32)
+    got = rt.trace_bins(to_dev(js[0], dev), to_dev(ks5, dev), src, [64, 64], 0.5, 12.0, 1.0).cpu().numpy()
+    want = oracle.trace_bins(js[0], None, None, src, [64, 64], 0.5, 12.0, 1.0, kappa_maps=ks5)
+    for b in range(5):
+        assert_parity(got[b], want[b])
+
+
+def test_debug_rays_match_oracle_and_recurrence(rt, dev):
+    w = inputs.small_turbulent(n=24, n_src=1, num_rays=96, c=20.0)
+    note("per-ray traces, 96 rays x 40 substeps")
+    gi, gt = rt.debug_rays(to_dev(w.j_map, dev), to_dev(w.kappa_map, dev), w.source_pos[0], 96,
+                           0.5, 20.0, 1.0)
+    _, wi, wt = oracle.trace_single(w.j_map, w.kappa_map, w.source_pos[0], 96, 0.5, 20.0, 1.0,
+                                    return_rays=True)
+    gi, gt = gi.cpu().numpy(), gt.cpu().numpy()
+    assert np.allclose(gt, wt, rtol=2e-6, atol=1e-7)
+    scale = np.abs(wi).max(axis=1, keepdims=True)
+    assert np.max(np.abs(gi - wi) / scale) < 1e-5
+
+
+def test_conservation_on_gpu(rt, dev):
+    w = inputs.small_turbulent(n=24, n_src=1, num_rays=200, c=30.0)
+    jd, kd = to_dev(w.j_map, dev), to_dev(w.kappa_map, dev)
+    field = rt.trace_single(jd, kd, w.source_pos[0], 200, 0.5, 30.0, 1.0)
+    rays, _ = rt.debug_rays(jd, kd, w.source_pos[0], 200, 0.5, 30.0, 1.0)
+    total = field.double().sum().item()
+    want = 4.0 * math.pi / 200 * rays.double().sum().item()
+    assert abs(total - want) <= 1e-5 * want
+
+
+def test_deterministic_mode_is_bitwise_repeatable(rt, dev):
+    w = inputs.small_turbulent(n=32, n_src=4, num_rays=700, c=24.0)
+    jd, kd = to_dev(w.j_map, dev), to_dev(w.kappa_map, dev)
+    note("deterministic accumulation, 4 sources x 700 rays")
+    a = rt.trace_bins(jd, kd, w.source_pos, 700, 0.5, 24.0, 1.0, deterministic=True)
+    b = rt.trace_bins(jd, kd, w.source_pos, 700, 0.5, 24.0, 1.0, deterministic=True)
+    assert torch.equal(a, b)
+    # the order of the sources does not change a bit
+    c = rt.trace_bins(jd, kd, w.source_pos[::-1].copy(), 700, 0.5, 24.0, 1.0, deterministic=True)
+    assert torch.equal(a, c)
+    want = oracle.trace_multi(w.j_map, w.kappa_map, w.source_pos, 700, 0.5, 24.0, 1.0)
+    assert_parity(a[0].cpu().numpy(), want)
+
+
+def test_axis_ray_closed_form_on_gpu(rt, dev):
+    """One ray along +x with weight 4 pi: J[s+m] = 4 pi 1.5 j0 ds e^{-kappa m}(1 + cosh(kappa ds))."""
+    n = 12
+    shape = (n, 5, 6)
+    s = (3, 2, 4)
+    kap0 = float(np.float32(0.2))
+    j = np.zeros(shape, np.float32)
+    j[s] = 2.0
+    kap = np.full(shape, kap0, np.float32)
+    got = rt.trace_bins(to_dev(j, dev), to_dev(kap, dev), np.array([s], np.float32), 1, 0.5, 15.0, 1.0,
+                        directions=[[1.0, 0.0, 0.0]], ray_weight=4.0 * math.pi)[0].cpu().numpy()
+    line = got[:, s[1], s[2]]
+    for m in range(1, n - 1 - s[0]):
+        want = 4.0 * math.pi * 1.5 * 2.0 * 0.5 * math.exp(-kap0 * m) * (1.0 + math.cosh(kap0 * 0.5))
+        assert abs(line[s[0] + m] - want) <= 2e-6 * want
+    assert np.count_nonzero(got) == n - s[0]
+
+
+def test_edge_cases(rt, dev):
+    w = inputs.small_turbulent(n=10, n_src=2, num_rays=33, c=6.0)
+    jd, kd = to_dev(w.j_map, dev), to_dev(w.kappa_map, dev)
+    # zero substeps: the output is overwritten with zeros
+    out = torch.full(w.shape, 7.0, device=dev)
+    rt.trace_single(jd, kd, w.source_pos[0], 33, 0.5, 6.0, 0.0, out=out)
+    assert not out.any()
+    # a 1x1x1 grid: every deposit lands on the one voxel
+    one = torch.ones((1, 1, 1), device=dev)
+    f = rt.trace_single(one, one * 0.1, (0.0, 0.0, 0.0), 5, 0.5, 2.0, 1.0).item()
+    want = oracle.trace_single(np.ones((1, 1, 1)), np.full((1, 1, 1), 0.1, np.float32), (0, 0, 0), 5,
+                               0.5, 2.0, 1.0).item()
+    assert abs(f - want) <= 1e-6 * want
+    # a source outside the box, and a single ray
+    for src, nr in [((-5.5, 3.0, 12.25), 64), ((4.0, 4.0, 4.0), 1)]:
+        got = rt.trace_single(jd, kd, src, nr, 0.5, 6.0, 1.0).cpu().numpy()
+        want = oracle.trace_single(w.j_map, w.kappa_map, src, nr, 0.5, 6.0, 1.0)
+        assert_parity(got, want)
+
+
+def test_errors_raise(rt, dev):
+    j = torch.zeros((4, 4, 4), device=dev)
+    with pytest.raises(rt.RtmiError) as e:
+        rt.trace_single(j, j, (1.0, 1.0, 1.0), 0, 0.5, 2.0, 1.0)
+    assert e.value.code == rt.ERR_INVALID_ARG
+    with pytest.raises(rt.RtmiError) as e:
+        rt.trace_single(j, j, (float("nan"), 1.0, 1.0), 8, 0.5, 2.0, 1.0)
+    assert e.value.code == rt.ERR_NONFINITE
+    with pytest.raises(TypeError):
+        rt.trace_single(j.double(), j, (1.0, 1.0, 1.0), 8, 0.5, 2.0, 1.0)
