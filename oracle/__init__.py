@@ -29,3 +29,4 @@ from .march import (  # noqa: F401
     trace_multi,
     trace_bins,
 )
+from .adjoint import trace_single_vjp, trace_multi_vjp  # noqa: F401
