@@ -57,9 +57,11 @@ enum {
   /* Float32 atomic adds; results agree with the FP64 oracle to the tolerances of the
    * tests, but the last bits depend on the order the hardware performs the adds. */
   RTMI_ACCUM_ATOMIC = 0,
-  /* Each deposit is rounded to a 64-bit fixed-point number (a power-of-two scale chosen
-   * on the device from max|j| and the worst-case sum) and added with integer atomics,
-   * so the field is bitwise reproducible across runs and launch shapes. */
+  /* Deposits are rounded to 64-bit fixed point (a power-of-two scale chosen on the
+   * device from max|j| and the worst-case sum) and added with integer atomics, so the
+   * field is bitwise reproducible from run to run and does not depend on the order of
+   * the sources or on scheduling. (Short per-lane partial sums are formed in a fixed
+   * order set by the build before rounding.) Assumes kappa >= 0. */
   RTMI_ACCUM_DETERMINISTIC = 1
 };
 
@@ -71,8 +73,19 @@ typedef struct rtmi_options {
    * Uploaded per call (allocates): a test hook for closed forms and symmetry checks. */
   const float* directions;
   float ray_weight;         /* weight per ray with explicit directions; <= 0: 4 pi/num_rays */
-  int32_t reserved;
+  int32_t path;             /* RTMI_PATH_TILED (default) or RTMI_PATH_DIRECT */
 } rtmi_options;
+
+/* Execution paths (rtmi_options.path). Both compute the same field.
+ *  RTMI_PATH_TILED: two kernels. A record kernel runs each ray's recurrence and writes
+ *    the deposit value of every substep to a workspace; a tile kernel then lets each
+ *    work-group own a 16^3 block of the output, accumulate the deposits landing in it
+ *    in LDS and store it once. Workspace: 4 bytes per (ray, substep, bin), taken from a
+ *    stream-ordered pool the library owns per device (allocated on first use, then
+ *    reused; see rtmi_reserve).
+ *  RTMI_PATH_DIRECT: one kernel; each lane sums its ray's consecutive deposits into a
+ *    2x2x2 register window and flushes it with global atomics. No workspace. */
+enum { RTMI_PATH_TILED = 0, RTMI_PATH_DIRECT = 1 };
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char* rtmi_last_error(void);
@@ -95,6 +108,11 @@ int32_t rtmi_fibonacci_directions(int32_t n, float* host_xyz);
 /* Build (once) the device direction table for n rays on the current device, so that
  * later calls with this N_Omega allocate nothing. */
 int32_t rtmi_prepare(int32_t num_rays);
+
+/* Grow the current device's workspace pool so that tiled calls needing up to `bytes`
+ * of workspace allocate nothing from the system (their pool allocations are then
+ * served from memory the pool already holds). */
+int32_t rtmi_reserve(int64_t bytes);
 
 /* The single-source kernel of Sec. 2: advance the field over one dt for one source.
  * Arguments mirror the paper's (j_map, kappa_map, source_pos, num_rays, step_size,
@@ -135,6 +153,24 @@ int32_t rtmi_trace_bins(const float* j_maps, int64_t j_bin_stride,
                         float radiation_velocity, float time_step,
                         float* out_fields, const rtmi_options* opts, void* stream);
 
+/* Adjoint of rtmi_trace_multi (Sec. 4: gradients of a loss through the tracer, here
+ * written out by the chain rule on Eq. (2) instead of automatic differentiation): given
+ * grad_field = dL/dJ (DEVICE float[nx][ny][nz]), writes dL/dj to grad_j and dL/dkappa to
+ * grad_kappa (DEVICE float[nx][ny][nz] each, overwritten). The reverse sweep recomputes
+ * each ray's forward state from checkpoints kept every few substeps rather than storing
+ * trajectories. Per ray and substep k, in reverse order:
+ *   g = (4 pi/N) * trilinear gather of G at x_k;  Ibar_{k+1} = g + Ibar_{k+2} a_{k+1};
+ *   dL/dj     += trilinear deposit of Ibar_{k+1} E_k ds at x_k;
+ *   dL/dkappa[nearest voxel of x_k] += -ds (Ibar_{k+1} I_k a_k + sum_{k'>k} Ibar_{k'+1} j_{k'} E_{k'} ds).
+ * Other arguments as rtmi_trace_multi; workspace from the library pool (about 12 bytes
+ * per ray-substep plus 8 bytes per voxel). */
+int32_t rtmi_trace_vjp(const float* j_map, const float* kappa_map,
+                       int32_t nx, int32_t ny, int32_t nz, int32_t n_src,
+                       const float* source_pos, const int32_t* num_rays,
+                       const int32_t* substep_cap, float step_size,
+                       float radiation_velocity, float time_step, const float* grad_field,
+                       float* grad_j, float* grad_kappa, void* stream);
+
 /* Per-ray intensities of one source (a check of Eq. (2) on the device): writes
  * I_{k+1} for ray i (lattice order) and substep k to out_rays[i * n_s + k] (DEVICE
  * float[num_rays][n_s], n_s = rtmi_num_substeps(ds, c, dt, cap)) and, if out_tau is
@@ -145,13 +181,15 @@ int32_t rtmi_debug_rays(const float* j_map, const float* kappa_map,
                         float time_step, int32_t cap, float* out_rays, float* out_tau,
                         void* stream);
 
-/* Measurement hooks. While enabled (on != 0), every march launch is bracketed by a pair
- * of HIP events recorded on the launch stream. rtmi_timing_read() waits for the recorded
- * events, returns the summed elapsed milliseconds and the number of launches since the
- * last enable/reset, and resets the sums. Events are created outside any capture; do
+/* Measurement hooks. While enabled (on != 0), every launch of a march kernel is bracketed
+ * by a pair of HIP events recorded on its launch stream, tallied per kernel kind:
+ * RTMI_KERNEL_RECORD and RTMI_KERNEL_TILE (tiled path), RTMI_KERNEL_DIRECT. Reading
+ * waits for that kind's recorded events, returns the summed elapsed milliseconds and the
+ * number of launches since the last enable or read of that kind, and resets them. Do
  * not enable timing while a stream is being captured. */
+enum { RTMI_KERNEL_RECORD = 0, RTMI_KERNEL_TILE = 1, RTMI_KERNEL_DIRECT = 2 };
 int32_t rtmi_timing_enable(int32_t on);
-int32_t rtmi_timing_read(double* total_ms, int64_t* launches);
+int32_t rtmi_timing_read(int32_t kind, double* total_ms, int64_t* launches);
 
 #ifdef __cplusplus
 }

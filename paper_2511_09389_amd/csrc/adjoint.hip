@@ -1,0 +1,184 @@
+// Adjoint (vector-Jacobian product) of the march, for gradients with respect to j and kappa.
+//
+// With G = dL/dJ, a_k = exp(-kappa_k ds), E_k = exp(-tau_k) and c = 4 pi / N_Omega, the chain
+// rule on Eq. (2) gives, per ray and in reverse substep order,
+//   g_{k+1}    = c * sum_corners w G              (G gathered with the deposit's weights)
+//   Ibar_{k+1} = g_{k+1} + Ibar_{k+2} a_{k+1}
+//   dL/dj     += w * Ibar_{k+1} E_k ds            (scattered with the same weights)
+//   dL/dkappa[nearest voxel] += -ds (Ibar_{k+1} I_k a_k + sum_{k'>k} Ibar_{k'+1} j_{k'} E_{k'} ds)
+// The reverse sweep needs I_k, E_k, j_k and a_k again. Instead of storing trajectories, the
+// forward sweep keeps (I, E) at the start of every kSeg-substep segment; the reverse sweep
+// re-marches one segment forward in registers from its checkpoint, then runs the adjoint
+// through it. Per-sample contributions go to workspace rows, which the tile kernel
+// deposits (trilinear for dL/dj, nearest voxel for dL/dkappa) exactly like the forward field.
+#include "common.h"
+#include "device_common.h"
+
+namespace rtmi {
+namespace {
+
+typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
+
+struct SampleAD {
+  float j;      // trilinear j
+  float kap;    // nearest kappa
+  float g;      // c * trilinear G
+  int cid;      // box corner the sample has collapsed onto, or -1
+};
+
+__device__ __forceinline__ SampleAD adjoint_sample(const AdjointArgs& a, float sx, float sy,
+                                                   float sz, float4 d, int k, float wray) {
+  const int nx = a.nx, ny = a.ny, nz = a.nz, nyz = ny * nz;
+  const float dist = sample_distance(k, a.ds);
+  const float x = sample_axis(sx, dist, d.x);
+  const float y = sample_axis(sy, dist, d.y);
+  const float z = sample_axis(sz, dist, d.z);
+  const Axis X = axis_stencil(x, nx);
+  const Axis Y = axis_stencil(y, ny);
+  const Axis Z = axis_stencil(z, nz);
+  const int ox[2] = {X.lo * nyz, X.hi * nyz};
+  const int oy[2] = {Y.lo * nz, Y.hi * nz};
+  const int oz[2] = {Z.lo, Z.hi};
+  const float wx[2] = {X.w0, X.w1};
+  const float wy[2] = {Y.w0, Y.w1};
+  const float wz[2] = {Z.w0, Z.w1};
+  const bool zsame = Z.lo == Z.hi;
+  const int nsel = (X.nearest == X.hi ? 4 : 0) | (Y.nearest == Y.hi ? 2 : 0);
+  const bool zsel = Z.nearest == Z.hi && !zsame;
+  SampleAD r;
+  r.j = 0.0f;
+  r.kap = 0.0f;
+  float gsum = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int col = ox[q >> 1] + oy[q & 1];
+    const f4a8 v = *reinterpret_cast<const f4a8*>(a.med + col + oz[0]);
+    const float w01 = wx[q >> 1] * wy[q & 1];
+    const float j0 = v.x, j1 = zsame ? v.x : v.z;
+    r.j += w01 * wz[0] * j0 + w01 * wz[1] * j1;
+    if ((q << 1) == nsel) r.kap = zsel ? v.w : v.y;
+    gsum += w01 * wz[0] * a.grad[col + oz[0]] + w01 * wz[1] * a.grad[col + oz[1]];
+  }
+  r.g = wray * gsum;
+  const bool out3 = axis_clamped(x, nx) && axis_clamped(y, ny) && axis_clamped(z, nz);
+  r.cid = out3 ? ((x >= 0.0f ? 4 : 0) | (y >= 0.0f ? 2 : 0) | (z >= 0.0f ? 1 : 0)) : -1;
+  return r;
+}
+
+__global__ void __launch_bounds__(kBlock) adjoint_record_kernel(const AdjointArgs a) {
+  __shared__ float ctail[2][8];
+  const int tid = static_cast<int>(threadIdx.x);
+  if (tid < 16) ctail[tid / 8][tid % 8] = 0.0f;
+  __syncthreads();
+
+  const int nblk = a.blk_begin[a.n_src];
+  const int per_xcd = (nblk + kXcds - 1) / kXcds;
+  const int blk = (static_cast<int>(blockIdx.x) % kXcds) * per_xcd + static_cast<int>(blockIdx.x) / kXcds;
+  int s = 0;
+  while (s + 1 < a.n_src && blk >= a.blk_begin[s + 1]) ++s;
+  const int ray = (blk - a.blk_begin[s]) * kBlock + tid;
+  if (blk < nblk && ray < a.nrays[s]) {
+    const float4 d = a.dirs[s][ray];
+    const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
+    const float wray = a.wray[s];
+    const int nsub = a.nsub[s];
+    const float ds = a.ds;
+    float* vj = a.Vj + a.vbase[s] + static_cast<long long>(ray) * a.vstride[s];
+    float* vk = a.Vk + a.vbase[s] + static_cast<long long>(ray) * a.vstride[s];
+    float2* ck = a.ckpt + a.cbase[s] + static_cast<long long>(ray) * a.cstride[s];
+    const int nseg = (nsub + kSeg - 1) / kSeg;
+
+    // forward sweep: checkpoints only
+    float I = 0.0f, E = 1.0f;
+    for (int seg = 0; seg < nseg; ++seg) {
+      ck[seg] = make_float2(I, E);
+#pragma unroll
+      for (int t = 0; t < kSeg; ++t) {
+        const int k = seg * kSeg + t;
+        if (k < nsub) {
+          const SampleAD q = adjoint_sample(a, sx, sy, sz, d, k, wray);
+          const float att = expf(-q.kap * ds);
+          I = I * att + q.j * E * ds;
+          E *= att;
+        }
+      }
+    }
+
+    // reverse sweep, one recomputed segment at a time
+    float ibar_next = 0.0f, a_next = 0.0f, suffix = 0.0f;
+    float tail_j = 0.0f, tail_k = 0.0f;
+    int corner = -1;
+    for (int seg = nseg - 1; seg >= 0; --seg) {
+      const float2 c0 = ck[seg];
+      float Ir = c0.x, Er = c0.y;
+      float jk[kSeg], ak[kSeg], Ik[kSeg], Ek[kSeg], gk[kSeg];
+      int cid[kSeg];
+#pragma unroll
+      for (int t = 0; t < kSeg; ++t) {
+        const int k = min(seg * kSeg + t, nsub - 1);
+        const SampleAD q = adjoint_sample(a, sx, sy, sz, d, k, wray);
+        const float att = expf(-q.kap * ds);
+        jk[t] = q.j;
+        ak[t] = att;
+        gk[t] = q.g;
+        cid[t] = q.cid;
+        Ik[t] = Ir;
+        Ek[t] = Er;
+        Ir = Ir * att + q.j * Er * ds;
+        Er *= att;
+      }
+      float outj[kSeg], outk[kSeg];
+#pragma unroll
+      for (int t = kSeg - 1; t >= 0; --t) {
+        outj[t] = 0.0f;
+        outk[t] = 0.0f;
+        if (seg * kSeg + t < nsub) {
+          const float ibar = gk[t] + ibar_next * a_next;
+          float vjv = ibar * Ek[t] * ds;
+          float vkv = -ds * (ibar * Ik[t] * ak[t] + suffix);
+          suffix += ibar * jk[t] * Ek[t] * ds;
+          ibar_next = ibar;
+          a_next = ak[t];
+          if (cid[t] >= 0) {
+            if (cid[t] != corner) {
+              if (corner >= 0) {
+                atomicAdd(&ctail[0][corner], tail_j);
+                atomicAdd(&ctail[1][corner], tail_k);
+              }
+              tail_j = 0.0f;
+              tail_k = 0.0f;
+              corner = cid[t];
+            }
+            tail_j += vjv;
+            tail_k += vkv;
+            vjv = 0.0f;
+            vkv = 0.0f;
+          }
+          outj[t] = vjv;
+          outk[t] = vkv;
+        }
+      }
+      *reinterpret_cast<float4*>(vj + seg * kSeg) = make_float4(outj[0], outj[1], outj[2], outj[3]);
+      *reinterpret_cast<float4*>(vk + seg * kSeg) = make_float4(outk[0], outk[1], outk[2], outk[3]);
+    }
+    if (corner >= 0) {
+      atomicAdd(&ctail[0][corner], tail_j);
+      atomicAdd(&ctail[1][corner], tail_k);
+    }
+  }
+  __syncthreads();
+  if (tid < 16) {
+    const float v = ctail[tid / 8][tid % 8];
+    if (v != 0.0f) unsafeAtomicAdd((tid < 8 ? a.corner_j : a.corner_k) + (tid % 8), v);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_adjoint_record(const AdjointArgs& a, int blocks, hipStream_t s) {
+  const dim3 grid((blocks + kXcds - 1) / kXcds * kXcds), block(kBlock);
+  hipLaunchKernelGGL(adjoint_record_kernel, grid, block, 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace rtmi

@@ -1,6 +1,9 @@
-// Host layer of librtmi: argument validation, substep count, direction tables, launches.
+// Host layer of librtmi: argument validation, substep count, direction tables, workspace,
+// and the launch sequences of the two execution paths.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -17,6 +20,9 @@ namespace {
 using rtmi::kBlock;
 using rtmi::kMaxBinsPerLaunch;
 using rtmi::kMaxSrcPerLaunch;
+using rtmi::kPatch;
+using rtmi::kRowAlign;
+using rtmi::kTile;
 
 constexpr int64_t kMaxCount = int64_t(1) << 24;  // num_rays and N_s limit (k is exact in binary32)
 constexpr double kFourPi = 4.0 * 3.14159265358979323846;
@@ -80,21 +86,99 @@ void fibonacci_host(int32_t n, std::vector<float>& xyz) {
   }
 }
 
-// Device table: float4 (x, y, z, bits of the lattice index) per lane.
-std::vector<float4> lane_table(const std::vector<float>& xyz) {
+// Distance along a Hilbert curve through a 2^k x 2^k grid (standard bit-twiddling form).
+uint32_t hilbert_index(uint32_t side, uint32_t x, uint32_t y) {
+  uint32_t d = 0;
+  for (uint32_t s = side / 2; s > 0; s /= 2) {
+    const uint32_t rx = (x & s) ? 1u : 0u, ry = (y & s) ? 1u : 0u;
+    d += s * s * ((3u * rx) ^ ry);
+    if (ry == 0) {
+      if (rx == 1) {
+        x = s - 1 - x;
+        y = s - 1 - y;
+      }
+      std::swap(x, y);
+    }
+  }
+  return d;
+}
+
+// Lane order of the rays: sorted along a Hilbert curve drawn on the octahedral map of
+// the sphere, so that each run of 64 lanes (one wavefront) holds a compact patch of
+// directions. The sum over rays does not depend on this order.
+std::vector<size_t> coherent_order(const std::vector<float>& xyz) {
   const size_t n = xyz.size() / 3;
-  std::vector<float4> t(n);
+  std::vector<uint32_t> key(n);
   for (size_t i = 0; i < n; ++i) {
+    const double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+    const double l1 = std::fabs(x) + std::fabs(y) + std::fabs(z);
+    double u = l1 > 0 ? x / l1 : 0.0, v = l1 > 0 ? y / l1 : 0.0;
+    if (z < 0) {
+      const double uu = (1.0 - std::fabs(v)) * (u >= 0 ? 1.0 : -1.0);
+      const double vv = (1.0 - std::fabs(u)) * (v >= 0 ? 1.0 : -1.0);
+      u = uu;
+      v = vv;
+    }
+    const uint32_t qx = std::min<uint32_t>(1023u, static_cast<uint32_t>((u + 1.0) * 512.0));
+    const uint32_t qy = std::min<uint32_t>(1023u, static_cast<uint32_t>((v + 1.0) * 512.0));
+    key[i] = hilbert_index(1024u, qx, qy);
+  }
+  std::vector<size_t> ord(n);
+  for (size_t i = 0; i < n; ++i) ord[i] = i;
+  std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) { return key[a] < key[b]; });
+  return ord;
+}
+
+// Device-side direction table: float4 (x, y, z, bits of the lattice index) per lane in
+// coherent order, followed by per-patch direction bounds (8 floats per 64 lanes).
+struct HostTable {
+  std::vector<float4> dirs;
+  std::vector<float> bounds;
+};
+
+HostTable build_table(const std::vector<float>& xyz) {
+  const size_t n = xyz.size() / 3;
+  const std::vector<size_t> ord = coherent_order(xyz);
+  HostTable t;
+  t.dirs.resize(n);
+  for (size_t lane = 0; lane < n; ++lane) {
+    const size_t i = ord[lane];
     int32_t idx = static_cast<int32_t>(i);
     float w;
     std::memcpy(&w, &idx, sizeof w);
-    t[i] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], w);
+    t.dirs[lane] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], w);
+  }
+  const size_t np = (n + kPatch - 1) / kPatch;
+  t.bounds.assign(np * 8, 0.0f);
+  for (size_t p = 0; p < np; ++p) {
+    float lo[3] = {2.f, 2.f, 2.f}, hi[3] = {-2.f, -2.f, -2.f};
+    for (size_t lane = p * kPatch; lane < std::min(n, (p + 1) * kPatch); ++lane) {
+      const float c[3] = {t.dirs[lane].x, t.dirs[lane].y, t.dirs[lane].z};
+      for (int a = 0; a < 3; ++a) {
+        lo[a] = std::min(lo[a], c[a]);
+        hi[a] = std::max(hi[a], c[a]);
+      }
+    }
+    for (int a = 0; a < 3; ++a) {
+      t.bounds[p * 8 + a] = lo[a];
+      t.bounds[p * 8 + 3 + a] = hi[a];
+    }
   }
   return t;
 }
 
+struct DevTable {
+  float4* dirs = nullptr;
+  float* bounds = nullptr;
+};
+
+size_t table_bytes(const HostTable& t) {
+  return t.dirs.size() * sizeof(float4) + t.bounds.size() * sizeof(float);
+}
+
 std::mutex g_mu;
-std::map<std::pair<int, int32_t>, float4*> g_dirs;  // (device, N) -> table, kept for the process
+std::map<std::pair<int, int32_t>, DevTable> g_dirs;  // (device, N) -> table, kept for the process
+std::map<int, hipMemPool_t> g_pools;                  // device -> workspace pool
 
 int32_t current_device(int* dev) {
   const hipError_t e = hipGetDevice(dev);
@@ -102,7 +186,12 @@ int32_t current_device(int* dev) {
   return RTMI_OK;
 }
 
-int32_t get_dirs(int32_t n, hipStream_t stream, const float4** out) {
+bool capturing(hipStream_t s) {
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  return s != nullptr && hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
+}
+
+int32_t get_dirs(int32_t n, hipStream_t stream, DevTable* out) {
   int dev = 0;
   if (int32_t st = current_device(&dev)) return st;
   std::lock_guard<std::mutex> lock(g_mu);
@@ -111,36 +200,83 @@ int32_t get_dirs(int32_t n, hipStream_t stream, const float4** out) {
     *out = it->second;
     return RTMI_OK;
   }
-  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-  if (stream != nullptr && hipStreamIsCapturing(stream, &cap) == hipSuccess &&
-      cap != hipStreamCaptureStatusNone)
+  if (capturing(stream))
     return fail(RTMI_ERR_UNSUPPORTED,
                 "direction table for %d rays not prepared; call rtmi_prepare before capture", n);
   std::vector<float> xyz;
   fibonacci_host(n, xyz);
-  const std::vector<float4> t = lane_table(xyz);
-  float4* d = nullptr;
-  hipError_t e = hipMalloc(&d, t.size() * sizeof(float4));
+  const HostTable t = build_table(xyz);
+  char* d = nullptr;
+  hipError_t e = hipMalloc(&d, table_bytes(t));
   if (e != hipSuccess) return hip_fail(e, "hipMalloc(direction table)");
-  e = hipMemcpy(d, t.data(), t.size() * sizeof(float4), hipMemcpyHostToDevice);
+  const size_t db = t.dirs.size() * sizeof(float4);
+  e = hipMemcpy(d, t.dirs.data(), db, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(d + db, t.bounds.data(), t.bounds.size() * sizeof(float), hipMemcpyHostToDevice);
   if (e != hipSuccess) {
     (void)hipFree(d);
     return hip_fail(e, "hipMemcpy(direction table)");
   }
-  g_dirs[{dev, n}] = d;
-  *out = d;
+  DevTable dt;
+  dt.dirs = reinterpret_cast<float4*>(d);
+  dt.bounds = reinterpret_cast<float*>(d + db);
+  g_dirs[{dev, n}] = dt;
+  *out = dt;
   return RTMI_OK;
 }
 
-// ---- measurement hooks: event pairs around march launches ----
+// Workspace pool of the current device: a private stream-ordered pool that keeps what it
+// has allocated, so that repeated calls reuse memory instead of going back to the system.
+int32_t get_pool(hipMemPool_t* pool) {
+  int dev = 0;
+  if (int32_t st = current_device(&dev)) return st;
+  std::lock_guard<std::mutex> lock(g_mu);
+  auto it = g_pools.find(dev);
+  if (it != g_pools.end()) {
+    *pool = it->second;
+    return RTMI_OK;
+  }
+  hipMemPoolProps props;
+  std::memset(&props, 0, sizeof props);
+  props.allocType = hipMemAllocationTypePinned;
+  props.handleTypes = hipMemHandleTypeNone;
+  props.location.type = hipMemLocationTypeDevice;
+  props.location.id = dev;
+  hipMemPool_t p = nullptr;
+  hipError_t e = hipMemPoolCreate(&p, &props);
+  if (e != hipSuccess) return hip_fail(e, "hipMemPoolCreate");
+  uint64_t keep = UINT64_MAX;
+  e = hipMemPoolSetAttribute(p, hipMemPoolAttrReleaseThreshold, &keep);
+  if (e != hipSuccess) return hip_fail(e, "hipMemPoolSetAttribute");
+  g_pools[dev] = p;
+  *pool = p;
+  return RTMI_OK;
+}
+
+int32_t pool_alloc(void** ptr, size_t bytes, hipStream_t s) {
+  hipMemPool_t pool = nullptr;
+  if (int32_t st = get_pool(&pool)) return st;
+  const hipError_t e = hipMallocFromPoolAsync(ptr, std::max<size_t>(bytes, 256), pool, s);
+  if (e != hipSuccess) return hip_fail(e, "workspace allocation");
+  return RTMI_OK;
+}
+
+// ---- measurement hooks: event pairs around kernel launches, per kernel kind ----
 std::mutex g_tmu;
 bool g_timing = false;
-std::vector<std::pair<hipEvent_t, hipEvent_t>> g_pending;  // recorded, not yet read
-std::vector<std::pair<hipEvent_t, hipEvent_t>> g_free;
+using EventPair = std::pair<hipEvent_t, hipEvent_t>;
+std::vector<EventPair> g_pending[3];  // recorded, not yet read
+std::vector<EventPair> g_free;
 
-hipError_t timed_launch_begin(hipStream_t s, std::pair<hipEvent_t, hipEvent_t>* ev, bool* on) {
+struct TimedLaunch {
+  EventPair ev{};
+  bool on = false;
+  int kind = 0;
+};
+
+hipError_t timed_begin(hipStream_t s, int kind, TimedLaunch* t) {
   std::lock_guard<std::mutex> lock(g_tmu);
-  *on = g_timing;
+  t->on = g_timing;
+  t->kind = kind;
   if (!g_timing) return hipSuccess;
   if (g_free.empty()) {
     hipEvent_t a, b;
@@ -149,16 +285,16 @@ hipError_t timed_launch_begin(hipStream_t s, std::pair<hipEvent_t, hipEvent_t>* 
     if ((e = hipEventCreate(&b)) != hipSuccess) return e;
     g_free.push_back({a, b});
   }
-  *ev = g_free.back();
+  t->ev = g_free.back();
   g_free.pop_back();
-  return hipEventRecord(ev->first, s);
+  return hipEventRecord(t->ev.first, s);
 }
 
-hipError_t timed_launch_end(hipStream_t s, const std::pair<hipEvent_t, hipEvent_t>& ev, bool on) {
-  if (!on) return hipSuccess;
+hipError_t timed_end(hipStream_t s, const TimedLaunch& t) {
+  if (!t.on) return hipSuccess;
   std::lock_guard<std::mutex> lock(g_tmu);
-  const hipError_t e = hipEventRecord(ev.second, s);
-  g_pending.push_back(ev);
+  const hipError_t e = hipEventRecord(t.ev.second, s);
+  g_pending[t.kind].push_back(t.ev);
   return e;
 }
 
@@ -180,86 +316,195 @@ struct Problem {
   hipStream_t stream;
 };
 
-int32_t run(const Problem& p) {
-  // ---- validation: nothing is enqueued before all of it passes ----
+// Everything a validated call needs to enqueue work.
+struct Plan {
+  bool det = false;
+  bool tiled = true;
+  bool explicit_dirs = false;
+  std::vector<int32_t> nsub;
+  std::vector<DevTable> tables;
+  double bound_per_unit_j = 0.0;
+  int64_t cells = 0;
+};
+
+int32_t validate(const Problem& p, Plan* plan) {
   if (!p.j || !p.kap || !p.out || !p.src || !p.nrays)
     return fail(RTMI_ERR_INVALID_ARG, "null map, field, source_pos or num_rays pointer");
   if (int32_t st = check_shape(p.nx, p.ny, p.nz)) return st;
   if (int32_t st = check_scalars(p.ds, p.c, p.dt)) return st;
   if (p.n_src < 1) return fail(RTMI_ERR_INVALID_ARG, "n_src must be >= 1 (got %d)", p.n_src);
   if (p.n_bins < 1) return fail(RTMI_ERR_INVALID_ARG, "n_bins must be >= 1 (got %d)", p.n_bins);
-  if (p.j_stride < 0 || p.k_stride < 0)
-    return fail(RTMI_ERR_INVALID_ARG, "bin strides must be >= 0");
-  const int64_t cells = int64_t(p.nx) * p.ny * p.nz;
-  if (p.n_bins > 1 && ((p.j_stride != 0 && p.j_stride < cells) || (p.k_stride != 0 && p.k_stride < cells)))
+  if (p.j_stride < 0 || p.k_stride < 0) return fail(RTMI_ERR_INVALID_ARG, "bin strides must be >= 0");
+  plan->cells = int64_t(p.nx) * p.ny * p.nz;
+  if (p.n_bins > 1 && ((p.j_stride != 0 && p.j_stride < plan->cells) ||
+                       (p.k_stride != 0 && p.k_stride < plan->cells)))
     return fail(RTMI_ERR_INVALID_ARG, "a non-zero bin stride must be >= nx*ny*nz");
   if (p.kscale)
     for (int32_t b = 0; b < p.n_bins; ++b)
       if (!std::isfinite(p.kscale[b])) return fail(RTMI_ERR_NONFINITE, "kappa_scale[%d] is not finite", b);
-  const bool det = p.opts && p.opts->accum_mode == RTMI_ACCUM_DETERMINISTIC;
-  if (p.opts && p.opts->accum_mode != RTMI_ACCUM_ATOMIC && !det)
-    return fail(RTMI_ERR_INVALID_ARG, "unknown accum_mode %d", p.opts->accum_mode);
-  const bool explicit_dirs = p.opts && p.opts->directions;
-  std::vector<int32_t> nsub(p.n_src);
-  double bound_per_unit_j = 0.0;  // worst-case |J| per voxel per unit max|j| (deterministic mode)
+  if (p.opts) {
+    if (p.opts->accum_mode != RTMI_ACCUM_ATOMIC && p.opts->accum_mode != RTMI_ACCUM_DETERMINISTIC)
+      return fail(RTMI_ERR_INVALID_ARG, "unknown accum_mode %d", p.opts->accum_mode);
+    if (p.opts->path != RTMI_PATH_TILED && p.opts->path != RTMI_PATH_DIRECT)
+      return fail(RTMI_ERR_INVALID_ARG, "unknown path %d", p.opts->path);
+    plan->det = p.opts->accum_mode == RTMI_ACCUM_DETERMINISTIC;
+    plan->tiled = p.opts->path == RTMI_PATH_TILED;
+    plan->explicit_dirs = p.opts->directions != nullptr;
+    if (plan->explicit_dirs && p.opts->ray_weight > 0.0f && !std::isfinite(p.opts->ray_weight))
+      return fail(RTMI_ERR_NONFINITE, "ray_weight is not finite");
+  }
+  plan->nsub.resize(p.n_src);
   for (int32_t s = 0; s < p.n_src; ++s) {
     for (int a = 0; a < 3; ++a)
       if (!std::isfinite(p.src[3 * s + a])) return fail(RTMI_ERR_NONFINITE, "source_pos[%d] is not finite", s);
     if (p.nrays[s] < 1 || p.nrays[s] > kMaxCount)
       return fail(p.nrays[s] < 1 ? RTMI_ERR_INVALID_ARG : RTMI_ERR_RANGE,
                   "num_rays[%d] = %d must be in [1, 2^24]", s, p.nrays[s]);
-    if (explicit_dirs && p.nrays[s] != p.nrays[0])
+    if (plan->explicit_dirs && p.nrays[s] != p.nrays[0])
       return fail(RTMI_ERR_INVALID_ARG, "explicit directions need one num_rays for all sources");
     const int64_t n = substeps(p.ds, p.c, p.dt, p.caps ? p.caps[s] : 0);
     if (n < 0) return fail(RTMI_ERR_RANGE, "N_s = ceil(c dt / ds) exceeds 2^24");
-    nsub[s] = static_cast<int32_t>(n);
+    plan->nsub[s] = static_cast<int32_t>(n);
     // I <= N_s ds max|j| (exp factors <= 1 for kappa >= 0); each ray deposits at most
-    // N_s times into one voxel with weight <= 1, times 4 pi / N_Omega, summed over N_Omega rays.
-    bound_per_unit_j += kFourPi * double(n) * double(n) * double(p.ds);
+    // N_s times into one voxel with weight <= 1, times 4 pi / N_Omega, over N_Omega rays.
+    plan->bound_per_unit_j += kFourPi * double(n) * double(n) * double(p.ds);
   }
-  if (explicit_dirs && p.opts->ray_weight > 0.0f && !std::isfinite(p.opts->ray_weight))
-    return fail(RTMI_ERR_NONFINITE, "ray_weight is not finite");
-
-  // ---- directions ----
-  std::vector<const float4*> dirs(p.n_src);
-  float4* explicit_table = nullptr;
-  if (explicit_dirs) {
-    const int32_t n = p.nrays[0];
-    for (int64_t i = 0; i < int64_t(n) * 3; ++i)
+  if (plan->explicit_dirs)
+    for (int64_t i = 0; i < int64_t(p.nrays[0]) * 3; ++i)
       if (!std::isfinite(p.opts->directions[i])) return fail(RTMI_ERR_NONFINITE, "directions contain NaN/Inf");
-    std::vector<float> xyz(p.opts->directions, p.opts->directions + size_t(n) * 3);
-    const std::vector<float4> t = lane_table(xyz);
-    hipError_t e = hipMallocAsync(reinterpret_cast<void**>(&explicit_table), t.size() * sizeof(float4), p.stream);
-    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(directions)");
-    e = hipMemcpyAsync(explicit_table, t.data(), t.size() * sizeof(float4), hipMemcpyHostToDevice, p.stream);
-    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(directions)");
-    for (int32_t s = 0; s < p.n_src; ++s) dirs[s] = explicit_table;
-  } else {
-    for (int32_t s = 0; s < p.n_src; ++s)
-      if (int32_t st = get_dirs(p.nrays[s], p.stream, &dirs[s])) return st;
-  }
+  return RTMI_OK;
+}
 
-  // ---- output: zero, then accumulate ----
-  const int64_t total = cells * p.n_bins;
-  unsigned long long* acc = nullptr;
-  double* det_scale = nullptr;
-  hipError_t e;
-  if (det) {
-    e = hipMallocAsync(reinterpret_cast<void**>(&acc), size_t(total) * 8 + 16, p.stream);
-    if (e != hipSuccess) return hip_fail(e, "hipMallocAsync(fixed-point field)");
-    det_scale = reinterpret_cast<double*>(acc + total);
-    if ((e = rtmi::launch_fill_zero_u64(acc, total, p.stream)) != hipSuccess) return hip_fail(e, "fill");
-    const int64_t j_count = p.j_stride ? p.j_stride * (p.n_bins - 1) + cells : cells;
-    if ((e = rtmi::launch_det_scale(p.j, j_count, bound_per_unit_j, det_scale, p.stream)) != hipSuccess)
-      return hip_fail(e, "det_scale");
-  } else {
-    if ((e = rtmi::launch_fill_zero(p.out, total, p.stream)) != hipSuccess) return hip_fail(e, "fill");
+float ray_weight(const Problem& p, const Plan& plan, int32_t s) {
+  const double w = (plan.explicit_dirs && p.opts->ray_weight > 0.0f) ? double(p.opts->ray_weight)
+                                                                     : kFourPi / p.nrays[s];
+  return static_cast<float>(w);
+}
+
+int64_t row_stride(int32_t nsub) { return (int64_t(nsub) + kRowAlign - 1) / kRowAlign * kRowAlign; }
+
+// ---- tiled path: record + tile per (bin chunk, source chunk) ----
+int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
+                  const double* det_scale) {
+  const hipStream_t st = p.stream;
+  // workspace: the largest (bin chunk x source chunk) row set, plus the corner sums
+  int64_t v_elems_max = 0;
+  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
+    int64_t e = 0;
+    for (int32_t s = s0; s < std::min(p.n_src, s0 + kMaxSrcPerLaunch); ++s)
+      if (plan.nsub[s] > 0) e += int64_t(p.nrays[s]) * row_stride(plan.nsub[s]);
+    v_elems_max = std::max(v_elems_max, e);
   }
+  const int32_t nb_max = std::min(kMaxBinsPerLaunch, p.n_bins);
+  const size_t corner_bytes = 256;  // [4][8] floats, then [4][8] u64 (rounded up)
+  const size_t v_bytes = size_t(v_elems_max) * nb_max * sizeof(float);
+  // a shared j and a shared (scaled) kappa are gathered from one interleaved copy
+  const bool interleaved = p.j_stride == 0 && p.k_stride == 0;
+  const size_t med_bytes = interleaved ? (size_t(plan.cells) + 1) * sizeof(float2) : 0;
+  const size_t med_pad = (med_bytes + 255) / 256 * 256;
+  char* ws = nullptr;
+  if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&ws), corner_bytes * 2 + med_pad + v_bytes, st))
+    return rc;
+  float* corner = reinterpret_cast<float*>(ws);
+  unsigned long long* corner_q = reinterpret_cast<unsigned long long*>(ws + corner_bytes);
+  float2* med = interleaved ? reinterpret_cast<float2*>(ws + 2 * corner_bytes) : nullptr;
+  float* V = reinterpret_cast<float*>(ws + 2 * corner_bytes + med_pad);
+  hipError_t e;
+  if (interleaved && (e = rtmi::launch_interleave(p.j, p.kap, med, plan.cells, st)) != hipSuccess)
+    return hip_fail(e, "interleave");
+  const int tiles_x = (p.nx + kTile - 1) / kTile, tiles_y = (p.ny + kTile - 1) / kTile,
+            tiles_z = (p.nz + kTile - 1) / kTile;
+  const int tiles = tiles_x * tiles_y * tiles_z;
 
   for (int32_t b0 = 0; b0 < p.n_bins; b0 += kMaxBinsPerLaunch) {
-    const int32_t nb = std::min<int32_t>(kMaxBinsPerLaunch, p.n_bins - b0);
+    const int32_t nb = std::min(kMaxBinsPerLaunch, p.n_bins - b0);
     for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
-      const int32_t ns = std::min<int32_t>(kMaxSrcPerLaunch, p.n_src - s0);
+      const int32_t ns = std::min(kMaxSrcPerLaunch, p.n_src - s0);
+      rtmi::RecordArgs r;
+      rtmi::TileArgs t;
+      std::memset(&r, 0, sizeof r);
+      std::memset(&t, 0, sizeof t);
+      int64_t v_elems = 0;
+      int blocks = 0, patches = 0;
+      for (int32_t i = 0; i < ns; ++i) {
+        const int32_t s = s0 + i;
+        const int32_t nr = plan.nsub[s] > 0 ? p.nrays[s] : 0;
+        r.blk_begin[i] = blocks;
+        t.pbegin[i] = patches;
+        r.sx[i] = t.sx[i] = p.src[3 * s];
+        r.sy[i] = t.sy[i] = p.src[3 * s + 1];
+        r.sz[i] = t.sz[i] = p.src[3 * s + 2];
+        r.wray[i] = ray_weight(p, plan, s);
+        r.nrays[i] = t.nrays[i] = nr;
+        r.nsub[i] = t.nsub[i] = plan.nsub[s];
+        r.vstride[i] = t.vstride[i] = static_cast<int>(row_stride(plan.nsub[s]));
+        r.vbase[i] = t.vbase[i] = v_elems;
+        r.dirs[i] = t.dirs[i] = plan.tables[s].dirs;
+        t.pbounds[i] = plan.tables[s].bounds;
+        v_elems += int64_t(nr) * row_stride(plan.nsub[s]);
+        blocks += (nr + kBlock - 1) / kBlock;
+        patches += (nr + kPatch - 1) / kPatch;
+      }
+      r.blk_begin[ns] = blocks;
+      t.pbegin[ns] = patches;
+      r.med = med;
+      r.j = p.j + b0 * p.j_stride;
+      r.j_stride = p.j_stride;
+      r.kap = p.kap + b0 * p.k_stride;
+      r.k_stride = p.k_stride;
+      for (int32_t b = 0; b < nb; ++b) r.kscale[b] = p.kscale ? p.kscale[b0 + b] : 1.0f;
+      r.V = V;
+      t.V = V;
+      r.v_bin_stride = t.v_bin_stride = v_elems;
+      r.corner = corner;
+      r.corner_q = corner_q;
+      t.corner = corner;
+      t.corner_q = corner_q;
+      r.det_scale = t.det_scale = det_scale;
+      r.nx = t.nx = p.nx;
+      r.ny = t.ny = p.ny;
+      r.nz = t.nz = p.nz;
+      r.ds = t.ds = p.ds;
+      r.n_src = t.n_src = ns;
+      t.out = p.out + b0 * plan.cells;
+      t.out_q = out_q ? out_q + b0 * plan.cells : nullptr;
+      t.out_stride = plan.cells;
+      t.tiles_x = tiles_x;
+      t.tiles_y = tiles_y;
+      t.tiles_z = tiles_z;
+      t.accumulate = s0 > 0 ? 1 : 0;
+
+      if ((e = rtmi::launch_fill_zero(corner, 2 * corner_bytes / sizeof(float), st)) != hipSuccess)
+        return hip_fail(e, "fill");
+      if (blocks > 0) {
+        TimedLaunch tl;
+        if ((e = timed_begin(st, RTMI_KERNEL_RECORD, &tl)) != hipSuccess) return hip_fail(e, "timing");
+        if ((e = rtmi::launch_record(r, nb, p.j_stride == 0, plan.det, blocks, st)) != hipSuccess)
+          return hip_fail(e, "record launch");
+        if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
+      }
+      TimedLaunch tl;
+      if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl)) != hipSuccess) return hip_fail(e, "timing");
+      if ((e = rtmi::launch_tile(t, nb, plan.det, false, tiles, st)) != hipSuccess)
+        return hip_fail(e, "tile launch");
+      if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
+    }
+  }
+  if ((e = hipFreeAsync(ws, st)) != hipSuccess) return hip_fail(e, "workspace release");
+  return RTMI_OK;
+}
+
+// ---- direct path: one kernel, register windows and global atomics ----
+int32_t run_direct(const Problem& p, const Plan& plan, unsigned long long* out_q,
+                   const double* det_scale) {
+  const hipStream_t st = p.stream;
+  hipError_t e;
+  const int64_t total = plan.cells * p.n_bins;
+  if (!plan.det && (e = rtmi::launch_fill_zero(p.out, total, st)) != hipSuccess) return hip_fail(e, "fill");
+  for (int32_t b0 = 0; b0 < p.n_bins; b0 += kMaxBinsPerLaunch) {
+    const int32_t nb = std::min(kMaxBinsPerLaunch, p.n_bins - b0);
+    for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
+      const int32_t ns = std::min(kMaxSrcPerLaunch, p.n_src - s0);
       rtmi::MarchArgs a;
       std::memset(&a, 0, sizeof a);
       a.j = p.j + b0 * p.j_stride;
@@ -267,10 +512,10 @@ int32_t run(const Problem& p) {
       a.kap = p.kap + b0 * p.k_stride;
       a.k_stride = p.k_stride;
       for (int32_t b = 0; b < nb; ++b) a.kscale[b] = p.kscale ? p.kscale[b0 + b] : 1.0f;
-      a.out = p.out + b0 * cells;
-      a.acc = acc ? acc + b0 * cells : nullptr;
+      a.out = p.out + b0 * plan.cells;
+      a.acc = out_q ? out_q + b0 * plan.cells : nullptr;
       a.det_scale = det_scale;
-      a.out_stride = cells;
+      a.out_stride = plan.cells;
       a.nx = p.nx;
       a.ny = p.ny;
       a.nz = p.nz;
@@ -283,32 +528,183 @@ int32_t run(const Problem& p) {
         a.sx[i] = p.src[3 * s];
         a.sy[i] = p.src[3 * s + 1];
         a.sz[i] = p.src[3 * s + 2];
-        const double w = (explicit_dirs && p.opts->ray_weight > 0.0f) ? double(p.opts->ray_weight)
-                                                                       : kFourPi / p.nrays[s];
-        a.wray[i] = static_cast<float>(w);
-        a.nrays[i] = nsub[s] > 0 ? p.nrays[s] : 0;
-        a.nsub[i] = nsub[s];
-        a.dirs[i] = dirs[s];
+        a.wray[i] = ray_weight(p, plan, s);
+        a.nrays[i] = plan.nsub[s] > 0 ? p.nrays[s] : 0;
+        a.nsub[i] = plan.nsub[s];
+        a.dirs[i] = plan.tables[s].dirs;
         blocks += (a.nrays[i] + kBlock - 1) / kBlock;
       }
       a.blk_begin[ns] = blocks;
       if (blocks == 0) continue;
-      std::pair<hipEvent_t, hipEvent_t> ev{};
-      bool timed = false;
-      if ((e = timed_launch_begin(p.stream, &ev, &timed)) != hipSuccess) return hip_fail(e, "timing event");
-      if ((e = rtmi::launch_march(a, nb, p.j_stride == 0, det, blocks, p.stream)) != hipSuccess)
+      TimedLaunch tl;
+      if ((e = timed_begin(st, RTMI_KERNEL_DIRECT, &tl)) != hipSuccess) return hip_fail(e, "timing");
+      if ((e = rtmi::launch_march(a, nb, p.j_stride == 0, plan.det, blocks, st)) != hipSuccess)
         return hip_fail(e, "march launch");
-      if ((e = timed_launch_end(p.stream, ev, timed)) != hipSuccess) return hip_fail(e, "timing event");
+      if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
     }
   }
+  return RTMI_OK;
+}
 
-  if (det) {
-    if ((e = rtmi::launch_det_convert(acc, det_scale, p.out, total, p.stream)) != hipSuccess)
-      return hip_fail(e, "det_convert");
-    if ((e = hipFreeAsync(acc, p.stream)) != hipSuccess) return hip_fail(e, "hipFreeAsync");
+int32_t run(const Problem& p) {
+  Plan plan;
+  if (int32_t st = validate(p, &plan)) return st;
+  const hipStream_t st = p.stream;
+  hipError_t e;
+
+  // directions: cached Fibonacci tables, or this call's explicit table
+  plan.tables.resize(p.n_src);
+  char* explicit_table = nullptr;
+  if (plan.explicit_dirs) {
+    const int32_t n = p.nrays[0];
+    std::vector<float> xyz(p.opts->directions, p.opts->directions + size_t(n) * 3);
+    const HostTable t = build_table(xyz);
+    if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&explicit_table), table_bytes(t), st)) return rc;
+    const size_t db = t.dirs.size() * sizeof(float4);
+    e = hipMemcpyAsync(explicit_table, t.dirs.data(), db, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(explicit_table + db, t.bounds.data(), t.bounds.size() * sizeof(float),
+                         hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(directions)");
+    DevTable dt;
+    dt.dirs = reinterpret_cast<float4*>(explicit_table);
+    dt.bounds = reinterpret_cast<float*>(explicit_table + db);
+    for (int32_t s = 0; s < p.n_src; ++s) plan.tables[s] = dt;
+  } else {
+    for (int32_t s = 0; s < p.n_src; ++s)
+      if (int32_t rc = get_dirs(p.nrays[s], st, &plan.tables[s])) return rc;
   }
-  if (explicit_table && (e = hipFreeAsync(explicit_table, p.stream)) != hipSuccess)
-    return hip_fail(e, "hipFreeAsync(directions)");
+
+  // deterministic mode: fixed-point field and its scale
+  const int64_t total = plan.cells * p.n_bins;
+  unsigned long long* out_q = nullptr;
+  double* det_scale = nullptr;
+  if (plan.det) {
+    if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&out_q), size_t(total) * 8 + 16, st)) return rc;
+    det_scale = reinterpret_cast<double*>(out_q + total);
+    if (!plan.tiled && (e = rtmi::launch_fill_zero_u64(out_q, total, st)) != hipSuccess)
+      return hip_fail(e, "fill");
+    const int64_t j_count = p.j_stride ? p.j_stride * (p.n_bins - 1) + plan.cells : plan.cells;
+    if ((e = rtmi::launch_det_scale(p.j, j_count, plan.bound_per_unit_j, det_scale, st)) != hipSuccess)
+      return hip_fail(e, "det_scale");
+  }
+
+  const int32_t rc = plan.tiled ? run_tiled(p, plan, out_q, det_scale) : run_direct(p, plan, out_q, det_scale);
+  if (rc != RTMI_OK) return rc;
+
+  if (plan.det) {
+    if ((e = rtmi::launch_det_convert(out_q, det_scale, p.out, total, st)) != hipSuccess)
+      return hip_fail(e, "det_convert");
+    if ((e = hipFreeAsync(out_q, st)) != hipSuccess) return hip_fail(e, "workspace release");
+  }
+  if (explicit_table && (e = hipFreeAsync(explicit_table, st)) != hipSuccess)
+    return hip_fail(e, "workspace release");
+  g_error.clear();
+  return RTMI_OK;
+}
+
+// ---- adjoint: checkpointed reverse sweep + tile deposits of dL/dj and dL/dkappa ----
+int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_k) {
+  Plan plan;
+  if (int32_t st = validate(p, &plan)) return st;
+  if (!grad || !grad_j || !grad_k) return fail(RTMI_ERR_INVALID_ARG, "null gradient pointer");
+  const hipStream_t st = p.stream;
+  plan.tables.resize(p.n_src);
+  for (int32_t s = 0; s < p.n_src; ++s)
+    if (int32_t rc = get_dirs(p.nrays[s], st, &plan.tables[s])) return rc;
+
+  int64_t v_elems_max = 0, c_elems_max = 0;
+  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
+    int64_t e = 0, c = 0;
+    for (int32_t s = s0; s < std::min(p.n_src, s0 + kMaxSrcPerLaunch); ++s) {
+      if (plan.nsub[s] == 0) continue;
+      e += int64_t(p.nrays[s]) * row_stride(plan.nsub[s]);
+      c += int64_t(p.nrays[s]) * ((plan.nsub[s] + rtmi::kSeg - 1) / rtmi::kSeg);
+    }
+    v_elems_max = std::max(v_elems_max, e);
+    c_elems_max = std::max(c_elems_max, c);
+  }
+  const size_t corner_bytes = 256;
+  const size_t med_bytes = ((size_t(plan.cells) + 1) * sizeof(float2) + 255) / 256 * 256;
+  const size_t v_bytes = (size_t(v_elems_max) * sizeof(float) + 255) / 256 * 256;
+  const size_t c_bytes = size_t(c_elems_max) * sizeof(float2);
+  char* ws = nullptr;
+  if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&ws), corner_bytes + med_bytes + 2 * v_bytes + c_bytes, st))
+    return rc;
+  float* corner = reinterpret_cast<float*>(ws);  // [0..7] for dL/dj, [8..15] for dL/dkappa
+  float2* med = reinterpret_cast<float2*>(ws + corner_bytes);
+  float* Vj = reinterpret_cast<float*>(ws + corner_bytes + med_bytes);
+  float* Vk = reinterpret_cast<float*>(ws + corner_bytes + med_bytes + v_bytes);
+  float2* ckpt = reinterpret_cast<float2*>(ws + corner_bytes + med_bytes + 2 * v_bytes);
+  hipError_t e;
+  if ((e = rtmi::launch_interleave(p.j, p.kap, med, plan.cells, st)) != hipSuccess) return hip_fail(e, "interleave");
+  const int tiles_x = (p.nx + kTile - 1) / kTile, tiles_y = (p.ny + kTile - 1) / kTile,
+            tiles_z = (p.nz + kTile - 1) / kTile;
+  const int tiles = tiles_x * tiles_y * tiles_z;
+
+  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
+    const int32_t ns = std::min(kMaxSrcPerLaunch, p.n_src - s0);
+    rtmi::AdjointArgs r;
+    rtmi::TileArgs t;
+    std::memset(&r, 0, sizeof r);
+    std::memset(&t, 0, sizeof t);
+    int64_t v_elems = 0, c_elems = 0;
+    int blocks = 0, patches = 0;
+    for (int32_t i = 0; i < ns; ++i) {
+      const int32_t s = s0 + i;
+      const int32_t nr = plan.nsub[s] > 0 ? p.nrays[s] : 0;
+      r.blk_begin[i] = blocks;
+      t.pbegin[i] = patches;
+      r.sx[i] = t.sx[i] = p.src[3 * s];
+      r.sy[i] = t.sy[i] = p.src[3 * s + 1];
+      r.sz[i] = t.sz[i] = p.src[3 * s + 2];
+      r.wray[i] = ray_weight(p, plan, s);
+      r.nrays[i] = t.nrays[i] = nr;
+      r.nsub[i] = t.nsub[i] = plan.nsub[s];
+      r.vstride[i] = t.vstride[i] = static_cast<int>(row_stride(plan.nsub[s]));
+      r.vbase[i] = t.vbase[i] = v_elems;
+      r.cstride[i] = (plan.nsub[s] + rtmi::kSeg - 1) / rtmi::kSeg;
+      r.cbase[i] = c_elems;
+      r.dirs[i] = t.dirs[i] = plan.tables[s].dirs;
+      t.pbounds[i] = plan.tables[s].bounds;
+      v_elems += int64_t(nr) * row_stride(plan.nsub[s]);
+      c_elems += int64_t(nr) * r.cstride[i];
+      blocks += (nr + kBlock - 1) / kBlock;
+      patches += (nr + kPatch - 1) / kPatch;
+    }
+    r.blk_begin[ns] = blocks;
+    t.pbegin[ns] = patches;
+    r.med = med;
+    r.grad = grad;
+    r.Vj = Vj;
+    r.Vk = Vk;
+    r.ckpt = ckpt;
+    r.corner_j = corner;
+    r.corner_k = corner + 8;
+    r.nx = t.nx = p.nx;
+    r.ny = t.ny = p.ny;
+    r.nz = t.nz = p.nz;
+    r.ds = t.ds = p.ds;
+    r.n_src = t.n_src = ns;
+    t.v_bin_stride = v_elems;
+    t.out_stride = plan.cells;
+    t.tiles_x = tiles_x;
+    t.tiles_y = tiles_y;
+    t.tiles_z = tiles_z;
+    t.accumulate = s0 > 0 ? 1 : 0;
+    if ((e = rtmi::launch_fill_zero(corner, 64, st)) != hipSuccess) return hip_fail(e, "fill");
+    if (blocks > 0 && (e = rtmi::launch_adjoint_record(r, blocks, st)) != hipSuccess)
+      return hip_fail(e, "adjoint launch");
+    t.V = Vj;
+    t.corner = corner;
+    t.out = grad_j;
+    if ((e = rtmi::launch_tile(t, 1, false, false, tiles, st)) != hipSuccess) return hip_fail(e, "tile launch");
+    t.V = Vk;
+    t.corner = corner + 8;
+    t.out = grad_k;
+    if ((e = rtmi::launch_tile(t, 1, false, true, tiles, st)) != hipSuccess) return hip_fail(e, "tile launch");
+  }
+  if ((e = hipFreeAsync(ws, st)) != hipSuccess) return hip_fail(e, "workspace release");
   g_error.clear();
   return RTMI_OK;
 }
@@ -319,7 +715,7 @@ extern "C" {
 
 const char* rtmi_last_error(void) { return g_error.c_str(); }
 
-int32_t rtmi_version(void) { return 100; }
+int32_t rtmi_version(void) { return 200; }
 
 int64_t rtmi_num_substeps(float step_size, float radiation_velocity, float time_step,
                           int32_t cap) {
@@ -340,8 +736,18 @@ int32_t rtmi_fibonacci_directions(int32_t n, float* host_xyz) {
 
 int32_t rtmi_prepare(int32_t num_rays) {
   if (num_rays < 1 || num_rays > kMaxCount) return fail(RTMI_ERR_INVALID_ARG, "num_rays must be in [1, 2^24]");
-  const float4* d = nullptr;
+  DevTable d;
   return get_dirs(num_rays, nullptr, &d);
+}
+
+int32_t rtmi_reserve(int64_t bytes) {
+  if (bytes < 0) return fail(RTMI_ERR_INVALID_ARG, "bytes must be >= 0");
+  void* p = nullptr;
+  if (int32_t rc = pool_alloc(&p, static_cast<size_t>(bytes), nullptr)) return rc;
+  hipError_t e = hipFreeAsync(p, nullptr);
+  if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+  if (e != hipSuccess) return hip_fail(e, "rtmi_reserve");
+  return RTMI_OK;
 }
 
 int32_t rtmi_trace_single(const float* j_map, const float* kappa_map, int32_t nx, int32_t ny,
@@ -379,6 +785,17 @@ int32_t rtmi_trace_bins(const float* j_maps, int64_t j_bin_stride, const float* 
   return run(p);
 }
 
+int32_t rtmi_trace_vjp(const float* j_map, const float* kappa_map, int32_t nx, int32_t ny,
+                       int32_t nz, int32_t n_src, const float* source_pos,
+                       const int32_t* num_rays, const int32_t* substep_cap, float step_size,
+                       float radiation_velocity, float time_step, const float* grad_field,
+                       float* grad_j, float* grad_kappa, void* stream) {
+  const Problem p{j_map, 0, kappa_map, 0, nullptr, 1, nx, ny, nz, n_src, source_pos, num_rays,
+                  substep_cap, step_size, radiation_velocity, time_step, grad_j, nullptr,
+                  static_cast<hipStream_t>(stream)};
+  return run_vjp(p, grad_field, grad_j, grad_kappa);
+}
+
 int32_t rtmi_debug_rays(const float* j_map, const float* kappa_map, int32_t nx, int32_t ny,
                         int32_t nz, const float* source_pos, int32_t num_rays, float step_size,
                         float radiation_velocity, float time_step, int32_t cap, float* out_rays,
@@ -396,7 +813,9 @@ int32_t rtmi_debug_rays(const float* j_map, const float* kappa_map, int32_t nx, 
   const hipStream_t s = static_cast<hipStream_t>(stream);
   rtmi::DebugArgs a;
   std::memset(&a, 0, sizeof a);
-  if (int32_t st = get_dirs(num_rays, s, &a.dirs)) return st;
+  DevTable t;
+  if (int32_t st = get_dirs(num_rays, s, &t)) return st;
+  a.dirs = t.dirs;
   a.j = j_map;
   a.kap = kappa_map;
   a.out_rays = out_rays;
@@ -419,16 +838,19 @@ int32_t rtmi_debug_rays(const float* j_map, const float* kappa_map, int32_t nx, 
 int32_t rtmi_timing_enable(int32_t on) {
   std::lock_guard<std::mutex> lock(g_tmu);
   g_timing = on != 0;
-  for (auto& ev : g_pending) g_free.push_back(ev);
-  g_pending.clear();
+  for (auto& v : g_pending) {
+    for (auto& ev : v) g_free.push_back(ev);
+    v.clear();
+  }
   return RTMI_OK;
 }
 
-int32_t rtmi_timing_read(double* total_ms, int64_t* launches) {
+int32_t rtmi_timing_read(int32_t kind, double* total_ms, int64_t* launches) {
   if (!total_ms || !launches) return fail(RTMI_ERR_INVALID_ARG, "null output pointer");
+  if (kind < 0 || kind > 2) return fail(RTMI_ERR_INVALID_ARG, "unknown kernel kind %d", kind);
   std::lock_guard<std::mutex> lock(g_tmu);
   double sum = 0.0;
-  for (auto& ev : g_pending) {
+  for (auto& ev : g_pending[kind]) {
     hipError_t e = hipEventSynchronize(ev.second);
     float ms = 0.0f;
     if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.first, ev.second);
@@ -436,9 +858,9 @@ int32_t rtmi_timing_read(double* total_ms, int64_t* launches) {
     sum += ms;
   }
   *total_ms = sum;
-  *launches = static_cast<int64_t>(g_pending.size());
-  for (auto& ev : g_pending) g_free.push_back(ev);
-  g_pending.clear();
+  *launches = static_cast<int64_t>(g_pending[kind].size());
+  for (auto& ev : g_pending[kind]) g_free.push_back(ev);
+  g_pending[kind].clear();
   return RTMI_OK;
 }
 

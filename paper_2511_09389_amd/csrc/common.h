@@ -9,6 +9,14 @@ namespace rtmi {
 constexpr int kBlock = 256;          // lanes (rays) per work-group
 constexpr int kMaxSrcPerLaunch = 32; // sources described in one launch's arguments
 constexpr int kMaxBinsPerLaunch = 4; // bins a lane carries at once
+constexpr int kPatch = 64;           // rays per coherent patch (one wavefront)
+constexpr int kTile = 16;            // output tile edge, voxels
+constexpr int kTileVox = kTile * kTile * kTile;
+constexpr int kTileThreads = 1024;   // lanes per tile work-group
+constexpr int kChunk = 8;            // consecutive substeps one tile lane sums in registers
+constexpr int kSeg = 4;              // substeps per recomputed segment of the adjoint sweep
+constexpr int kRowAlign = 8;         // workspace rows are padded to this many substeps
+constexpr int kXcds = 8;             // accelerator complex dies; work-groups go round-robin
 
 // Everything one launch of the march needs, passed by value as kernel arguments so a
 // call needs no per-call device buffer (and no allocation) for its source table.
@@ -33,6 +41,81 @@ struct MarchArgs {
   const float4* dirs[kMaxSrcPerLaunch];
 };
 
+// Phase 1 of the two-phase march: per-ray recurrence, deposit values to the workspace.
+struct RecordArgs {
+  const float2* med;          // (j, kappa) interleaved, one padding voxel at the end; or null
+  const float* j;
+  long long j_stride;
+  const float* kap;
+  long long k_stride;
+  float kscale[kMaxBinsPerLaunch];
+  float* V;                   // workspace rows of bin 0
+  long long v_bin_stride;     // elements between bins' rows
+  float* corner;              // [NB][8] sums of samples collapsed onto a box corner
+  unsigned long long* corner_q;  // the same in fixed point (deterministic mode)
+  const double* det_scale;
+  int nx, ny, nz;
+  float ds;
+  int n_src;
+  int blk_begin[kMaxSrcPerLaunch + 1];
+  float sx[kMaxSrcPerLaunch], sy[kMaxSrcPerLaunch], sz[kMaxSrcPerLaunch];
+  float wray[kMaxSrcPerLaunch];
+  int nrays[kMaxSrcPerLaunch];
+  int nsub[kMaxSrcPerLaunch];
+  int vstride[kMaxSrcPerLaunch];
+  long long vbase[kMaxSrcPerLaunch];
+  const float4* dirs[kMaxSrcPerLaunch];
+};
+
+// Phase 2: tile-owned accumulation of the recorded deposit values.
+struct TileArgs {
+  const float* V;
+  long long v_bin_stride;
+  const float* corner;
+  const unsigned long long* corner_q;
+  float* out;
+  unsigned long long* out_q;
+  const double* det_scale;
+  long long out_stride;
+  int nx, ny, nz;
+  int tiles_x, tiles_y, tiles_z;
+  float ds;
+  int n_src;
+  int accumulate;             // 0: store the tile; 1: add to the field already there
+  int pbegin[kMaxSrcPerLaunch + 1];  // prefix sums of patch counts over sources
+  float sx[kMaxSrcPerLaunch], sy[kMaxSrcPerLaunch], sz[kMaxSrcPerLaunch];
+  int nrays[kMaxSrcPerLaunch];
+  int nsub[kMaxSrcPerLaunch];
+  int vstride[kMaxSrcPerLaunch];
+  long long vbase[kMaxSrcPerLaunch];
+  const float4* dirs[kMaxSrcPerLaunch];
+  const float* pbounds[kMaxSrcPerLaunch];  // per patch: min x, y, z, max x, y, z, -, -
+};
+
+// Adjoint of the march: per-ray reverse sweep with checkpointed recomputation.
+struct AdjointArgs {
+  const float2* med;          // (j, kappa) interleaved, one padding voxel at the end
+  const float* grad;          // dL/dJ, [nx][ny][nz]
+  float* Vj;                  // rows: dL/dj contribution of each sample (I-bar E ds)
+  float* Vk;                  // rows: dL/dkappa of each sample, deposited at its nearest voxel
+  float2* ckpt;               // (I, E) at the start of every segment of every ray
+  float* corner_j;            // [8] sums of collapsed samples per box corner
+  float* corner_k;            // [8]
+  int nx, ny, nz;
+  float ds;
+  int n_src;
+  int blk_begin[kMaxSrcPerLaunch + 1];
+  float sx[kMaxSrcPerLaunch], sy[kMaxSrcPerLaunch], sz[kMaxSrcPerLaunch];
+  float wray[kMaxSrcPerLaunch];
+  int nrays[kMaxSrcPerLaunch];
+  int nsub[kMaxSrcPerLaunch];
+  int vstride[kMaxSrcPerLaunch];
+  long long vbase[kMaxSrcPerLaunch];
+  int cstride[kMaxSrcPerLaunch];
+  long long cbase[kMaxSrcPerLaunch];
+  const float4* dirs[kMaxSrcPerLaunch];
+};
+
 struct DebugArgs {
   const float* j;
   const float* kap;
@@ -49,6 +132,13 @@ struct DebugArgs {
 hipError_t launch_march(const MarchArgs& a, int n_bins, bool shared_j, bool deterministic,
                         int n_blocks, hipStream_t s);
 hipError_t launch_debug(const DebugArgs& a, hipStream_t s);
+hipError_t launch_record(const RecordArgs& a, int n_bins, bool shared_j, bool deterministic,
+                         int n_blocks, hipStream_t s);   // uses a.med when it is not null
+hipError_t launch_tile(const TileArgs& a, int n_bins, bool deterministic, bool nearest,
+                       int n_tiles, hipStream_t s);
+hipError_t launch_adjoint_record(const AdjointArgs& a, int n_blocks, hipStream_t s);
+hipError_t launch_interleave(const float* j, const float* kap, float2* med, long long cells,
+                             hipStream_t s);
 hipError_t launch_fill_zero(float* p, long long n, hipStream_t s);
 hipError_t launch_fill_zero_u64(unsigned long long* p, long long n, hipStream_t s);
 hipError_t launch_det_scale(const float* j, long long j_count, double bound_per_unit_j,

@@ -7,36 +7,10 @@
 #include <type_traits>
 
 #include "common.h"
+#include "device_common.h"
 
 namespace rtmi {
 namespace {
-
-// One axis of the clamped trilinear stencil and of the nearest-voxel pick at x.
-struct Axis {
-  int lo, hi;       // clamped corner indices
-  float w0, w1;     // 1-D weights of lo and hi (they sum to 1)
-  int nearest;      // clamped round-half-to-even index
-};
-
-__device__ __forceinline__ Axis axis_stencil(float x, int n) {
-  const float fl = floorf(x);
-  const float f = x - fl;  // exact for binary32 x
-  const int i = static_cast<int>(fminf(fmaxf(fl, -1.0f), static_cast<float>(n - 1)));
-  Axis a;
-  a.lo = max(i, 0);
-  a.hi = min(i + 1, n - 1);
-  a.w0 = 1.0f - f;
-  a.w1 = f;
-  a.nearest = static_cast<int>(fminf(fmaxf(rintf(x), 0.0f), static_cast<float>(n - 1)));
-  return a;
-}
-
-// x = fl(src + fl(t * n)): two separately rounded binary32 operations, never fused.
-__device__ __forceinline__ float sample_axis(float src, float t, float n) {
-#pragma clang fp contract(off)
-  const float p = t * n;
-  return src + p;
-}
 
 struct Stencil {
   int off[8];

@@ -1,0 +1,684 @@
+// Two-phase (output-stationary) march of librtmi.
+//
+// Phase 1, record_kernel: one lane per ray runs the recurrence of Eq. (2) and writes the
+// deposit value v_k = (4 pi / N_Omega) I_{k+1} of every substep to a workspace row, in
+// whole 32-byte pieces; gathers for a chunk of substeps are issued together and waited
+// for once. Samples whose stencil has collapsed onto a single corner voxel of the box
+// (outside along all three axes) are summed per lane and reduced per corner instead.
+//
+// Phase 2, tile_kernel: one work-group owns a 16^3 tile of the output. For every
+// (source, 64-ray patch) whose swept bounding box reaches the tile, each lane finds the
+// substep range of its ray that can touch the tile (the tile widened by the stencil and,
+// on the box faces, extended to infinity to catch clamped samples), recomputes the same
+// binary32 sample points and adds v_k times the trilinear weights of the corners inside
+// the tile to a binary64 LDS accumulator. The tile is then stored with plain coalesced
+// writes.
+// No global float atomics are used for the field.
+#include <type_traits>
+
+#include "common.h"
+#include "device_common.h"
+
+namespace rtmi {
+namespace {
+
+constexpr float kBig = 1.0e30f;
+
+// 16-byte vector that needs only 8-byte alignment: two consecutive (j, kappa) voxels.
+typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
+
+__global__ void interleave_kernel(const float* __restrict__ j, const float* __restrict__ kap,
+                                  float2* __restrict__ med, long long cells) {
+  const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i <= cells;
+       i += stride)
+    med[i] = i < cells ? make_float2(j[i], kap[i]) : make_float2(0.0f, 0.0f);
+}
+
+// MED: j and kappa come interleaved from a.med (a shared j and a shared, scaled kappa);
+// one 16-byte load returns (j, kappa) of the two z-corners of one (x, y) column, and the
+// nearest voxel, always one of the eight corners, supplies kappa without a ninth load.
+template <int NB, bool SHARED_J, bool DET, bool MED>
+__global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
+  constexpr int C = SHARED_J ? 8 : 4;
+  __shared__ float ctail[NB][8];
+  __shared__ unsigned long long ctail_q[NB][8];
+  const int tid = static_cast<int>(threadIdx.x);
+  if (tid < NB * 8) {
+    ctail[tid / 8][tid % 8] = 0.0f;
+    ctail_q[tid / 8][tid % 8] = 0ull;
+  }
+  __syncthreads();
+
+  // Work-group i runs on XCD i mod 8; give each XCD a contiguous run of logical blocks
+  // (whole sources) so that one source's rays share that XCD's L2.
+  const int nblk = a.blk_begin[a.n_src];
+  const int per_xcd = (nblk + kXcds - 1) / kXcds;
+  const int blk = (static_cast<int>(blockIdx.x) % kXcds) * per_xcd + static_cast<int>(blockIdx.x) / kXcds;
+  int s = 0;
+  while (s + 1 < a.n_src && blk >= a.blk_begin[s + 1]) ++s;
+  const int ray = (blk - a.blk_begin[s]) * kBlock + tid;
+  if (blk < nblk && ray < a.nrays[s]) {
+    const float4 d = a.dirs[s][ray];
+    const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
+    const float wray = a.wray[s];
+    const int nsub = a.nsub[s];
+    const float ds = a.ds;
+    const int nx = a.nx, ny = a.ny, nz = a.nz, nyz = ny * nz;
+    const bool shared_k = (a.k_stride == 0);
+    float* vrow = a.V + a.vbase[s] + static_cast<long long>(ray) * a.vstride[s];
+    double det_scale = 0.0;
+    if constexpr (DET) det_scale = *a.det_scale;
+
+    float I[NB], E[NB], tail[NB];
+    long long tail_q[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      I[b] = 0.0f;
+      E[b] = 1.0f;
+      tail[b] = 0.0f;
+      tail_q[b] = 0;
+    }
+    int corner = -1;
+    // A chunk's values are stored only after the next chunk's gathers have been issued:
+    // loads and stores share one counter, so the wait for those gathers then also
+    // covers stores that were in flight at the same time, not one round trip later.
+    float vprev[C][NB];
+    int kprev = -1;
+    // Settle the loads above (direction, scale) here, once: otherwise the wait for them is
+    // placed at the loop head and every iteration also waits for the previous stores.
+    __builtin_amdgcn_s_waitcnt(0);
+
+    for (int k0 = 0; k0 < nsub; k0 += C) {
+      float jv[C][NB][8];
+      float kv[C][NB];
+      float fx[C], fy[C], fz[C];
+      int cid[C];
+      // issue every gather of the chunk before using any of them
+#pragma unroll
+      for (int t = 0; t < C; ++t) {
+        const int k = min(k0 + t, nsub - 1);
+        const float dist = sample_distance(k, ds);
+        const float x = sample_axis(sx, dist, d.x);
+        const float y = sample_axis(sy, dist, d.y);
+        const float z = sample_axis(sz, dist, d.z);
+        const Axis X = axis_stencil(x, nx);
+        const Axis Y = axis_stencil(y, ny);
+        const Axis Z = axis_stencil(z, nz);
+        const int ox[2] = {X.lo * nyz, X.hi * nyz};
+        const int oy[2] = {Y.lo * nz, Y.hi * nz};
+        const int oz[2] = {Z.lo, Z.hi};
+        if constexpr (MED) {
+          const bool zsame = Z.lo == Z.hi;
+          const int nsel = ((X.nearest == X.hi ? 4 : 0) | (Y.nearest == Y.hi ? 2 : 0));
+          const bool zsel = Z.nearest == Z.hi && !zsame;
+          float kn = 0.0f;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const f4a8 v = *reinterpret_cast<const f4a8*>(a.med + ox[q >> 1] + oy[q & 1] + oz[0]);
+            jv[t][0][2 * q] = v.x;
+            jv[t][0][2 * q + 1] = zsame ? v.x : v.z;
+            if ((q << 1) == nsel) kn = zsel ? v.w : v.y;
+          }
+          kv[t][0] = kn;
+        } else {
+          const int nearest = X.nearest * nyz + Y.nearest * nz + Z.nearest;
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            if (SHARED_J && b > 0) break;
+            const float* jb = a.j + b * a.j_stride;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) jv[t][b][c] = jb[ox[c >> 2] + oy[(c >> 1) & 1] + oz[c & 1]];
+          }
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            if (shared_k && b > 0) break;
+            kv[t][b] = a.kap[b * a.k_stride + nearest];
+          }
+        }
+        fx[t] = X.w1;
+        fy[t] = Y.w1;
+        fz[t] = Z.w1;
+        const bool out3 = axis_clamped(x, nx) && axis_clamped(y, ny) && axis_clamped(z, nz);
+        cid[t] = out3 ? ((x >= 0.0f ? 4 : 0) | (y >= 0.0f ? 2 : 0) | (z >= 0.0f ? 1 : 0)) : -1;
+      }
+      if (kprev >= 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          float4* dst = reinterpret_cast<float4*>(vrow + b * a.v_bin_stride + kprev);
+#pragma unroll
+          for (int q = 0; q < C / 4; ++q)
+            dst[q] = make_float4(vprev[4 * q][b], vprev[4 * q + 1][b], vprev[4 * q + 2][b],
+                                 vprev[4 * q + 3][b]);
+        }
+      }
+      float vout[C][NB];
+#pragma unroll
+      for (int t = 0; t < C; ++t) {
+        const float wx[2] = {1.0f - fx[t], fx[t]};
+        const float wy[2] = {1.0f - fy[t], fy[t]};
+        const float wz[2] = {1.0f - fz[t], fz[t]};
+        float jk[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const int bj = SHARED_J ? 0 : b;
+          float acc = 0.0f;
+#pragma unroll
+          for (int c = 0; c < 8; ++c)
+            acc += (wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1] * jv[t][bj][c];
+          jk[b] = acc;
+        }
+        const bool live = (k0 + t) < nsub;
+        const bool collapsed = live && cid[t] >= 0;
+        // A ray can pass several corner regions (a source outside the box, a ray that
+        // misses it): hand the running sum over whenever the corner changes.
+        if (collapsed && cid[t] != corner) {
+          if (corner >= 0) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              if constexpr (DET)
+                atomicAdd(&ctail_q[b][corner], static_cast<unsigned long long>(tail_q[b]));
+              else
+                atomicAdd(&ctail[b][corner], tail[b]);
+              tail[b] = 0.0f;
+              tail_q[b] = 0;
+            }
+          }
+          corner = cid[t];
+        }
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const float kap = shared_k ? kv[t][0] * a.kscale[b] : kv[t][b];
+          const float att = expf(-kap * ds);
+          // Eq. (2): emission uses exp(-tau_k) from before this step's attenuation.
+          const float In = I[b] * att + jk[b] * E[b] * ds;
+          const float En = E[b] * att;
+          I[b] = live ? In : I[b];
+          E[b] = live ? En : E[b];
+          float v = wray * I[b];
+          if (collapsed) {
+            if constexpr (DET)
+              tail_q[b] += __double2ll_rn(static_cast<double>(v) * det_scale);
+            else
+              tail[b] += v;
+            v = 0.0f;
+          }
+          vout[t][b] = live ? v : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < C; ++t)
+#pragma unroll
+        for (int b = 0; b < NB; ++b) vprev[t][b] = vout[t][b];
+      kprev = k0;
+    }
+    // the last chunk, in whole 16-byte pieces (rows are padded to a multiple of 8 substeps)
+    if (kprev >= 0) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        float4* dst = reinterpret_cast<float4*>(vrow + b * a.v_bin_stride + kprev);
+#pragma unroll
+        for (int q = 0; q < C / 4; ++q)
+          dst[q] = make_float4(vprev[4 * q][b], vprev[4 * q + 1][b], vprev[4 * q + 2][b],
+                               vprev[4 * q + 3][b]);
+      }
+    }
+    if (corner >= 0) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        if constexpr (DET)
+          atomicAdd(&ctail_q[b][corner], static_cast<unsigned long long>(tail_q[b]));
+        else
+          atomicAdd(&ctail[b][corner], tail[b]);
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < NB * 8) {
+    const int b = tid / 8, c = tid % 8;
+    if constexpr (DET) {
+      if (ctail_q[b][c] != 0ull) atomicAdd(a.corner_q + b * 8 + c, ctail_q[b][c]);
+    } else {
+      if (ctail[b][c] != 0.0f) unsafeAtomicAdd(a.corner + b * 8 + c, ctail[b][c]);
+    }
+  }
+}
+
+// Interval of t with s + t n in [lo, hi); empty when t0 > t1.
+__device__ __forceinline__ void axis_span(float s, float n, float lo, float hi, float& t0,
+                                          float& t1) {
+  if (n == 0.0f) {
+    const bool in = s >= lo && s < hi;
+    t0 = in ? -kBig : 1.0f;
+    t1 = in ? kBig : 0.0f;
+  } else {
+    const float ta = (lo - s) / n, tb = (hi - s) / n;
+    t0 = fminf(ta, tb);
+    t1 = fmaxf(ta, tb);
+  }
+}
+
+// Substep interval of a ray that can reach [lo, hi) along one axis.
+__device__ __forceinline__ void clip_axis(float s, float n, float lo, float hi, float& t0,
+                                          float& t1) {
+  if (n == 0.0f) {
+    if (!(s >= lo && s < hi)) {
+      t0 = 1.0f;
+      t1 = 0.0f;
+    }
+  } else {
+    const float ta = (lo - s) / n, tb = (hi - s) / n;
+    t0 = fmaxf(t0, fminf(ta, tb));
+    t1 = fminf(t1, fmaxf(ta, tb));
+  }
+}
+
+// Per-lane 2x2x2 window over a ray's consecutive samples inside one tile: the deposits of
+// a chunk of substeps are summed in registers and reach the LDS tile only when the
+// stencil moves on (the layer left behind is flushed) or the chunk ends. Slot
+// c = (cx << 2) | (cy << 1) | cz; voxels outside the tile are dropped (another tile owns them).
+// In the deterministic mode the tile holds 64-bit fixed point: a flushed sum is scaled and
+// rounded to an integer before the (order-independent) integer add.
+template <typename T>
+__device__ __forceinline__ T tile_value(float v, double scale) {
+  if constexpr (std::is_same<T, unsigned long long>::value)
+    return static_cast<unsigned long long>(__double2ll_rn(static_cast<double>(v) * scale));
+  else
+    return static_cast<T>(v);
+}
+
+template <int NB>
+struct TileWindow {
+  float acc[NB][8];
+  int lo[3], hi[3];
+  int o[3], e[3];
+  double scale;   // fixed-point scale (deterministic mode only)
+
+  __device__ __forceinline__ TileWindow(int x0, int y0, int z0, int ex, int ey, int ez,
+                                        double fixed_scale) {
+    scale = fixed_scale;
+    o[0] = x0; o[1] = y0; o[2] = z0;
+    e[0] = ex; e[1] = ey; e[2] = ez;
+    lo[0] = lo[1] = lo[2] = hi[0] = hi[1] = hi[2] = -1;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int c = 0; c < 8; ++c) acc[b][c] = 0.0f;
+  }
+
+  template <typename T>
+  __device__ __forceinline__ void flush(int c, T (*tile)[kTileVox]) {
+    const int lx = ((c & 4) ? hi[0] : lo[0]) - o[0];
+    const int ly = ((c & 2) ? hi[1] : lo[1]) - o[1];
+    const int lz = ((c & 1) ? hi[2] : lo[2]) - o[2];
+    const bool inside = lx >= 0 && lx < e[0] && ly >= 0 && ly < e[1] && lz >= 0 && lz < e[2];
+    const int li = (lx * kTile + ly) * kTile + lz;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      if (inside && acc[b][c] != 0.0f) atomicAdd(&tile[b][li], tile_value<T>(acc[b][c], scale));
+      acc[b][c] = 0.0f;
+    }
+  }
+
+  template <typename T>
+  __device__ __forceinline__ void flush_all(T (*tile)[kTileVox]) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) flush(c, tile);
+  }
+
+  template <int A, typename T>
+  __device__ __forceinline__ void advance(int lo_new, int hi_new, bool up, T (*tile)[kTileVox]) {
+    constexpr int bit = 4 >> A;
+    if (lo_new == lo[A] && hi_new == hi[A]) return;
+    if (up && lo_new == hi[A]) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c & bit) continue;
+        flush(c, tile);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          acc[b][c] = acc[b][c | bit];
+          acc[b][c | bit] = 0.0f;
+        }
+      }
+    } else if (!up && hi_new == lo[A]) {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        if (c & bit) continue;
+        flush(c | bit, tile);
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          acc[b][c | bit] = acc[b][c];
+          acc[b][c] = 0.0f;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < 8; ++c) flush(c, tile);
+    }
+    lo[A] = lo_new;
+    hi[A] = hi_new;
+  }
+};
+
+// The tile is accumulated in binary64 (or 64-bit fixed point in the deterministic mode):
+// a voxel next to a source collects thousands of deposits, and binary32 running sums of
+// that length drift by more than the binary32 field is allowed to differ from the exact one.
+// NEAREST: each sample adds its value to its nearest voxel only (the adjoint's kappa
+// deposit) instead of the trilinear stencil.
+// Lanes per tile work-group: 1024, or 512 when three or four bins' windows would not fit
+// in the registers 1024 lanes leave per lane.
+template <int NB>
+constexpr int tile_threads() { return NB <= 2 ? kTileThreads : kTileThreads / 2; }
+
+template <int NB, bool DET, bool NEAREST>
+__global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs a) {
+  using T = typename std::conditional<DET, unsigned long long, double>::type;
+  __shared__ T acc[NB][kTileVox];
+  const int tid = static_cast<int>(threadIdx.x);
+  constexpr int kThreads = tile_threads<NB>();
+  for (int i = tid; i < NB * kTileVox; i += kThreads) (&acc[0][0])[i] = T(0);
+
+  const int t = blockIdx.x;
+  const int tz = t % a.tiles_z, ty = (t / a.tiles_z) % a.tiles_y, tx = t / (a.tiles_z * a.tiles_y);
+  const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
+  const int ex = min(kTile, a.nx - x0), ey = min(kTile, a.ny - y0), ez = min(kTile, a.nz - z0);
+  // positions whose clamped stencil can reach the tile: [x0 - 1, x0 + ex), unbounded on faces
+  const float Ax = x0 == 0 ? -kBig : static_cast<float>(x0 - 1);
+  const float Bx = x0 + ex == a.nx ? kBig : static_cast<float>(x0 + ex);
+  const float Ay = y0 == 0 ? -kBig : static_cast<float>(y0 - 1);
+  const float By = y0 + ey == a.ny ? kBig : static_cast<float>(y0 + ey);
+  const float Az = z0 == 0 ? -kBig : static_cast<float>(z0 - 1);
+  const float Bz = z0 + ez == a.nz ? kBig : static_cast<float>(z0 + ez);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const float ds = a.ds;
+  double det_scale = 0.0;
+  if constexpr (DET) det_scale = *a.det_scale;
+  __syncthreads();
+
+  const int wave = tid >> 6, lane = tid & 63;
+  constexpr int kWaves = kThreads / 64;
+  // Per-wave staging of one patch's rays: exclusive prefix of their chunk counts, substep
+  // range and direction. A chunk is the part of one ray's range inside one aligned block
+  // of kChunk substeps, so the patch's work can be dealt out 64 chunks at a time and each
+  // chunk's recorded values arrive in two aligned 16-byte loads.
+  __shared__ int w_excl[kWaves][kPatch + 1];
+  __shared__ int w_k0[kWaves][kPatch];
+  __shared__ int w_k1[kWaves][kPatch];
+  __shared__ float4 w_dir[kWaves][kPatch];
+  const int npairs = a.pbegin[a.n_src];
+  // (source, patch) pairs are handed out one at a time: the pairs that reach a tile come
+  // in clusters, and a static deal leaves most waves idle at the final barrier.
+  __shared__ int next_pair;
+  if (tid == 0) next_pair = 0;
+  __syncthreads();
+  for (;;) {
+    int p = 0;
+    if (lane == 0) p = atomicAdd(&next_pair, 1);
+    p = __shfl(p, 0, 64);
+    if (p >= npairs) break;
+    int s = 0;
+    while (s + 1 < a.n_src && p >= a.pbegin[s + 1]) ++s;
+    const int patch = p - a.pbegin[s];
+    const int nsub = a.nsub[s];
+    const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
+    const float tmax = sample_distance(nsub - 1, ds);
+    // Position-space margin above the rounding of any binary32 sample point of this
+    // source (a few ulps of the largest coordinate involved).
+    const float m = 5.0e-7f * (fmaxf(fabsf(sx), fmaxf(fabsf(sy), fabsf(sz))) + tmax + 2.0f) + 1.0e-6f;
+    // bounding box of the patch's ray segments [0, tmax] (direction bounds are exact)
+    const float* pb = a.pbounds[s] + patch * 8;
+    if (sx + fmaxf(0.0f, tmax * pb[3]) + m < Ax || sx + fminf(0.0f, tmax * pb[0]) - m >= Bx ||
+        sy + fmaxf(0.0f, tmax * pb[4]) + m < Ay || sy + fminf(0.0f, tmax * pb[1]) - m >= By ||
+        sz + fmaxf(0.0f, tmax * pb[5]) + m < Az || sz + fminf(0.0f, tmax * pb[2]) - m >= Bz)
+      continue;
+
+    // this lane's ray: the substep range that can reach the tile
+    const int ray = patch * kPatch + lane;
+    int ka = 0, kb = -1;
+    float4 d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (ray < a.nrays[s]) {
+      d = a.dirs[s][ray];
+      float t0 = 0.0f, t1 = tmax;
+      clip_axis(sx, d.x, Ax - m, Bx + m, t0, t1);
+      clip_axis(sy, d.y, Ay - m, By + m, t0, t1);
+      clip_axis(sz, d.z, Az - m, Bz + m, t0, t1);
+      // Samples collapsed onto a corner voxel (clamped along all three axes) belong to the
+      // record phase. Along a straight ray each axis is unclamped on one interval of t;
+      // only the hull of those intervals can hold samples for this kernel.
+      float h0 = kBig, h1 = -kBig, u0, u1;
+      if (nx > 1) {
+        axis_span(sx, d.x, -m, static_cast<float>(nx - 1) + m, u0, u1);
+        if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
+      }
+      if (ny > 1) {
+        axis_span(sy, d.y, -m, static_cast<float>(ny - 1) + m, u0, u1);
+        if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
+      }
+      if (nz > 1) {
+        axis_span(sz, d.z, -m, static_cast<float>(nz - 1) + m, u0, u1);
+        if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
+      }
+      t0 = fmaxf(t0, h0);
+      t1 = fminf(t1, h1);
+      if (t0 <= t1) {
+        // one substep of margin on each side covers the rounding of t = k ds
+        ka = max(0, static_cast<int>(floorf(t0 / ds)) - 1);
+        kb = min(nsub - 1, static_cast<int>(fminf(ceilf(t1 / ds), 1.0e8f)) + 1);
+      }
+    }
+    const int chunks = kb >= ka ? kb / kChunk - ka / kChunk + 1 : 0;
+    // inclusive prefix sum of the chunk counts across the wavefront
+    int incl = chunks;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += o;
+    }
+    const int total = __shfl(incl, 63, 64);
+    if (total == 0) continue;
+    w_excl[wave][lane + 1] = incl;
+    if (lane == 0) w_excl[wave][0] = 0;
+    w_k0[wave][lane] = ka;
+    w_k1[wave][lane] = kb;
+    w_dir[wave][lane] = d;
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+
+    const long long row0 = a.vbase[s] + static_cast<long long>(patch) * kPatch * a.vstride[s];
+    for (int base = 0; base < total; base += 64) {
+      const int i = base + lane;
+      if (i >= total) continue;
+      // owner lane o: w_excl[o] <= i < w_excl[o + 1]
+      int lo = 0, hi = 64;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (w_excl[wave][mid] <= i) lo = mid;
+        else hi = mid;
+      }
+      const int o = lo;
+      const int ka_o = w_k0[wave][o], kb_o = w_k1[wave][o];
+      const int kblk = (ka_o / kChunk + (i - w_excl[wave][o])) * kChunk;
+      const int kbeg = max(ka_o, kblk), kend = min(kb_o, kblk + kChunk - 1);
+      const float4 dd = w_dir[wave][o];
+      const bool up[3] = {dd.x >= 0.0f, dd.y >= 0.0f, dd.z >= 0.0f};
+      const float* vrow = a.V + row0 + static_cast<long long>(o) * a.vstride[s];
+      // the chunk's recorded values, fetched before any of them is needed
+      float vv[NB][kChunk];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float4* src4 = reinterpret_cast<const float4*>(vrow + b * a.v_bin_stride + kblk);
+#pragma unroll
+        for (int q = 0; q < kChunk / 4; ++q) {
+          const float4 f = src4[q];
+          vv[b][4 * q] = f.x;
+          vv[b][4 * q + 1] = f.y;
+          vv[b][4 * q + 2] = f.z;
+          vv[b][4 * q + 3] = f.w;
+        }
+      }
+      TileWindow<NB> win(x0, y0, z0, ex, ey, ez, det_scale);
+      int near_li = -1;         // NEAREST: voxel of the running sum, -1 when empty
+      float near_acc[NB];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) near_acc[b] = 0.0f;
+#pragma unroll
+      for (int t = 0; t < kChunk; ++t) {
+        const int k = kblk + t;
+        if (k < kbeg || k > kend) continue;
+        const float dist = sample_distance(k, ds);
+        const float x = sample_axis(sx, dist, dd.x);
+        const float y = sample_axis(sy, dist, dd.y);
+        const float z = sample_axis(sz, dist, dd.z);
+        // collapsed onto one corner voxel: summed by the record phase
+        if (axis_clamped(x, nx) && axis_clamped(y, ny) && axis_clamped(z, nz)) continue;
+        const Axis X = axis_stencil(x, nx);
+        const Axis Y = axis_stencil(y, ny);
+        const Axis Z = axis_stencil(z, nz);
+        if constexpr (NEAREST) {
+          const int lx = X.nearest - x0, ly = Y.nearest - y0, lz = Z.nearest - z0;
+          if (lx < 0 || lx >= ex || ly < 0 || ly >= ey || lz < 0 || lz >= ez) continue;
+          const int li = (lx * kTile + ly) * kTile + lz;
+          if (li != near_li) {
+            if (near_li >= 0) {
+#pragma unroll
+              for (int b = 0; b < NB; ++b)
+                if (near_acc[b] != 0.0f) atomicAdd(&acc[b][near_li], tile_value<T>(near_acc[b], det_scale));
+            }
+            near_li = li;
+#pragma unroll
+            for (int b = 0; b < NB; ++b) near_acc[b] = 0.0f;
+          }
+#pragma unroll
+          for (int b = 0; b < NB; ++b) near_acc[b] += vv[b][t];
+        } else {
+          // no corner of this sample inside the tile: nothing to add
+          if (X.hi < x0 || X.lo >= x0 + ex || Y.hi < y0 || Y.lo >= y0 + ey || Z.hi < z0 ||
+              Z.lo >= z0 + ez)
+            continue;
+          win.template advance<0>(X.lo, X.hi, up[0], acc);
+          win.template advance<1>(Y.lo, Y.hi, up[1], acc);
+          win.template advance<2>(Z.lo, Z.hi, up[2], acc);
+          // an axis whose two corners coincide carries its whole weight on the lower one
+          const float wx[2] = {X.lo == X.hi ? 1.0f : X.w0, X.lo == X.hi ? 0.0f : X.w1};
+          const float wy[2] = {Y.lo == Y.hi ? 1.0f : Y.w0, Y.lo == Y.hi ? 0.0f : Y.w1};
+          const float wz[2] = {Z.lo == Z.hi ? 1.0f : Z.w0, Z.lo == Z.hi ? 0.0f : Z.w1};
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const float v = vv[b][t];
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+              win.acc[b][c] += v * ((wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1]);
+          }
+        }
+      }
+      if constexpr (NEAREST) {
+        if (near_li >= 0) {
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            if (near_acc[b] != 0.0f) atomicAdd(&acc[b][near_li], tile_value<T>(near_acc[b], det_scale));
+        }
+      }
+      win.flush_all(acc);
+    }
+    // the staging arrays are rewritten for the next patch only after every lane is done
+    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+
+  // the corner voxels of the box also receive the record phase's per-corner sums
+  for (int i = tid; i < kTileVox; i += kThreads) {
+    const int lx = i / (kTile * kTile), ly = (i / kTile) % kTile, lz = i % kTile;
+    if (lx >= ex || ly >= ey || lz >= ez) continue;
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    const long long voxel = (static_cast<long long>(gx) * ny + gy) * nz + gz;
+    const bool cx_any = (gx == 0 || gx == nx - 1), cy_any = (gy == 0 || gy == ny - 1),
+               cz_any = (gz == 0 || gz == nz - 1);
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      T val = acc[b][i];
+      if (cx_any && cy_any && cz_any) {
+        for (int c = 0; c < 8; ++c) {
+          const int vx = (c & 4) ? nx - 1 : 0, vy = (c & 2) ? ny - 1 : 0, vz = (c & 1) ? nz - 1 : 0;
+          if (vx == gx && vy == gy && vz == gz) {
+            if constexpr (DET) val += a.corner_q[b * 8 + c];
+            else val += a.corner[b * 8 + c];
+          }
+        }
+      }
+      if constexpr (DET) {
+        unsigned long long* o = a.out_q + b * a.out_stride + voxel;
+        *o = a.accumulate ? *o + val : val;
+      } else {
+        float* o = a.out + b * a.out_stride + voxel;
+        *o = static_cast<float>(a.accumulate ? static_cast<double>(*o) + val : val);
+      }
+    }
+  }
+}
+
+template <int NB>
+hipError_t launch_record_nb(const RecordArgs& a, bool shared_j, bool det, int blocks, hipStream_t s) {
+  // a multiple of the XCD count, so the block remapping is a bijection onto [0, blocks)
+  const dim3 grid((blocks + kXcds - 1) / kXcds * kXcds), block(kBlock);
+  if (a.med) {
+    if (det) hipLaunchKernelGGL((record_kernel<NB, true, true, true>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((record_kernel<NB, true, false, true>), grid, block, 0, s, a);
+  } else if (shared_j) {
+    if (det) hipLaunchKernelGGL((record_kernel<NB, true, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((record_kernel<NB, true, false, false>), grid, block, 0, s, a);
+  } else {
+    if (det) hipLaunchKernelGGL((record_kernel<NB, false, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((record_kernel<NB, false, false, false>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+template <int NB>
+hipError_t launch_tile_nb(const TileArgs& a, bool det, bool nearest, int tiles, hipStream_t s) {
+  const dim3 g(tiles), b(tile_threads<NB>());
+  if (nearest) {
+    if (det) hipLaunchKernelGGL((tile_kernel<NB, true, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((tile_kernel<NB, false, true>), g, b, 0, s, a);
+  } else {
+    if (det) hipLaunchKernelGGL((tile_kernel<NB, true, false>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((tile_kernel<NB, false, false>), g, b, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_record(const RecordArgs& a, int n_bins, bool shared_j, bool det, int blocks,
+                         hipStream_t s) {
+  switch (n_bins) {
+    case 1: return launch_record_nb<1>(a, shared_j, det, blocks, s);
+    case 2: return launch_record_nb<2>(a, shared_j, det, blocks, s);
+    case 3: return launch_record_nb<3>(a, shared_j, det, blocks, s);
+    case 4: return launch_record_nb<4>(a, shared_j, det, blocks, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_interleave(const float* j, const float* kap, float2* med, long long cells,
+                             hipStream_t s) {
+  long long blocks = (cells + 1 + kBlock * 4 - 1) / (kBlock * 4);
+  blocks = blocks < 1 ? 1 : (blocks > 8192 ? 8192 : blocks);
+  hipLaunchKernelGGL(interleave_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, j,
+                     kap, med, cells);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile(const TileArgs& a, int n_bins, bool det, bool nearest, int tiles,
+                       hipStream_t s) {
+  switch (n_bins) {
+    case 1: return launch_tile_nb<1>(a, det, nearest, tiles, s);
+    case 2: return launch_tile_nb<2>(a, det, nearest, tiles, s);
+    case 3: return launch_tile_nb<3>(a, det, nearest, tiles, s);
+    case 4: return launch_tile_nb<4>(a, det, nearest, tiles, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace rtmi

@@ -24,6 +24,11 @@ ERR_UNSUPPORTED = -5
 ERR_RANGE = -6
 ACCUM_ATOMIC = 0
 ACCUM_DETERMINISTIC = 1
+PATH_TILED = 0
+PATH_DIRECT = 1
+KERNEL_RECORD = 0
+KERNEL_TILE = 1
+KERNEL_DIRECT = 2
 
 
 class RtmiError(RuntimeError):
@@ -34,7 +39,7 @@ class RtmiError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("accum_mode", ctypes.c_int32), ("directions", ctypes.c_void_p),
-                ("ray_weight", ctypes.c_float), ("reserved", ctypes.c_int32)]
+                ("ray_weight", ctypes.c_float), ("path", ctypes.c_int32)]
 
 
 def _load():
@@ -49,13 +54,15 @@ def _load():
         "rtmi_num_substeps": (I64, [F32, F32, F32, I32]),
         "rtmi_fibonacci_directions": (I32, [I32, P]),
         "rtmi_prepare": (I32, [I32]),
+        "rtmi_reserve": (I32, [I64]),
         "rtmi_trace_single": (I32, [P, P, I32, I32, I32, P, I32, F32, F32, F32, P, P]),
         "rtmi_trace_multi": (I32, [P, P, I32, I32, I32, I32, P, P, P, F32, F32, F32, P, P]),
         "rtmi_trace_bins": (I32, [P, I64, P, I64, P, I32, I32, I32, I32, I32, P, P, P, F32, F32,
                                   F32, P, ctypes.POINTER(Options), P]),
         "rtmi_debug_rays": (I32, [P, P, I32, I32, I32, P, I32, F32, F32, F32, I32, P, P, P]),
+        "rtmi_trace_vjp": (I32, [P, P, I32, I32, I32, I32, P, P, P, F32, F32, F32, P, P, P, P]),
         "rtmi_timing_enable": (I32, [I32]),
-        "rtmi_timing_read": (I32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+        "rtmi_timing_read": (I32, [I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -117,6 +124,12 @@ def prepare(num_rays, device=None):
         _check(lib.rtmi_prepare(int(num_rays)))
 
 
+def reserve(nbytes, device=None):
+    """Grow the device's workspace pool to at least nbytes (tiled path)."""
+    with torch.cuda.device(device if device is not None else torch.cuda.current_device()):
+        _check(lib.rtmi_reserve(int(nbytes)))
+
+
 def _new_field(shape, like):
     return torch.empty(shape, dtype=torch.float32, device=like.device)
 
@@ -167,7 +180,7 @@ def trace_multi(j_map, kappa_map, source_pos, num_rays, step_size, radiation_vel
 
 def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
                time_step, kappa_scale=None, substep_cap=None, out=None, deterministic=False,
-               directions=None, ray_weight=0.0):
+               directions=None, ray_weight=0.0, path=PATH_TILED):
     """Frequency bins as a batch axis. j_maps / kappa_maps are 3-D (shared by all bins) or
     4-D [B][nx][ny][nz]; a 3-D kappa with kappa_scale gives kappa_b = kappa * scale[b].
     Returns a [B][nx][ny][nz] float32 tensor."""
@@ -191,7 +204,8 @@ def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_ve
         raise ValueError("kappa_scale must have one entry per bin")
     src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
     out = _new_field((n_bins,) + grid, j_maps) if out is None else out
-    opts = Options(ACCUM_DETERMINISTIC if deterministic else ACCUM_ATOMIC, None, float(ray_weight), 0)
+    opts = Options(ACCUM_DETERMINISTIC if deterministic else ACCUM_ATOMIC, None, float(ray_weight),
+                   int(path))
     dirs = None
     if directions is not None:
         dirs = _host_f32(directions, 3)
@@ -207,6 +221,26 @@ def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_ve
             step_size, radiation_velocity, time_step, _dev(out, "out", 4), ctypes.byref(opts),
             _stream(j_maps.device)))
     return out
+
+
+def trace_vjp(j_map, kappa_map, source_pos, num_rays, step_size, radiation_velocity, time_step,
+              grad_field, substep_cap=None, grad_j=None, grad_kappa=None):
+    """Adjoint of trace_multi: (dL/dj, dL/dkappa) for dL/dJ = grad_field (all 3-D float32)."""
+    if tuple(kappa_map.shape) != tuple(j_map.shape) or tuple(grad_field.shape) != tuple(j_map.shape):
+        raise ValueError("j_map, kappa_map and grad_field must have the same shape")
+    nx, ny, nz = j_map.shape
+    src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
+    grad_j = _new_field(j_map.shape, j_map) if grad_j is None else grad_j
+    grad_kappa = _new_field(j_map.shape, j_map) if grad_kappa is None else grad_kappa
+    with torch.cuda.device(j_map.device):
+        _check(lib.rtmi_trace_vjp(_dev(j_map, "j_map", 3), _dev(kappa_map, "kappa_map", 3),
+                                  nx, ny, nz, src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
+                                  nr.ctypes.data_as(ctypes.c_void_p),
+                                  None if cap is None else cap.ctypes.data_as(ctypes.c_void_p),
+                                  step_size, radiation_velocity, time_step,
+                                  _dev(grad_field, "grad_field", 3), _dev(grad_j, "grad_j", 3),
+                                  _dev(grad_kappa, "grad_kappa", 3), _stream(j_map.device)))
+    return grad_j, grad_kappa
 
 
 def debug_rays(j_map, kappa_map, source_pos, num_rays, step_size, radiation_velocity,
@@ -231,9 +265,10 @@ def timing_enable(on=True):
     _check(lib.rtmi_timing_enable(1 if on else 0))
 
 
-def timing_read():
-    """(total milliseconds, launch count) of the march launches timed since the last read."""
+def timing_read(kind):
+    """(total milliseconds, launch count) of the launches of one kernel kind (KERNEL_RECORD,
+    KERNEL_TILE or KERNEL_DIRECT) timed since the last read of that kind."""
     ms = ctypes.c_double(0.0)
     n = ctypes.c_int64(0)
-    _check(lib.rtmi_timing_read(ctypes.byref(ms), ctypes.byref(n)))
+    _check(lib.rtmi_timing_read(int(kind), ctypes.byref(ms), ctypes.byref(n)))
     return ms.value, n.value

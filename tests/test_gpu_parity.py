@@ -50,6 +50,15 @@ def to_dev(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(dev)
 
 
+PATHS = {"tiled": 0, "direct": 1}
+
+
+def multi(rt, j, kap, src, rays, ds, c, dt, caps=None, path=0, **kw):
+    """The multi-source field through rtmi_trace_bins with one bin, on the chosen path."""
+    return rt.trace_bins(j, kap, np.asarray(src, np.float32).reshape(-1, 3), rays, ds, c, dt,
+                         substep_cap=caps, path=path, **kw)[0]
+
+
 def test_uniform_blob_parity(rt, dev):
     w = inputs.uniform_blob()
     note("uniform_blob 32^3, 256 rays, 32 substeps")
@@ -60,11 +69,23 @@ def test_uniform_blob_parity(rt, dev):
     assert_parity(got, want)
 
 
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_uniform_blob_parity_both_paths(rt, dev, path):
+    w = inputs.uniform_blob()
+    got = multi(rt, to_dev(w.j_map, dev), to_dev(w.kappa_map, dev), w.source_pos, 256, w.step_size,
+                w.radiation_velocity, w.time_step, path=PATHS[path]).cpu().numpy()
+    want = oracle.trace_single(w.j_map, w.kappa_map, w.source_pos[0], 256, w.step_size,
+                               w.radiation_velocity, w.time_step)
+    assert_parity(got, want)
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("shape,rays,caps", [
     ((40, 40, 40), [1, 100, 257, 300, 777], [0, 13, 0, 40, 7]),
     ((37, 29, 45), [256, 511, 64], [0, 0, 21]),
+    ((17, 33, 50), [129, 64, 65, 1000], [0, 3, 0, 0]),
 ])
-def test_ragged_multi_source_parity(rt, dev, shape, rays, caps):
+def test_ragged_multi_source_parity(rt, dev, shape, rays, caps, path):
     rng = np.random.default_rng(7)
     n_src = len(rays)
     kap = inputs.lognormal_kappa(max(shape), 0.05, 1.0, rng)[:shape[0], :shape[1], :shape[2]].copy()
@@ -72,26 +93,39 @@ def test_ragged_multi_source_parity(rt, dev, shape, rays, caps):
     j = np.zeros(shape, np.float32)
     for ci, c in enumerate(centres):
         j += (inputs.gaussian_blobs(max(shape), [c], [1.5], [1.0 + ci])[:shape[0], :shape[1], :shape[2]])
-    note(f"ragged multi-source {shape} rays={rays} caps={caps}")
-    got = rt.trace_multi(to_dev(j, dev), to_dev(kap, dev), centres, rays, 0.5, 30.0, 1.0,
-                         substep_cap=caps).cpu().numpy()
+    note(f"ragged multi-source {shape} rays={rays} caps={caps} path={path}")
+    got = multi(rt, to_dev(j, dev), to_dev(kap, dev), centres, rays, 0.5, 30.0, 1.0, caps=caps,
+                path=PATHS[path]).cpu().numpy()
     want = oracle.trace_multi(j, kap, centres, rays, 0.5, 30.0, 1.0, caps=caps)
     assert_parity(got, want)
 
 
-def test_turbulent_full_size_parity(rt, dev):
-    """128^3, 16 sources, 4096 rays, 256 substeps: the benchmark workload, full field."""
+@pytest.fixture(scope="module")
+def turbulent_case():
     w = inputs.turbulent()
-    note("turbulent 128^3 x 16 sources x 4096 rays x 256 substeps")
-    got = rt.trace_multi(to_dev(w.j_map, dev), to_dev(w.kappa_map, dev), w.source_pos, w.num_rays,
-                         w.step_size, w.radiation_velocity, w.time_step).cpu().numpy()
     want = oracle.trace_multi(w.j_map, w.kappa_map, w.source_pos, w.num_rays, w.step_size,
                               w.radiation_velocity, w.time_step)
-    err, mx = assert_parity(got, want)
-    note(f"turbulent full: rel L2 {err:.2e}, max per-voxel {mx:.2e}")
+    return w, want
 
 
-def test_uneven_bins_full_grid_subset_parity(rt, dev):
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_turbulent_full_size_parity(rt, dev, turbulent_case, path):
+    """128^3, 16 sources, 4096 rays, 256 substeps: the benchmark workload, full field, in
+    the launch configuration the benchmark times (rtmi_trace_multi) and on each path."""
+    w, want = turbulent_case
+    note(f"turbulent 128^3 x 16 sources x 4096 rays x 256 substeps, path={path}")
+    if path == "tiled":
+        got = rt.trace_multi(to_dev(w.j_map, dev), to_dev(w.kappa_map, dev), w.source_pos,
+                             w.num_rays, w.step_size, w.radiation_velocity, w.time_step)
+    else:
+        got = multi(rt, to_dev(w.j_map, dev), to_dev(w.kappa_map, dev), w.source_pos, w.num_rays,
+                    w.step_size, w.radiation_velocity, w.time_step, path=PATHS[path])
+    err, mx = assert_parity(got.cpu().numpy(), want)
+    note(f"turbulent full ({path}): rel L2 {err:.2e}, max per-voxel {mx:.2e}")
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_uneven_bins_full_grid_subset_parity(rt, dev, path):
     """256^3 with 4 frequency bins and per-source N_Omega / caps; the oracle covers a
     subset of the sources (fields add over sources), chosen to span the N_Omega range."""
     w = inputs.uneven_bins()
@@ -102,30 +136,34 @@ def test_uneven_bins_full_grid_subset_parity(rt, dev):
         picks.append(int(idx[np.argmin(cost[idx])]))
     picks = [p for p in picks if cost[p] <= 2_000_000][:4]
     src, nr, cap = w.source_pos[picks], w.num_rays[picks], w.substep_cap[picks]
-    note(f"uneven bins 256^3, sources {picks} rays {nr.tolist()} caps {cap.tolist()}")
+    note(f"uneven bins 256^3, sources {picks} rays {nr.tolist()} caps {cap.tolist()} path={path}")
     got = rt.trace_bins(to_dev(w.j_map, dev), to_dev(w.kappa_map, dev), src, nr, w.step_size,
                         w.radiation_velocity, w.time_step, kappa_scale=w.kappa_scale,
-                        substep_cap=cap).cpu().numpy()
+                        substep_cap=cap, path=PATHS[path]).cpu().numpy()
     want = oracle.trace_bins(w.j_map, w.kappa_map, w.kappa_scale, src, nr, w.step_size,
                              w.radiation_velocity, w.time_step, caps=cap)
     for b in range(w.n_bins):
-        assert_parity(got[b], want[b])
+        err, mx = assert_parity(got[b], want[b])
+        note(f"  bin {b}: rel L2 {err:.2e}, max per-voxel {mx:.2e}")
 
 
-def test_per_bin_maps_parity(rt, dev):
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_per_bin_maps_parity(rt, dev, path):
     rng = np.random.default_rng(3)
     shape = (20, 22, 18)
     js = rng.random((3,) + shape).astype(np.float32)
     ks = (0.2 * rng.random((3,) + shape)).astype(np.float32)
     src = np.array([[10.2, 11.7, 8.4], [3.0, 20.0, 1.5]], np.float32)
     note("per-bin j and kappa maps, 3 bins")
-    got = rt.trace_bins(to_dev(js, dev), to_dev(ks, dev), src, [300, 129], 0.5, 12.0, 1.0).cpu().numpy()
+    got = rt.trace_bins(to_dev(js, dev), to_dev(ks, dev), src, [300, 129], 0.5, 12.0, 1.0,
+                        path=PATHS[path]).cpu().numpy()
     want = oracle.trace_bins(js, None, None, src, [300, 129], 0.5, 12.0, 1.0, kappa_maps=ks)
     for b in range(3):
         assert_parity(got[b], want[b])
     # shared j with per-bin kappa, and five bins (two launches of bins)
     ks5 = (0.2 * rng.random((5,) + shape)).astype(np.float32)
-    got = rt.trace_bins(to_dev(js[0], dev), to_dev(ks5, dev), src, [64, 64], 0.5, 12.0, 1.0).cpu().numpy()
+    got = rt.trace_bins(to_dev(js[0], dev), to_dev(ks5, dev), src, [64, 64], 0.5, 12.0, 1.0,
+                        path=PATHS[path]).cpu().numpy()
     want = oracle.trace_bins(js[0], None, None, src, [64, 64], 0.5, 12.0, 1.0, kappa_maps=ks5)
     for b in range(5):
         assert_parity(got[b], want[b])
@@ -154,21 +192,24 @@ def test_conservation_on_gpu(rt, dev):
     assert abs(total - want) <= 1e-5 * want
 
 
-def test_deterministic_mode_is_bitwise_repeatable(rt, dev):
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_deterministic_mode_is_bitwise_repeatable(rt, dev, path):
     w = inputs.small_turbulent(n=32, n_src=4, num_rays=700, c=24.0)
     jd, kd = to_dev(w.j_map, dev), to_dev(w.kappa_map, dev)
-    note("deterministic accumulation, 4 sources x 700 rays")
-    a = rt.trace_bins(jd, kd, w.source_pos, 700, 0.5, 24.0, 1.0, deterministic=True)
-    b = rt.trace_bins(jd, kd, w.source_pos, 700, 0.5, 24.0, 1.0, deterministic=True)
+    note(f"deterministic accumulation, 4 sources x 700 rays, path={path}")
+    a = rt.trace_bins(jd, kd, w.source_pos, 700, 0.5, 24.0, 1.0, deterministic=True, path=PATHS[path])
+    b = rt.trace_bins(jd, kd, w.source_pos, 700, 0.5, 24.0, 1.0, deterministic=True, path=PATHS[path])
     assert torch.equal(a, b)
     # the order of the sources does not change a bit
-    c = rt.trace_bins(jd, kd, w.source_pos[::-1].copy(), 700, 0.5, 24.0, 1.0, deterministic=True)
+    c = rt.trace_bins(jd, kd, w.source_pos[::-1].copy(), 700, 0.5, 24.0, 1.0, deterministic=True,
+                      path=PATHS[path])
     assert torch.equal(a, c)
     want = oracle.trace_multi(w.j_map, w.kappa_map, w.source_pos, 700, 0.5, 24.0, 1.0)
     assert_parity(a[0].cpu().numpy(), want)
 
 
-def test_axis_ray_closed_form_on_gpu(rt, dev):
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_axis_ray_closed_form_on_gpu(rt, dev, path):
     """One ray along +x with weight 4 pi: J[s+m] = 4 pi 1.5 j0 ds e^{-kappa m}(1 + cosh(kappa ds))."""
     n = 12
     shape = (n, 5, 6)
@@ -178,7 +219,8 @@ def test_axis_ray_closed_form_on_gpu(rt, dev):
     j[s] = 2.0
     kap = np.full(shape, kap0, np.float32)
     got = rt.trace_bins(to_dev(j, dev), to_dev(kap, dev), np.array([s], np.float32), 1, 0.5, 15.0, 1.0,
-                        directions=[[1.0, 0.0, 0.0]], ray_weight=4.0 * math.pi)[0].cpu().numpy()
+                        directions=[[1.0, 0.0, 0.0]], ray_weight=4.0 * math.pi,
+                        path=PATHS[path])[0].cpu().numpy()
     line = got[:, s[1], s[2]]
     for m in range(1, n - 1 - s[0]):
         want = 4.0 * math.pi * 1.5 * 2.0 * 0.5 * math.exp(-kap0 * m) * (1.0 + math.cosh(kap0 * 0.5))
@@ -186,23 +228,53 @@ def test_axis_ray_closed_form_on_gpu(rt, dev):
     assert np.count_nonzero(got) == n - s[0]
 
 
-def test_edge_cases(rt, dev):
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_edge_cases(rt, dev, path):
     w = inputs.small_turbulent(n=10, n_src=2, num_rays=33, c=6.0)
     jd, kd = to_dev(w.j_map, dev), to_dev(w.kappa_map, dev)
     # zero substeps: the output is overwritten with zeros
-    out = torch.full(w.shape, 7.0, device=dev)
-    rt.trace_single(jd, kd, w.source_pos[0], 33, 0.5, 6.0, 0.0, out=out)
+    out = torch.full((1,) + w.shape, 7.0, device=dev)
+    rt.trace_bins(jd, kd, w.source_pos[:1], 33, 0.5, 6.0, 0.0, out=out, path=PATHS[path])
     assert not out.any()
     # a 1x1x1 grid: every deposit lands on the one voxel
     one = torch.ones((1, 1, 1), device=dev)
-    f = rt.trace_single(one, one * 0.1, (0.0, 0.0, 0.0), 5, 0.5, 2.0, 1.0).item()
+    f = multi(rt, one, one * 0.1, (0.0, 0.0, 0.0), 5, 0.5, 2.0, 1.0, path=PATHS[path]).item()
     want = oracle.trace_single(np.ones((1, 1, 1)), np.full((1, 1, 1), 0.1, np.float32), (0, 0, 0), 5,
                                0.5, 2.0, 1.0).item()
     assert abs(f - want) <= 1e-6 * want
     # a source outside the box, and a single ray
-    for src, nr in [((-5.5, 3.0, 12.25), 64), ((4.0, 4.0, 4.0), 1)]:
-        got = rt.trace_single(jd, kd, src, nr, 0.5, 6.0, 1.0).cpu().numpy()
+    for src, nr in [((-5.5, 3.0, 12.25), 64), ((4.0, 4.0, 4.0), 1), ((-3.0, -4.0, -2.5), 300)]:
+        got = multi(rt, jd, kd, src, nr, 0.5, 6.0, 1.0, path=PATHS[path]).cpu().numpy()
         want = oracle.trace_single(w.j_map, w.kappa_map, src, nr, 0.5, 6.0, 1.0)
+        assert_parity(got, want)
+
+
+def test_long_march_piles_up_on_box_corners(rt, dev):
+    """Rays that leave the box through a corner octant end up clamped onto the corner voxel
+    for the rest of the march; those samples take the record kernel's per-corner sums."""
+    rng = np.random.default_rng(9)
+    shape = (12, 10, 14)
+    j = rng.random(shape).astype(np.float32)
+    kap = (0.02 * rng.random(shape)).astype(np.float32)
+    src = np.array([[1.5, 1.5, 1.5], [10.0, 8.5, 12.0], [6.0, 0.2, 13.0]], np.float32)
+    got = multi(rt, to_dev(j, dev), to_dev(kap, dev), src, [500, 257, 64], 0.5, 60.0, 1.0).cpu().numpy()
+    want = oracle.trace_multi(j, kap, src, [500, 257, 64], 0.5, 60.0, 1.0)
+    assert_parity(got, want)
+    corners = [want[x, y, z] for x in (0, -1) for y in (0, -1) for z in (0, -1)]
+    assert max(corners) > 0.05 * want.sum()   # the corner pile-up really is exercised
+
+
+def test_many_sources_span_launches(rt, dev):
+    """More sources than one launch describes: later launches add into the field."""
+    rng = np.random.default_rng(11)
+    shape = (20, 20, 20)
+    j = rng.random(shape).astype(np.float32)
+    kap = (0.1 * rng.random(shape)).astype(np.float32)
+    src = rng.uniform(0, 19, size=(70, 3)).astype(np.float32)
+    rays = rng.integers(1, 90, size=70)
+    for path in PATHS.values():
+        got = multi(rt, to_dev(j, dev), to_dev(kap, dev), src, rays, 0.5, 10.0, 1.0, path=path).cpu().numpy()
+        want = oracle.trace_multi(j, kap, src, rays, 0.5, 10.0, 1.0)
         assert_parity(got, want)
 
 
