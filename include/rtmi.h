@@ -74,6 +74,11 @@ typedef struct rtmi_options {
   const float* directions;
   float ray_weight;         /* weight per ray with explicit directions; <= 0: 4 pi/num_rays */
   int32_t path;             /* RTMI_PATH_TILED (default) or RTMI_PATH_DIRECT */
+  /* Tiled path: work-groups sharing one 16^3 output tile, each taking every parts-th
+   * (source, ray patch) pair and adding its share atomically, 1..8; 0 picks a value from
+   * the tile count and the device's compute units. Changes the speed, not the field (in
+   * the deterministic mode, not a bit of it). Ignored by the direct path. */
+  int32_t tile_parts;
 } rtmi_options;
 
 /* Execution paths (rtmi_options.path). Both compute the same field.

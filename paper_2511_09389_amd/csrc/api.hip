@@ -149,20 +149,49 @@ HostTable build_table(const std::vector<float>& xyz) {
     t.dirs[lane] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], w);
   }
   const size_t np = (n + kPatch - 1) / kPatch;
-  t.bounds.assign(np * 8, 0.0f);
+  t.bounds.assign(np * rtmi::kPatchRec, 0.0f);
   for (size_t p = 0; p < np; ++p) {
+    float* rec = &t.bounds[p * rtmi::kPatchRec];
+    const size_t l0 = p * kPatch, l1 = std::min(n, (p + 1) * kPatch);
     float lo[3] = {2.f, 2.f, 2.f}, hi[3] = {-2.f, -2.f, -2.f};
-    for (size_t lane = p * kPatch; lane < std::min(n, (p + 1) * kPatch); ++lane) {
+    double axis[3] = {0.0, 0.0, 0.0};
+    for (size_t lane = l0; lane < l1; ++lane) {
       const float c[3] = {t.dirs[lane].x, t.dirs[lane].y, t.dirs[lane].z};
       for (int a = 0; a < 3; ++a) {
         lo[a] = std::min(lo[a], c[a]);
         hi[a] = std::max(hi[a], c[a]);
+        axis[a] += c[a];
       }
     }
-    for (int a = 0; a < 3; ++a) {
-      t.bounds[p * 8 + a] = lo[a];
-      t.bounds[p * 8 + 3 + a] = hi[a];
+    // cone around the mean direction that holds every ray of the patch (a whole-sphere
+    // cone when the patch's mean direction degenerates)
+    const double len = std::sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+    double cos_b = -1.0;
+    if (len > 1e-9) {
+      for (int a = 0; a < 3; ++a) axis[a] /= len;
+      cos_b = 1.0;
+      for (size_t lane = l0; lane < l1; ++lane) {
+        const double dn = std::sqrt(double(t.dirs[lane].x) * t.dirs[lane].x +
+                                    double(t.dirs[lane].y) * t.dirs[lane].y +
+                                    double(t.dirs[lane].z) * t.dirs[lane].z);
+        const double c = (axis[0] * t.dirs[lane].x + axis[1] * t.dirs[lane].y + axis[2] * t.dirs[lane].z) / dn;
+        cos_b = std::min(cos_b, c);
+      }
+      // widen by 2e-3 rad: the kernel compares binary32 cosines, whose rounding near 1
+      // is worth a few 1e-4 rad of angle
+      const double b = std::acos(std::max(-1.0, std::min(1.0, cos_b))) + 2e-3;
+      cos_b = b >= 3.14159265358979323846 ? -1.0 : std::cos(b);
+    } else {
+      axis[0] = 1.0;
+      axis[1] = axis[2] = 0.0;
     }
+    for (int a = 0; a < 3; ++a) {
+      rec[a] = lo[a];
+      rec[3 + a] = hi[a];
+      rec[8 + a] = static_cast<float>(axis[a]);
+    }
+    rec[11] = static_cast<float>(cos_b);
+    rec[12] = static_cast<float>(std::sqrt(std::max(0.0, 1.0 - cos_b * cos_b)));
   }
   return t;
 }
@@ -321,6 +350,7 @@ struct Plan {
   bool det = false;
   bool tiled = true;
   bool explicit_dirs = false;
+  int32_t tile_parts = 0;   // 0: automatic
   std::vector<int32_t> nsub;
   std::vector<DevTable> tables;
   double bound_per_unit_j = 0.0;
@@ -350,6 +380,9 @@ int32_t validate(const Problem& p, Plan* plan) {
     plan->det = p.opts->accum_mode == RTMI_ACCUM_DETERMINISTIC;
     plan->tiled = p.opts->path == RTMI_PATH_TILED;
     plan->explicit_dirs = p.opts->directions != nullptr;
+    if (p.opts->tile_parts < 0 || p.opts->tile_parts > 8)
+      return fail(RTMI_ERR_INVALID_ARG, "tile_parts must be in [0, 8] (got %d)", p.opts->tile_parts);
+    plan->tile_parts = p.opts->tile_parts;
     if (plan->explicit_dirs && p.opts->ray_weight > 0.0f && !std::isfinite(p.opts->ray_weight))
       return fail(RTMI_ERR_NONFINITE, "ray_weight is not finite");
   }
@@ -379,6 +412,18 @@ float ray_weight(const Problem& p, const Plan& plan, int32_t s) {
   const double w = (plan.explicit_dirs && p.opts->ray_weight > 0.0f) ? double(p.opts->ray_weight)
                                                                      : kFourPi / p.nrays[s];
   return static_cast<float>(w);
+}
+
+// Work-groups per output tile: enough that a few heavy tiles (next to sources, on the box
+// edges) do not leave most of the device idle at the end, for grids with few tiles.
+int tile_parts(int tiles) {
+  int dev = 0, cus = 256;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
+  }
+  int parts = (8 * cus + tiles - 1) / tiles;
+  return std::max(1, std::min(8, parts));
 }
 
 int64_t row_stride(int32_t nsub) { return (int64_t(nsub) + kRowAlign - 1) / kRowAlign * kRowAlign; }
@@ -415,6 +460,13 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
   const int tiles_x = (p.nx + kTile - 1) / kTile, tiles_y = (p.ny + kTile - 1) / kTile,
             tiles_z = (p.nz + kTile - 1) / kTile;
   const int tiles = tiles_x * tiles_y * tiles_z;
+  const int parts = plan.tile_parts > 0 ? plan.tile_parts : tile_parts(tiles);
+  if (parts > 1) {   // the parts of a tile add into a zeroed field
+    const int64_t total = plan.cells * p.n_bins;
+    if (plan.det) e = rtmi::launch_fill_zero_u64(out_q, total, st);
+    else e = rtmi::launch_fill_zero(p.out, total, st);
+    if (e != hipSuccess) return hip_fail(e, "fill");
+  }
 
   for (int32_t b0 = 0; b0 < p.n_bins; b0 += kMaxBinsPerLaunch) {
     const int32_t nb = std::min(kMaxBinsPerLaunch, p.n_bins - b0);
@@ -473,6 +525,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       t.tiles_y = tiles_y;
       t.tiles_z = tiles_z;
       t.accumulate = s0 > 0 ? 1 : 0;
+      t.parts = parts;
 
       if ((e = rtmi::launch_fill_zero(corner, 2 * corner_bytes / sizeof(float), st)) != hipSuccess)
         return hip_fail(e, "fill");
@@ -485,7 +538,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       }
       TimedLaunch tl;
       if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl)) != hipSuccess) return hip_fail(e, "timing");
-      if ((e = rtmi::launch_tile(t, nb, plan.det, false, tiles, st)) != hipSuccess)
+      if ((e = rtmi::launch_tile(t, nb, plan.det, false, tiles * parts, st)) != hipSuccess)
         return hip_fail(e, "tile launch");
       if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
     }
@@ -692,6 +745,7 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
     t.tiles_y = tiles_y;
     t.tiles_z = tiles_z;
     t.accumulate = s0 > 0 ? 1 : 0;
+    t.parts = 1;
     if ((e = rtmi::launch_fill_zero(corner, 64, st)) != hipSuccess) return hip_fail(e, "fill");
     if (blocks > 0 && (e = rtmi::launch_adjoint_record(r, blocks, st)) != hipSuccess)
       return hip_fail(e, "adjoint launch");

@@ -15,6 +15,9 @@ constexpr int kTileVox = kTile * kTile * kTile;
 constexpr int kTileThreads = 1024;   // lanes per tile work-group
 constexpr int kChunk = 8;            // consecutive substeps one tile lane sums in registers
 constexpr int kSeg = 4;              // substeps per recomputed segment of the adjoint sweep
+// Per-patch record of the direction table: min x, y, z, max x, y, z, -, -, cone axis
+// x, y, z, cos and sin of the cone's half-angle, -, -, -.
+constexpr int kPatchRec = 16;
 constexpr int kRowAlign = 8;         // workspace rows are padded to this many substeps
 constexpr int kXcds = 8;             // accelerator complex dies; work-groups go round-robin
 
@@ -82,6 +85,8 @@ struct TileArgs {
   float ds;
   int n_src;
   int accumulate;             // 0: store the tile; 1: add to the field already there
+  int parts;                  // work-groups per tile; > 1: each adds its share atomically
+                              // into a field the caller zeroed
   int pbegin[kMaxSrcPerLaunch + 1];  // prefix sums of patch counts over sources
   float sx[kMaxSrcPerLaunch], sy[kMaxSrcPerLaunch], sz[kMaxSrcPerLaunch];
   int nrays[kMaxSrcPerLaunch];
@@ -89,7 +94,7 @@ struct TileArgs {
   int vstride[kMaxSrcPerLaunch];
   long long vbase[kMaxSrcPerLaunch];
   const float4* dirs[kMaxSrcPerLaunch];
-  const float* pbounds[kMaxSrcPerLaunch];  // per patch: min x, y, z, max x, y, z, -, -
+  const float* pbounds[kMaxSrcPerLaunch];  // per patch: kPatchRec floats (bounds and cone)
 };
 
 // Adjoint of the march: per-ray reverse sweep with checkpointed recomputation.

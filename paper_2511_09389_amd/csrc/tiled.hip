@@ -244,33 +244,28 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
   }
 }
 
-// Interval of t with s + t n in [lo, hi); empty when t0 > t1.
-__device__ __forceinline__ void axis_span(float s, float n, float lo, float hi, float& t0,
-                                          float& t1) {
+// Interval of t with s + t n in [lo, hi), from inv = 1/n (approximate reciprocal; the
+// callers' margins cover its error); empty when t0 > t1.
+__device__ __forceinline__ void axis_span(float s, float n, float inv, float lo, float hi,
+                                          float& t0, float& t1) {
   if (n == 0.0f) {
     const bool in = s >= lo && s < hi;
     t0 = in ? -kBig : 1.0f;
     t1 = in ? kBig : 0.0f;
   } else {
-    const float ta = (lo - s) / n, tb = (hi - s) / n;
+    const float ta = (lo - s) * inv, tb = (hi - s) * inv;
     t0 = fminf(ta, tb);
     t1 = fmaxf(ta, tb);
   }
 }
 
-// Substep interval of a ray that can reach [lo, hi) along one axis.
-__device__ __forceinline__ void clip_axis(float s, float n, float lo, float hi, float& t0,
-                                          float& t1) {
-  if (n == 0.0f) {
-    if (!(s >= lo && s < hi)) {
-      t0 = 1.0f;
-      t1 = 0.0f;
-    }
-  } else {
-    const float ta = (lo - s) / n, tb = (hi - s) / n;
-    t0 = fmaxf(t0, fminf(ta, tb));
-    t1 = fminf(t1, fmaxf(ta, tb));
-  }
+// Narrow [t0, t1] to the t where a ray can reach [lo, hi) along one axis.
+__device__ __forceinline__ void clip_axis(float s, float n, float inv, float lo, float hi,
+                                          float& t0, float& t1) {
+  float u0, u1;
+  axis_span(s, n, inv, lo, hi, u0, u1);
+  t0 = fmaxf(t0, u0);
+  t1 = fminf(t1, u1);
 }
 
 // Per-lane 2x2x2 window over a ray's consecutive samples inside one tile: the deposits of
@@ -366,10 +361,10 @@ struct TileWindow {
 // that length drift by more than the binary32 field is allowed to differ from the exact one.
 // NEAREST: each sample adds its value to its nearest voxel only (the adjoint's kappa
 // deposit) instead of the trilinear stencil.
-// Lanes per tile work-group: 1024, or 512 when three or four bins' windows would not fit
+// Lanes per tile work-group: 1024, or 512 when several bins. windows would not fit
 // in the registers 1024 lanes leave per lane.
 template <int NB>
-constexpr int tile_threads() { return NB <= 2 ? kTileThreads : kTileThreads / 2; }
+constexpr int tile_threads() { return NB == 1 ? kTileThreads : kTileThreads / 2; }
 
 template <int NB, bool DET, bool NEAREST>
 __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs a) {
@@ -379,7 +374,9 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
   constexpr int kThreads = tile_threads<NB>();
   for (int i = tid; i < NB * kTileVox; i += kThreads) (&acc[0][0])[i] = T(0);
 
-  const int t = blockIdx.x;
+  // work-group -> (tile, part): part q of a tile takes the pairs with index = q mod parts
+  const int t = static_cast<int>(blockIdx.x) / a.parts;
+  const int part = static_cast<int>(blockIdx.x) % a.parts;
   const int tz = t % a.tiles_z, ty = (t / a.tiles_z) % a.tiles_y, tx = t / (a.tiles_z * a.tiles_y);
   const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
   const int ex = min(kTile, a.nx - x0), ey = min(kTile, a.ny - y0), ez = min(kTile, a.nz - z0);
@@ -394,196 +391,252 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
   const float ds = a.ds;
   double det_scale = 0.0;
   if constexpr (DET) det_scale = *a.det_scale;
-  __syncthreads();
-
   const int wave = tid >> 6, lane = tid & 63;
   constexpr int kWaves = kThreads / 64;
-  // Per-wave staging of one patch's rays: exclusive prefix of their chunk counts, substep
-  // range and direction. A chunk is the part of one ray's range inside one aligned block
-  // of kChunk substeps, so the patch's work can be dealt out 64 chunks at a time and each
-  // chunk's recorded values arrive in two aligned 16-byte loads.
-  __shared__ int w_excl[kWaves][kPatch + 1];
-  __shared__ int w_k0[kWaves][kPatch];
-  __shared__ int w_k1[kWaves][kPatch];
-  __shared__ float4 w_dir[kWaves][kPatch];
+  // Records of one batch: record r holds ray (r mod 64) of the pair taken by wave r / 64,
+  // with its substep range, direction and the exclusive prefix of the chunk counts. A
+  // chunk is the part of one ray's range inside one aligned block of kChunk substeps, so
+  // its recorded values arrive in aligned 16-byte loads.
+  __shared__ int r_excl[kThreads + 1];
+  __shared__ int r_k0[kThreads];
+  __shared__ int r_k1[kThreads];
+  __shared__ float4 r_dir[kThreads];
+  __shared__ int w_tot[kWaves];
+  __shared__ float4 b_src[kWaves];        // source position of each wave's pair
+  __shared__ long long b_row[kWaves];     // workspace offset of the pair's first ray
+  __shared__ int b_vstride[kWaves];
   const int npairs = a.pbegin[a.n_src];
-  // (source, patch) pairs are handed out one at a time: the pairs that reach a tile come
-  // in clusters, and a static deal leaves most waves idle at the final barrier.
-  __shared__ int next_pair;
-  if (tid == 0) next_pair = 0;
-  __syncthreads();
-  for (;;) {
-    int p = 0;
-    if (lane == 0) p = atomicAdd(&next_pair, 1);
-    p = __shfl(p, 0, 64);
-    if (p >= npairs) break;
-    int s = 0;
-    while (s + 1 < a.n_src && p >= a.pbegin[s + 1]) ++s;
-    const int patch = p - a.pbegin[s];
-    const int nsub = a.nsub[s];
-    const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
-    const float tmax = sample_distance(nsub - 1, ds);
-    // Position-space margin above the rounding of any binary32 sample point of this
-    // source (a few ulps of the largest coordinate involved).
-    const float m = 5.0e-7f * (fmaxf(fabsf(sx), fmaxf(fabsf(sy), fabsf(sz))) + tmax + 2.0f) + 1.0e-6f;
-    // bounding box of the patch's ray segments [0, tmax] (direction bounds are exact)
-    const float* pb = a.pbounds[s] + patch * 8;
-    if (sx + fmaxf(0.0f, tmax * pb[3]) + m < Ax || sx + fminf(0.0f, tmax * pb[0]) - m >= Bx ||
-        sy + fmaxf(0.0f, tmax * pb[4]) + m < Ay || sy + fminf(0.0f, tmax * pb[1]) - m >= By ||
-        sz + fmaxf(0.0f, tmax * pb[5]) + m < Az || sz + fminf(0.0f, tmax * pb[2]) - m >= Bz)
-      continue;
-
-    // this lane's ray: the substep range that can reach the tile
-    const int ray = patch * kPatch + lane;
-    int ka = 0, kb = -1;
-    float4 d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (ray < a.nrays[s]) {
-      d = a.dirs[s][ray];
-      float t0 = 0.0f, t1 = tmax;
-      clip_axis(sx, d.x, Ax - m, Bx + m, t0, t1);
-      clip_axis(sy, d.y, Ay - m, By + m, t0, t1);
-      clip_axis(sz, d.z, Az - m, Bz + m, t0, t1);
-      // Samples collapsed onto a corner voxel (clamped along all three axes) belong to the
-      // record phase. Along a straight ray each axis is unclamped on one interval of t;
-      // only the hull of those intervals can hold samples for this kernel.
-      float h0 = kBig, h1 = -kBig, u0, u1;
-      if (nx > 1) {
-        axis_span(sx, d.x, -m, static_cast<float>(nx - 1) + m, u0, u1);
-        if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
-      }
-      if (ny > 1) {
-        axis_span(sy, d.y, -m, static_cast<float>(ny - 1) + m, u0, u1);
-        if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
-      }
-      if (nz > 1) {
-        axis_span(sz, d.z, -m, static_cast<float>(nz - 1) + m, u0, u1);
-        if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
-      }
-      t0 = fmaxf(t0, h0);
-      t1 = fminf(t1, h1);
-      if (t0 <= t1) {
-        // one substep of margin on each side covers the rounding of t = k ds
-        ka = max(0, static_cast<int>(floorf(t0 / ds)) - 1);
-        kb = min(nsub - 1, static_cast<int>(fminf(ceilf(t1 / ds), 1.0e8f)) + 1);
-      }
-    }
-    const int chunks = kb >= ka ? kb / kChunk - ka / kChunk + 1 : 0;
-    // inclusive prefix sum of the chunk counts across the wavefront
-    int incl = chunks;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int o = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += o;
-    }
-    const int total = __shfl(incl, 63, 64);
-    if (total == 0) continue;
-    w_excl[wave][lane + 1] = incl;
-    if (lane == 0) w_excl[wave][0] = 0;
-    w_k0[wave][lane] = ka;
-    w_k1[wave][lane] = kb;
-    w_dir[wave][lane] = d;
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-
-    const long long row0 = a.vbase[s] + static_cast<long long>(patch) * kPatch * a.vstride[s];
-    for (int base = 0; base < total; base += 64) {
-      const int i = base + lane;
-      if (i >= total) continue;
-      // owner lane o: w_excl[o] <= i < w_excl[o + 1]
-      int lo = 0, hi = 64;
-      while (hi - lo > 1) {
-        const int mid = (lo + hi) >> 1;
-        if (w_excl[wave][mid] <= i) lo = mid;
-        else hi = mid;
-      }
-      const int o = lo;
-      const int ka_o = w_k0[wave][o], kb_o = w_k1[wave][o];
-      const int kblk = (ka_o / kChunk + (i - w_excl[wave][o])) * kChunk;
-      const int kbeg = max(ka_o, kblk), kend = min(kb_o, kblk + kChunk - 1);
-      const float4 dd = w_dir[wave][o];
-      const bool up[3] = {dd.x >= 0.0f, dd.y >= 0.0f, dd.z >= 0.0f};
-      const float* vrow = a.V + row0 + static_cast<long long>(o) * a.vstride[s];
-      // the chunk's recorded values, fetched before any of them is needed
-      float vv[NB][kChunk];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const float4* src4 = reinterpret_cast<const float4*>(vrow + b * a.v_bin_stride + kblk);
-#pragma unroll
-        for (int q = 0; q < kChunk / 4; ++q) {
-          const float4 f = src4[q];
-          vv[b][4 * q] = f.x;
-          vv[b][4 * q + 1] = f.y;
-          vv[b][4 * q + 2] = f.z;
-          vv[b][4 * q + 3] = f.w;
+  // Tile-interior test for the cone cull: the tile widened by the stencil, as a sphere.
+  const bool interior = x0 > 0 && y0 > 0 && z0 > 0 && x0 + ex < nx && y0 + ey < ny && z0 + ez < nz;
+  const float tcx = static_cast<float>(x0) - 1.0f + 0.5f * static_cast<float>(ex + 1);
+  const float tcy = static_cast<float>(y0) - 1.0f + 0.5f * static_cast<float>(ey + 1);
+  const float tcz = static_cast<float>(z0) - 1.0f + 0.5f * static_cast<float>(ez + 1);
+  const float trad = 0.5f * sqrtf(static_cast<float>((ex + 1) * (ex + 1) + (ey + 1) * (ey + 1) +
+                                                     (ez + 1) * (ez + 1))) + 0.01f;
+  // (source, patch) pairs are culled by the whole work-group, a block at a time; the pairs
+  // that may reach the tile go to a list that is then expanded in batches.
+  __shared__ int pair_list[kThreads];
+  __shared__ int pair_count;
+  for (int blk0 = 0; blk0 < npairs; blk0 += kThreads) {
+    if (tid == 0) pair_count = 0;
+    __syncthreads();
+    {
+      const int p = blk0 + tid;
+      if (p < npairs && p % a.parts == part) {
+        int lo = 0, hi = a.n_src;   // source s: pbegin[s] <= p < pbegin[s + 1]
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (a.pbegin[mid] <= p) lo = mid;
+          else hi = mid;
         }
-      }
-      TileWindow<NB> win(x0, y0, z0, ex, ey, ez, det_scale);
-      int near_li = -1;         // NEAREST: voxel of the running sum, -1 when empty
-      float near_acc[NB];
-#pragma unroll
-      for (int b = 0; b < NB; ++b) near_acc[b] = 0.0f;
-#pragma unroll
-      for (int t = 0; t < kChunk; ++t) {
-        const int k = kblk + t;
-        if (k < kbeg || k > kend) continue;
-        const float dist = sample_distance(k, ds);
-        const float x = sample_axis(sx, dist, dd.x);
-        const float y = sample_axis(sy, dist, dd.y);
-        const float z = sample_axis(sz, dist, dd.z);
-        // collapsed onto one corner voxel: summed by the record phase
-        if (axis_clamped(x, nx) && axis_clamped(y, ny) && axis_clamped(z, nz)) continue;
-        const Axis X = axis_stencil(x, nx);
-        const Axis Y = axis_stencil(y, ny);
-        const Axis Z = axis_stencil(z, nz);
-        if constexpr (NEAREST) {
-          const int lx = X.nearest - x0, ly = Y.nearest - y0, lz = Z.nearest - z0;
-          if (lx < 0 || lx >= ex || ly < 0 || ly >= ey || lz < 0 || lz >= ez) continue;
-          const int li = (lx * kTile + ly) * kTile + lz;
-          if (li != near_li) {
-            if (near_li >= 0) {
-#pragma unroll
-              for (int b = 0; b < NB; ++b)
-                if (near_acc[b] != 0.0f) atomicAdd(&acc[b][near_li], tile_value<T>(near_acc[b], det_scale));
+        const int s = lo;
+        const int patch = p - a.pbegin[s];
+        const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
+        const float tmax = sample_distance(a.nsub[s] - 1, ds);
+        const float m = 5.0e-7f * (fmaxf(fabsf(sx), fmaxf(fabsf(sy), fabsf(sz))) + tmax + 2.0f) + 1.0e-6f;
+        const float* pb = a.pbounds[s] + patch * kPatchRec;
+        // bounding box of the patch's ray segments [0, tmax] (direction bounds are exact)
+        bool reach = !(sx + fmaxf(0.0f, tmax * pb[3]) + m < Ax || sx + fminf(0.0f, tmax * pb[0]) - m >= Bx ||
+                       sy + fmaxf(0.0f, tmax * pb[4]) + m < Ay || sy + fminf(0.0f, tmax * pb[1]) - m >= By ||
+                       sz + fmaxf(0.0f, tmax * pb[5]) + m < Az || sz + fminf(0.0f, tmax * pb[2]) - m >= Bz);
+        if (reach && interior) {
+          // cone of the patch's directions against the sphere around the widened tile
+          const float vx = tcx - sx, vy = tcy - sy, vz = tcz - sz;
+          const float dist = sqrtf(vx * vx + vy * vy + vz * vz);
+          const float rad = trad + m;
+          if (dist - rad > tmax + 1.0f) {
+            reach = false;
+          } else if (dist > rad) {
+            const float beta = acosf(fminf(1.0f, fmaxf(-1.0f, pb[11])));
+            const float alpha = asinf(fminf(1.0f, rad / dist));
+            if (beta + alpha < 3.1f) {
+              const float c = (pb[8] * vx + pb[9] * vy + pb[10] * vz) / dist;
+              reach = c >= cosf(beta + alpha) - 1.0e-3f;
             }
-            near_li = li;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) near_acc[b] = 0.0f;
-          }
-#pragma unroll
-          for (int b = 0; b < NB; ++b) near_acc[b] += vv[b][t];
-        } else {
-          // no corner of this sample inside the tile: nothing to add
-          if (X.hi < x0 || X.lo >= x0 + ex || Y.hi < y0 || Y.lo >= y0 + ey || Z.hi < z0 ||
-              Z.lo >= z0 + ez)
-            continue;
-          win.template advance<0>(X.lo, X.hi, up[0], acc);
-          win.template advance<1>(Y.lo, Y.hi, up[1], acc);
-          win.template advance<2>(Z.lo, Z.hi, up[2], acc);
-          // an axis whose two corners coincide carries its whole weight on the lower one
-          const float wx[2] = {X.lo == X.hi ? 1.0f : X.w0, X.lo == X.hi ? 0.0f : X.w1};
-          const float wy[2] = {Y.lo == Y.hi ? 1.0f : Y.w0, Y.lo == Y.hi ? 0.0f : Y.w1};
-          const float wz[2] = {Z.lo == Z.hi ? 1.0f : Z.w0, Z.lo == Z.hi ? 0.0f : Z.w1};
-#pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            const float v = vv[b][t];
-#pragma unroll
-            for (int c = 0; c < 8; ++c)
-              win.acc[b][c] += v * ((wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1]);
           }
         }
+        if (reach) pair_list[atomicAdd(&pair_count, 1)] = p;
       }
-      if constexpr (NEAREST) {
-        if (near_li >= 0) {
-#pragma unroll
-          for (int b = 0; b < NB; ++b)
-            if (near_acc[b] != 0.0f) atomicAdd(&acc[b][near_li], tile_value<T>(near_acc[b], det_scale));
-        }
-      }
-      win.flush_all(acc);
     }
-    // the staging arrays are rewritten for the next patch only after every lane is done
-    __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    __syncthreads();
+    const int n_items = pair_count;
+    // The listed pairs are expanded kWaves at a time: each wave turns one pair's 64 rays
+    // into records (substep range, direction), a work-group-wide prefix sum over the
+    // records' chunk counts follows, and then every lane takes chunks of any record, so
+    // a heavy pair is shared by the whole work-group instead of one wavefront.
+    for (int b0 = 0; b0 < n_items; b0 += kWaves) {
+      const int it = b0 + wave;
+      int ka = 0, kb = -1;
+      float4 d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+      if (it < n_items) {
+        const int p = pair_list[it];
+        int s = 0;
+        while (s + 1 < a.n_src && p >= a.pbegin[s + 1]) ++s;
+        const int patch = p - a.pbegin[s];
+        const int nsub = a.nsub[s];
+        const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
+        const float tmax = sample_distance(nsub - 1, ds);
+        const float m = 5.0e-7f * (fmaxf(fabsf(sx), fmaxf(fabsf(sy), fabsf(sz))) + tmax + 2.0f) + 1.0e-6f;
+        if (lane == 0) {
+          b_src[wave] = make_float4(sx, sy, sz, 0.0f);
+          b_row[wave] = a.vbase[s] + static_cast<long long>(patch) * kPatch * a.vstride[s];
+          b_vstride[wave] = a.vstride[s];
+        }
+        // this lane's ray: the substep range that can reach the tile
+        const int ray = patch * kPatch + lane;
+        if (ray < a.nrays[s]) {
+          d = a.dirs[s][ray];
+          const float ix = __builtin_amdgcn_rcpf(d.x), iy = __builtin_amdgcn_rcpf(d.y),
+                      iz = __builtin_amdgcn_rcpf(d.z);
+          float t0 = 0.0f, t1 = tmax;
+          clip_axis(sx, d.x, ix, Ax - m, Bx + m, t0, t1);
+          clip_axis(sy, d.y, iy, Ay - m, By + m, t0, t1);
+          clip_axis(sz, d.z, iz, Az - m, Bz + m, t0, t1);
+          // Samples collapsed onto a corner voxel (clamped along all three axes) belong to
+          // the record phase. Along a straight ray each axis is unclamped on one interval
+          // of t; only the hull of those intervals can hold samples for this kernel.
+          float h0 = kBig, h1 = -kBig, u0, u1;
+          if (nx > 1) {
+            axis_span(sx, d.x, ix, -m, static_cast<float>(nx - 1) + m, u0, u1);
+            if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
+          }
+          if (ny > 1) {
+            axis_span(sy, d.y, iy, -m, static_cast<float>(ny - 1) + m, u0, u1);
+            if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
+          }
+          if (nz > 1) {
+            axis_span(sz, d.z, iz, -m, static_cast<float>(nz - 1) + m, u0, u1);
+            if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
+          }
+          t0 = fmaxf(t0, h0);
+          t1 = fminf(t1, h1);
+          if (t0 <= t1) {
+            // one substep of margin on each side covers the rounding of t = k ds
+            ka = max(0, static_cast<int>(floorf(t0 / ds)) - 1);
+            kb = min(nsub - 1, static_cast<int>(fminf(ceilf(t1 / ds), 1.0e8f)) + 1);
+          }
+        }
+      }
+      const int chunks = kb >= ka ? kb / kChunk - ka / kChunk + 1 : 0;
+      // inclusive prefix sum of the chunk counts across the wavefront
+      int incl = chunks;
+#pragma unroll
+      for (int off = 1; off < 64; off <<= 1) {
+        const int o = __shfl_up(incl, off, 64);
+        if (lane >= off) incl += o;
+      }
+      if (lane == 63) w_tot[wave] = incl;
+      r_k0[tid] = ka;
+      r_k1[tid] = kb;
+      r_dir[tid] = d;
+      __syncthreads();
+      int off = 0, total = 0;
+#pragma unroll
+      for (int w = 0; w < kWaves; ++w) {
+        const int v = w_tot[w];
+        off += w < wave ? v : 0;
+        total += v;
+      }
+      r_excl[tid + 1] = off + incl;
+      if (tid == 0) r_excl[0] = 0;
+      __syncthreads();
+
+      for (int i = tid; i < total; i += kThreads) {
+        // owner record o: r_excl[o] <= i < r_excl[o + 1]
+        int lo = 0, hi = kThreads;
+        while (hi - lo > 1) {
+          const int mid = (lo + hi) >> 1;
+          if (r_excl[mid] <= i) lo = mid;
+          else hi = mid;
+        }
+        const int o = lo, ow = o >> 6;
+        const int ka_o = r_k0[o], kb_o = r_k1[o];
+        const int kblk = (ka_o / kChunk + (i - r_excl[o])) * kChunk;
+        const int kbeg = max(ka_o, kblk), kend = min(kb_o, kblk + kChunk - 1);
+        const float4 dd = r_dir[o];
+        const float4 src = b_src[ow];
+        const bool up[3] = {dd.x >= 0.0f, dd.y >= 0.0f, dd.z >= 0.0f};
+        const float* vrow = a.V + b_row[ow] + static_cast<long long>(o & 63) * b_vstride[ow];
+        // the chunk's recorded values, fetched before any of them is needed
+        float vv[NB][kChunk];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+          const float4* src4 = reinterpret_cast<const float4*>(vrow + b * a.v_bin_stride + kblk);
+#pragma unroll
+          for (int q = 0; q < kChunk / 4; ++q) {
+            const float4 f = src4[q];
+            vv[b][4 * q] = f.x;
+            vv[b][4 * q + 1] = f.y;
+            vv[b][4 * q + 2] = f.z;
+            vv[b][4 * q + 3] = f.w;
+          }
+        }
+        TileWindow<NB> win(x0, y0, z0, ex, ey, ez, det_scale);
+        int near_li = -1;         // NEAREST: voxel of the running sum, -1 when empty
+        float near_acc[NB];
+#pragma unroll
+        for (int b = 0; b < NB; ++b) near_acc[b] = 0.0f;
+#pragma unroll
+        for (int t = 0; t < kChunk; ++t) {
+          const int k = kblk + t;
+          if (k < kbeg || k > kend) continue;
+          const float dist = sample_distance(k, ds);
+          const float x = sample_axis(src.x, dist, dd.x);
+          const float y = sample_axis(src.y, dist, dd.y);
+          const float z = sample_axis(src.z, dist, dd.z);
+          // collapsed onto one corner voxel: summed by the record phase
+          if (axis_clamped(x, nx) && axis_clamped(y, ny) && axis_clamped(z, nz)) continue;
+          const Axis X = axis_stencil(x, nx);
+          const Axis Y = axis_stencil(y, ny);
+          const Axis Z = axis_stencil(z, nz);
+          if constexpr (NEAREST) {
+            const int lx = X.nearest - x0, ly = Y.nearest - y0, lz = Z.nearest - z0;
+            if (lx < 0 || lx >= ex || ly < 0 || ly >= ey || lz < 0 || lz >= ez) continue;
+            const int li = (lx * kTile + ly) * kTile + lz;
+            if (li != near_li) {
+              if (near_li >= 0) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b)
+                  if (near_acc[b] != 0.0f) atomicAdd(&acc[b][near_li], tile_value<T>(near_acc[b], det_scale));
+              }
+              near_li = li;
+#pragma unroll
+              for (int b = 0; b < NB; ++b) near_acc[b] = 0.0f;
+            }
+#pragma unroll
+            for (int b = 0; b < NB; ++b) near_acc[b] += vv[b][t];
+          } else {
+            // no corner of this sample inside the tile: nothing to add
+            if (X.hi < x0 || X.lo >= x0 + ex || Y.hi < y0 || Y.lo >= y0 + ey || Z.hi < z0 ||
+                Z.lo >= z0 + ez)
+              continue;
+            win.template advance<0>(X.lo, X.hi, up[0], acc);
+            win.template advance<1>(Y.lo, Y.hi, up[1], acc);
+            win.template advance<2>(Z.lo, Z.hi, up[2], acc);
+            // an axis whose two corners coincide carries its whole weight on the lower one
+            const float wx[2] = {X.lo == X.hi ? 1.0f : X.w0, X.lo == X.hi ? 0.0f : X.w1};
+            const float wy[2] = {Y.lo == Y.hi ? 1.0f : Y.w0, Y.lo == Y.hi ? 0.0f : Y.w1};
+            const float wz[2] = {Z.lo == Z.hi ? 1.0f : Z.w0, Z.lo == Z.hi ? 0.0f : Z.w1};
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+              const float v = vv[b][t];
+#pragma unroll
+              for (int c = 0; c < 8; ++c)
+                win.acc[b][c] += v * ((wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1]);
+            }
+          }
+        }
+        if constexpr (NEAREST) {
+          if (near_li >= 0) {
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+              if (near_acc[b] != 0.0f) atomicAdd(&acc[b][near_li], tile_value<T>(near_acc[b], det_scale));
+          }
+        }
+        win.flush_all(acc);
+      }
+      __syncthreads();   // the records are rewritten by the next batch
+    }
   }
   __syncthreads();
 
@@ -598,7 +651,7 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
       T val = acc[b][i];
-      if (cx_any && cy_any && cz_any) {
+      if (cx_any && cy_any && cz_any && part == 0) {
         for (int c = 0; c < 8; ++c) {
           const int vx = (c & 4) ? nx - 1 : 0, vy = (c & 2) ? ny - 1 : 0, vz = (c & 1) ? nz - 1 : 0;
           if (vx == gx && vy == gy && vz == gz) {
@@ -609,10 +662,19 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
       }
       if constexpr (DET) {
         unsigned long long* o = a.out_q + b * a.out_stride + voxel;
-        *o = a.accumulate ? *o + val : val;
+        if (a.parts > 1) {
+          if (val != 0ull) atomicAdd(o, val);
+        } else {
+          *o = a.accumulate ? *o + val : val;
+        }
       } else {
         float* o = a.out + b * a.out_stride + voxel;
-        *o = static_cast<float>(a.accumulate ? static_cast<double>(*o) + val : val);
+        if (a.parts > 1) {
+          // consecutive lanes hold consecutive z: the adds of a wave coalesce
+          if (val != 0.0) unsafeAtomicAdd(o, static_cast<float>(val));
+        } else {
+          *o = static_cast<float>(a.accumulate ? static_cast<double>(*o) + val : val);
+        }
       }
     }
   }

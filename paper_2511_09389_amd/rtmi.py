@@ -39,7 +39,8 @@ class RtmiError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("accum_mode", ctypes.c_int32), ("directions", ctypes.c_void_p),
-                ("ray_weight", ctypes.c_float), ("path", ctypes.c_int32)]
+                ("ray_weight", ctypes.c_float), ("path", ctypes.c_int32),
+                ("tile_parts", ctypes.c_int32)]
 
 
 def _load():
@@ -180,7 +181,7 @@ def trace_multi(j_map, kappa_map, source_pos, num_rays, step_size, radiation_vel
 
 def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
                time_step, kappa_scale=None, substep_cap=None, out=None, deterministic=False,
-               directions=None, ray_weight=0.0, path=PATH_TILED):
+               directions=None, ray_weight=0.0, path=PATH_TILED, tile_parts=0):
     """Frequency bins as a batch axis. j_maps / kappa_maps are 3-D (shared by all bins) or
     4-D [B][nx][ny][nz]; a 3-D kappa with kappa_scale gives kappa_b = kappa * scale[b].
     Returns a [B][nx][ny][nz] float32 tensor."""
@@ -205,7 +206,7 @@ def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_ve
     src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
     out = _new_field((n_bins,) + grid, j_maps) if out is None else out
     opts = Options(ACCUM_DETERMINISTIC if deterministic else ACCUM_ATOMIC, None, float(ray_weight),
-                   int(path))
+                   int(path), int(tile_parts))
     dirs = None
     if directions is not None:
         dirs = _host_f32(directions, 3)
