@@ -75,7 +75,7 @@ typedef struct rtmi_options {
   float ray_weight;         /* weight per ray with explicit directions; <= 0: 4 pi/num_rays */
   int32_t path;             /* RTMI_PATH_TILED (default) or RTMI_PATH_DIRECT */
   /* Tiled path: work-groups sharing one 16^3 output tile, each taking every parts-th
-   * (source, ray patch) pair and adding its share atomically, 1..8; 0 picks a value from
+   * (source, ray patch) pair and adding its share atomically, 1..32; 0 picks a value from
    * the tile count and the device's compute units. Changes the speed, not the field (in
    * the deterministic mode, not a bit of it). Ignored by the direct path. */
   int32_t tile_parts;

@@ -380,8 +380,8 @@ int32_t validate(const Problem& p, Plan* plan) {
     plan->det = p.opts->accum_mode == RTMI_ACCUM_DETERMINISTIC;
     plan->tiled = p.opts->path == RTMI_PATH_TILED;
     plan->explicit_dirs = p.opts->directions != nullptr;
-    if (p.opts->tile_parts < 0 || p.opts->tile_parts > 8)
-      return fail(RTMI_ERR_INVALID_ARG, "tile_parts must be in [0, 8] (got %d)", p.opts->tile_parts);
+    if (p.opts->tile_parts < 0 || p.opts->tile_parts > 32)
+      return fail(RTMI_ERR_INVALID_ARG, "tile_parts must be in [0, 32] (got %d)", p.opts->tile_parts);
     plan->tile_parts = p.opts->tile_parts;
     if (plan->explicit_dirs && p.opts->ray_weight > 0.0f && !std::isfinite(p.opts->ray_weight))
       return fail(RTMI_ERR_NONFINITE, "ray_weight is not finite");
@@ -414,16 +414,15 @@ float ray_weight(const Problem& p, const Plan& plan, int32_t s) {
   return static_cast<float>(w);
 }
 
-// Work-groups per output tile: enough that a few heavy tiles (next to sources, on the box
-// edges) do not leave most of the device idle at the end, for grids with few tiles.
-int tile_parts(int tiles) {
-  int dev = 0, cus = 256;
-  if (hipGetDevice(&dev) == hipSuccess) {
-    int v = 0;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) cus = v;
-  }
-  int parts = (8 * cus + tiles - 1) / tiles;
-  return std::max(1, std::min(8, parts));
+// Work-groups per output tile for one tile launch: the launch's ray-substeps (bins after
+// the first weighted 0.3, since they share the geometry) spread so that each work-group
+// gets about kPartWork of them. Tiles next to sources carry several times the mean load;
+// split this way they span several compute units instead of finishing last.
+constexpr double kPartWork = 3000.0;
+int auto_tile_parts(double ray_substeps, int n_bins, int tiles) {
+  const double work = ray_substeps * (1.0 + 0.3 * (n_bins - 1));
+  const double parts = std::round(work / (double(tiles) * kPartWork));
+  return static_cast<int>(std::max(1.0, std::min(32.0, parts)));
 }
 
 int64_t row_stride(int32_t nsub) { return (int64_t(nsub) + kRowAlign - 1) / kRowAlign * kRowAlign; }
@@ -460,8 +459,18 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
   const int tiles_x = (p.nx + kTile - 1) / kTile, tiles_y = (p.ny + kTile - 1) / kTile,
             tiles_z = (p.nz + kTile - 1) / kTile;
   const int tiles = tiles_x * tiles_y * tiles_z;
-  const int parts = plan.tile_parts > 0 ? plan.tile_parts : tile_parts(tiles);
-  if (parts > 1) {   // the parts of a tile add into a zeroed field
+  // work-groups per tile of each source chunk's launches
+  std::vector<int> parts_of;
+  bool zeroed = false;
+  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
+    double work = 0.0;
+    for (int32_t s = s0; s < std::min(p.n_src, s0 + kMaxSrcPerLaunch); ++s)
+      work += double(p.nrays[s]) * plan.nsub[s];
+    const int parts = plan.tile_parts > 0 ? plan.tile_parts : auto_tile_parts(work, nb_max, tiles);
+    parts_of.push_back(parts);
+    zeroed = zeroed || parts > 1;
+  }
+  if (zeroed) {   // the parts of a tile add into a zeroed field
     const int64_t total = plan.cells * p.n_bins;
     if (plan.det) e = rtmi::launch_fill_zero_u64(out_q, total, st);
     else e = rtmi::launch_fill_zero(p.out, total, st);
@@ -524,7 +533,8 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       t.tiles_x = tiles_x;
       t.tiles_y = tiles_y;
       t.tiles_z = tiles_z;
-      t.accumulate = s0 > 0 ? 1 : 0;
+      const int parts = parts_of[s0 / kMaxSrcPerLaunch];
+      t.accumulate = (s0 > 0 || zeroed) ? 1 : 0;
       t.parts = parts;
 
       if ((e = rtmi::launch_fill_zero(corner, 2 * corner_bytes / sizeof(float), st)) != hipSuccess)

@@ -12,7 +12,7 @@ constexpr int kMaxBinsPerLaunch = 4; // bins a lane carries at once
 constexpr int kPatch = 64;           // rays per coherent patch (one wavefront)
 constexpr int kTile = 16;            // output tile edge, voxels
 constexpr int kTileVox = kTile * kTile * kTile;
-constexpr int kTileThreads = 1024;   // lanes per tile work-group
+constexpr int kTileThreads = 512;    // lanes per tile work-group
 constexpr int kChunk = 8;            // consecutive substeps one tile lane sums in registers
 constexpr int kSeg = 4;              // substeps per recomputed segment of the adjoint sweep
 // Per-patch record of the direction table: min x, y, z, max x, y, z, -, -, cone axis

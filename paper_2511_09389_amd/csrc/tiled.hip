@@ -268,12 +268,9 @@ __device__ __forceinline__ void clip_axis(float s, float n, float inv, float lo,
   t1 = fminf(t1, u1);
 }
 
-// Per-lane 2x2x2 window over a ray's consecutive samples inside one tile: the deposits of
-// a chunk of substeps are summed in registers and reach the LDS tile only when the
-// stencil moves on (the layer left behind is flushed) or the chunk ends. Slot
-// c = (cx << 2) | (cy << 1) | cz; voxels outside the tile are dropped (another tile owns them).
-// In the deterministic mode the tile holds 64-bit fixed point: a flushed sum is scaled and
-// rounded to an integer before the (order-independent) integer add.
+// Deposits reach the LDS tile one corner at a time. In the deterministic mode the tile
+// holds 64-bit fixed point: each value is scaled and rounded to an integer before the
+// (order-independent) integer add.
 template <typename T>
 __device__ __forceinline__ T tile_value(float v, double scale) {
   if constexpr (std::is_same<T, unsigned long long>::value)
@@ -282,89 +279,39 @@ __device__ __forceinline__ T tile_value(float v, double scale) {
     return static_cast<T>(v);
 }
 
-template <int NB>
-struct TileWindow {
-  float acc[NB][8];
-  int lo[3], hi[3];
-  int o[3], e[3];
-  double scale;   // fixed-point scale (deterministic mode only)
-
-  __device__ __forceinline__ TileWindow(int x0, int y0, int z0, int ex, int ey, int ez,
-                                        double fixed_scale) {
-    scale = fixed_scale;
-    o[0] = x0; o[1] = y0; o[2] = z0;
-    e[0] = ex; e[1] = ey; e[2] = ez;
-    lo[0] = lo[1] = lo[2] = hi[0] = hi[1] = hi[2] = -1;
-#pragma unroll
-    for (int b = 0; b < NB; ++b)
-#pragma unroll
-      for (int c = 0; c < 8; ++c) acc[b][c] = 0.0f;
-  }
-
-  template <typename T>
-  __device__ __forceinline__ void flush(int c, T (*tile)[kTileVox]) {
-    const int lx = ((c & 4) ? hi[0] : lo[0]) - o[0];
-    const int ly = ((c & 2) ? hi[1] : lo[1]) - o[1];
-    const int lz = ((c & 1) ? hi[2] : lo[2]) - o[2];
-    const bool inside = lx >= 0 && lx < e[0] && ly >= 0 && ly < e[1] && lz >= 0 && lz < e[2];
-    const int li = (lx * kTile + ly) * kTile + lz;
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      if (inside && acc[b][c] != 0.0f) atomicAdd(&tile[b][li], tile_value<T>(acc[b][c], scale));
-      acc[b][c] = 0.0f;
-    }
-  }
-
-  template <typename T>
-  __device__ __forceinline__ void flush_all(T (*tile)[kTileVox]) {
-#pragma unroll
-    for (int c = 0; c < 8; ++c) flush(c, tile);
-  }
-
-  template <int A, typename T>
-  __device__ __forceinline__ void advance(int lo_new, int hi_new, bool up, T (*tile)[kTileVox]) {
-    constexpr int bit = 4 >> A;
-    if (lo_new == lo[A] && hi_new == hi[A]) return;
-    if (up && lo_new == hi[A]) {
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        if (c & bit) continue;
-        flush(c, tile);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          acc[b][c] = acc[b][c | bit];
-          acc[b][c | bit] = 0.0f;
-        }
-      }
-    } else if (!up && hi_new == lo[A]) {
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        if (c & bit) continue;
-        flush(c | bit, tile);
-#pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          acc[b][c | bit] = acc[b][c];
-          acc[b][c] = 0.0f;
-        }
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < 8; ++c) flush(c, tile);
-    }
-    lo[A] = lo_new;
-    hi[A] = hi_new;
-  }
+// One axis of a sample's stencil as seen from a tile: both corners' offsets in the LDS
+// block, clamped into the tile, and their weights, zero for a corner outside the tile
+// (another tile owns it). An axis whose two corners coincide carries its whole weight
+// on the lower one.
+struct TileAxis {
+  int off[2];
+  float w[2];
+  bool any;   // some corner of this axis lies in the tile
 };
+
+__device__ __forceinline__ TileAxis tile_axis(const Axis& A, int origin, int extent, int stride) {
+  TileAxis r;
+  const bool same = A.lo == A.hi;
+  const int l0 = A.lo - origin, l1 = A.hi - origin;
+  const bool in0 = static_cast<unsigned>(l0) < static_cast<unsigned>(extent);
+  const bool in1 = static_cast<unsigned>(l1) < static_cast<unsigned>(extent) && !same;
+  r.w[0] = in0 ? (same ? 1.0f : A.w0) : 0.0f;
+  r.w[1] = in1 ? A.w1 : 0.0f;
+  r.off[0] = min(max(l0, 0), extent - 1) * stride;
+  r.off[1] = min(max(l1, 0), extent - 1) * stride;
+  r.any = in0 | in1;
+  return r;
+}
 
 // The tile is accumulated in binary64 (or 64-bit fixed point in the deterministic mode):
 // a voxel next to a source collects thousands of deposits, and binary32 running sums of
 // that length drift by more than the binary32 field is allowed to differ from the exact one.
 // NEAREST: each sample adds its value to its nearest voxel only (the adjoint's kappa
 // deposit) instead of the trilinear stencil.
-// Lanes per tile work-group: 1024, or 512 when several bins. windows would not fit
-// in the registers 1024 lanes leave per lane.
+// Lanes per tile work-group. 512 lets two work-groups share a compute unit (one bin), so
+// one can compute while the other waits at a barrier or on memory.
 template <int NB>
-constexpr int tile_threads() { return NB == 1 ? kTileThreads : kTileThreads / 2; }
+constexpr int tile_threads() { return kTileThreads; }
 
 template <int NB, bool DET, bool NEAREST>
 __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs a) {
@@ -555,7 +502,6 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
         const int kbeg = max(ka_o, kblk), kend = min(kb_o, kblk + kChunk - 1);
         const float4 dd = r_dir[o];
         const float4 src = b_src[ow];
-        const bool up[3] = {dd.x >= 0.0f, dd.y >= 0.0f, dd.z >= 0.0f};
         const float* vrow = a.V + b_row[ow] + static_cast<long long>(o & 63) * b_vstride[ow];
         // the chunk's recorded values, fetched before any of them is needed
         float vv[NB][kChunk];
@@ -571,69 +517,47 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
             vv[b][4 * q + 3] = f.w;
           }
         }
-        TileWindow<NB> win(x0, y0, z0, ex, ey, ez, det_scale);
-        int near_li = -1;         // NEAREST: voxel of the running sum, -1 when empty
-        float near_acc[NB];
-#pragma unroll
-        for (int b = 0; b < NB; ++b) near_acc[b] = 0.0f;
+        // Each sample adds its eight weighted corners straight to the tile: no per-lane
+        // state to flush, and no branch that diverges with where each ray stands.
 #pragma unroll
         for (int t = 0; t < kChunk; ++t) {
           const int k = kblk + t;
-          if (k < kbeg || k > kend) continue;
           const float dist = sample_distance(k, ds);
           const float x = sample_axis(src.x, dist, dd.x);
           const float y = sample_axis(src.y, dist, dd.y);
           const float z = sample_axis(src.z, dist, dd.z);
-          // collapsed onto one corner voxel: summed by the record phase
-          if (axis_clamped(x, nx) && axis_clamped(y, ny) && axis_clamped(z, nz)) continue;
+          // outside this ray's range for the tile, or collapsed onto one corner voxel of
+          // the box (summed by the record phase)
+          // (bitwise tests: one branch per sample, not a chain of short-circuit branches)
+          const int clamped = static_cast<int>(axis_clamped(x, nx)) + static_cast<int>(axis_clamped(y, ny)) +
+                              static_cast<int>(axis_clamped(z, nz));
+          if ((k < kbeg) | (k > kend) | (clamped == 3)) continue;
           const Axis X = axis_stencil(x, nx);
           const Axis Y = axis_stencil(y, ny);
           const Axis Z = axis_stencil(z, nz);
           if constexpr (NEAREST) {
             const int lx = X.nearest - x0, ly = Y.nearest - y0, lz = Z.nearest - z0;
-            if (lx < 0 || lx >= ex || ly < 0 || ly >= ey || lz < 0 || lz >= ez) continue;
-            const int li = (lx * kTile + ly) * kTile + lz;
-            if (li != near_li) {
-              if (near_li >= 0) {
-#pragma unroll
-                for (int b = 0; b < NB; ++b)
-                  if (near_acc[b] != 0.0f) atomicAdd(&acc[b][near_li], tile_value<T>(near_acc[b], det_scale));
-              }
-              near_li = li;
-#pragma unroll
-              for (int b = 0; b < NB; ++b) near_acc[b] = 0.0f;
-            }
-#pragma unroll
-            for (int b = 0; b < NB; ++b) near_acc[b] += vv[b][t];
-          } else {
-            // no corner of this sample inside the tile: nothing to add
-            if (X.hi < x0 || X.lo >= x0 + ex || Y.hi < y0 || Y.lo >= y0 + ey || Z.hi < z0 ||
-                Z.lo >= z0 + ez)
+            if ((static_cast<unsigned>(lx) >= static_cast<unsigned>(ex)) |
+                (static_cast<unsigned>(ly) >= static_cast<unsigned>(ey)) |
+                (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
               continue;
-            win.template advance<0>(X.lo, X.hi, up[0], acc);
-            win.template advance<1>(Y.lo, Y.hi, up[1], acc);
-            win.template advance<2>(Z.lo, Z.hi, up[2], acc);
-            // an axis whose two corners coincide carries its whole weight on the lower one
-            const float wx[2] = {X.lo == X.hi ? 1.0f : X.w0, X.lo == X.hi ? 0.0f : X.w1};
-            const float wy[2] = {Y.lo == Y.hi ? 1.0f : Y.w0, Y.lo == Y.hi ? 0.0f : Y.w1};
-            const float wz[2] = {Z.lo == Z.hi ? 1.0f : Z.w0, Z.lo == Z.hi ? 0.0f : Z.w1};
+            const int li = (lx * kTile + ly) * kTile + lz;
 #pragma unroll
-            for (int b = 0; b < NB; ++b) {
-              const float v = vv[b][t];
+            for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][t], det_scale));
+          } else {
+            const TileAxis tx = tile_axis(X, x0, ex, kTile * kTile);
+            const TileAxis ty = tile_axis(Y, y0, ey, kTile);
+            const TileAxis tz = tile_axis(Z, z0, ez, 1);
+            if (!(tx.any & ty.any & tz.any)) continue;
 #pragma unroll
-              for (int c = 0; c < 8; ++c)
-                win.acc[b][c] += v * ((wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1]);
+            for (int c = 0; c < 8; ++c) {
+              const float w = (tx.w[c >> 2] * ty.w[(c >> 1) & 1]) * tz.w[c & 1];
+              const int li = tx.off[c >> 2] + ty.off[(c >> 1) & 1] + tz.off[c & 1];
+#pragma unroll
+              for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][t] * w, det_scale));
             }
           }
         }
-        if constexpr (NEAREST) {
-          if (near_li >= 0) {
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-              if (near_acc[b] != 0.0f) atomicAdd(&acc[b][near_li], tile_value<T>(near_acc[b], det_scale));
-          }
-        }
-        win.flush_all(acc);
       }
       __syncthreads();   // the records are rewritten by the next batch
     }
