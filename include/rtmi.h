@@ -74,11 +74,12 @@ typedef struct rtmi_options {
   const float* directions;
   float ray_weight;         /* weight per ray with explicit directions; <= 0: 4 pi/num_rays */
   int32_t path;             /* RTMI_PATH_TILED (default) or RTMI_PATH_DIRECT */
-  /* Tiled path: work-groups sharing one 16^3 output tile, each taking every parts-th
-   * (source, ray patch) pair and adding its share atomically, 1..32; 0 picks a value from
-   * the tile count and the device's compute units. Changes the speed, not the field (in
-   * the deterministic mode, not a bit of it). Ignored by the direct path. */
-  int32_t tile_parts;
+  /* Tiled path: size of a tile work item in chunks (a chunk is one ray's substeps inside
+   * one aligned block of 8, for one tile). A tile whose rays bring C chunks is split into
+   * ceil(C / tile_item_chunks) work items (at most 64), which separate work-groups take
+   * and add atomically. 0 picks 1024. Changes the speed, not the field (in the
+   * deterministic mode, not a bit of it). Ignored by the direct path. */
+  int32_t tile_item_chunks;
 } rtmi_options;
 
 /* Execution paths (rtmi_options.path). Both compute the same field.
@@ -157,6 +158,44 @@ int32_t rtmi_trace_bins(const float* j_maps, int64_t j_bin_stride,
                         const int32_t* substep_cap, float step_size,
                         float radiation_velocity, float time_step,
                         float* out_fields, const rtmi_options* opts, void* stream);
+
+/* ---- Plans: the batched multi-source, multi-bin march set up once, run many times ----
+ *
+ * The multi-source routine (Sec. 2, "loop-and-sum") and the frequency bins (Sec. 2,
+ * "Frequency-bin agnosticism") as one prepared execution: sources with their own N_Omega
+ * and substep caps, times bins, exactly as rtmi_trace_bins computes them (same field, and
+ * in the deterministic mode the same bits). Creation validates the geometry, uploads the
+ * direction tables, allocates the whole workspace (rtmi_plan_workspace_bytes) and
+ * computes the tile schedules, which depend on the geometry only; it synchronises and
+ * may allocate. Execution takes new maps and only enqueues kernels: it allocates nothing,
+ * does not synchronise and reads no device data on the host, so it may be captured into
+ * a HIP graph and replayed. Executions of one plan share its workspace: they must be
+ * ordered on one stream (or otherwise serialised), never run concurrently. A plan
+ * belongs to the device current at creation, which must be current when it executes.
+ * Tiled path only (opts->path = RTMI_PATH_DIRECT is refused with RTMI_ERR_UNSUPPORTED).
+ * Kernel timing (rtmi_timing_enable) must be off while a graph is being captured. */
+typedef struct rtmi_plan rtmi_plan;
+
+/* Arguments as rtmi_trace_bins without the maps and field; the host arrays are copied.
+ * On success *plan receives the plan, else NULL and a negative RTMI_ERR_* code. */
+int32_t rtmi_plan_create(int32_t nx, int32_t ny, int32_t nz, int32_t n_src,
+                         const float* source_pos, const int32_t* num_rays,
+                         const int32_t* substep_cap, int32_t n_bins,
+                         int64_t j_bin_stride, int64_t kappa_bin_stride,
+                         const float* kappa_scale, float step_size,
+                         float radiation_velocity, float time_step,
+                         const rtmi_options* opts, rtmi_plan** plan);
+
+/* out_fields [n_bins][nx][ny][nz] (DEVICE, overwritten) from j_maps and kappa_maps
+ * (DEVICE, laid out as the bin strides given at creation), on `stream`. */
+int32_t rtmi_plan_execute(const rtmi_plan* plan, const float* j_maps,
+                          const float* kappa_maps, float* out_fields, void* stream);
+
+/* Device bytes the plan holds. */
+int64_t rtmi_plan_workspace_bytes(const rtmi_plan* plan);
+
+/* Frees the plan (NULL is accepted). No execution of it may still be pending. */
+int32_t rtmi_plan_destroy(rtmi_plan* plan);
 
 /* Adjoint of rtmi_trace_multi (Sec. 4: gradients of a loss through the tracer, here
  * written out by the chain rule on Eq. (2) instead of automatic differentiation): given

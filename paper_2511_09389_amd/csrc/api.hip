@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <utility>
@@ -350,16 +351,18 @@ struct Plan {
   bool det = false;
   bool tiled = true;
   bool explicit_dirs = false;
-  int32_t tile_parts = 0;   // 0: automatic
+  int32_t item_chunks = 0;  // tile work-item size; 0: kItemChunks
   std::vector<int32_t> nsub;
   std::vector<DevTable> tables;
   double bound_per_unit_j = 0.0;
   int64_t cells = 0;
 };
 
-int32_t validate(const Problem& p, Plan* plan) {
-  if (!p.j || !p.kap || !p.out || !p.src || !p.nrays)
-    return fail(RTMI_ERR_INVALID_ARG, "null map, field, source_pos or num_rays pointer");
+// maps_given: the call carries its maps and field (false when a plan is made without them)
+int32_t validate(const Problem& p, Plan* plan, bool maps_given = true) {
+  if (maps_given && (!p.j || !p.kap || !p.out))
+    return fail(RTMI_ERR_INVALID_ARG, "null map or field pointer");
+  if (!p.src || !p.nrays) return fail(RTMI_ERR_INVALID_ARG, "null source_pos or num_rays pointer");
   if (int32_t st = check_shape(p.nx, p.ny, p.nz)) return st;
   if (int32_t st = check_scalars(p.ds, p.c, p.dt)) return st;
   if (p.n_src < 1) return fail(RTMI_ERR_INVALID_ARG, "n_src must be >= 1 (got %d)", p.n_src);
@@ -380,9 +383,10 @@ int32_t validate(const Problem& p, Plan* plan) {
     plan->det = p.opts->accum_mode == RTMI_ACCUM_DETERMINISTIC;
     plan->tiled = p.opts->path == RTMI_PATH_TILED;
     plan->explicit_dirs = p.opts->directions != nullptr;
-    if (p.opts->tile_parts < 0 || p.opts->tile_parts > 32)
-      return fail(RTMI_ERR_INVALID_ARG, "tile_parts must be in [0, 32] (got %d)", p.opts->tile_parts);
-    plan->tile_parts = p.opts->tile_parts;
+    if (p.opts->tile_item_chunks < 0 || p.opts->tile_item_chunks > (1 << 20))
+      return fail(RTMI_ERR_INVALID_ARG, "tile_item_chunks must be in [0, 2^20] (got %d)",
+                  p.opts->tile_item_chunks);
+    plan->item_chunks = p.opts->tile_item_chunks;
     if (plan->explicit_dirs && p.opts->ray_weight > 0.0f && !std::isfinite(p.opts->ray_weight))
       return fail(RTMI_ERR_NONFINITE, "ray_weight is not finite");
   }
@@ -414,72 +418,117 @@ float ray_weight(const Problem& p, const Plan& plan, int32_t s) {
   return static_cast<float>(w);
 }
 
-// Work-groups per output tile for one tile launch: the launch's ray-substeps (bins after
-// the first weighted 0.3, since they share the geometry) spread so that each work-group
-// gets about kPartWork of them. Tiles next to sources carry several times the mean load;
-// split this way they span several compute units instead of finishing last.
-constexpr double kPartWork = 3000.0;
-int auto_tile_parts(double ray_substeps, int n_bins, int tiles) {
-  const double work = ray_substeps * (1.0 + 0.3 * (n_bins - 1));
-  const double parts = std::round(work / (double(tiles) * kPartWork));
-  return static_cast<int>(std::max(1.0, std::min(32.0, parts)));
-}
+size_t align256(size_t n) { return (n + 255) / 256 * 256; }
+
+// Target chunks (ray segments of up to kChunk substeps inside one tile) per tile work
+// item when the caller does not choose: two rounds of the work-group's lanes.
+constexpr int kItemChunks = 2 * rtmi::kTileThreads;
+
+// Schedule buffers of the tile launches, carved from the workspace.
+struct TileSchedule {
+  unsigned long long* cost = nullptr;
+  int2* map = nullptr;
+  int* counters = nullptr;
+  static size_t bytes(int tiles) {
+    return align256(size_t(tiles) * sizeof(unsigned long long)) +
+           align256(size_t(tiles) * rtmi::kMaxParts * sizeof(int2)) + 256;
+  }
+  void carve(char* base, int tiles) {
+    cost = reinterpret_cast<unsigned long long*>(base);
+    base += align256(size_t(tiles) * sizeof(unsigned long long));
+    map = reinterpret_cast<int2*>(base);
+    base += align256(size_t(tiles) * rtmi::kMaxParts * sizeof(int2));
+    counters = reinterpret_cast<int*>(base);
+  }
+  void apply(rtmi::TileArgs& t, int item_chunks) const {
+    t.tile_cost = cost;
+    t.item_map = map;
+    t.item_total = counters;
+    t.item_next = counters + 1;
+    t.item_done = counters + 2;
+    t.item_chunks = item_chunks > 0 ? item_chunks : kItemChunks;
+  }
+};
 
 int64_t row_stride(int32_t nsub) { return (int64_t(nsub) + kRowAlign - 1) / kRowAlign * kRowAlign; }
 
 // ---- tiled path: record + tile per (bin chunk, source chunk) ----
-int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
-                  const double* det_scale) {
-  const hipStream_t st = p.stream;
-  // workspace: the largest (bin chunk x source chunk) row set, plus the corner sums
+
+// Workspace of a tiled execution: corner sums, tile schedules (one shared by all launches,
+// or one per launch when a plan keeps them), the interleaved (j, kappa) copy and the
+// recorded rows of the largest launch.
+struct TiledLayout {
+  int tiles_x = 0, tiles_y = 0, tiles_z = 0, tiles = 0;
+  int n_launch = 0;
+  bool interleaved = false;
+  size_t corner = 0, sched = 0, med = 0, v = 0, total = 0;   // byte offsets / size
+  size_t sched_bytes = 0;
+};
+
+constexpr size_t kCornerBytes = 256;   // [4][8] floats, then (next 256 B) [4][8] u64
+
+TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_launch) {
+  TiledLayout L;
+  L.tiles_x = (p.nx + kTile - 1) / kTile;
+  L.tiles_y = (p.ny + kTile - 1) / kTile;
+  L.tiles_z = (p.nz + kTile - 1) / kTile;
+  L.tiles = L.tiles_x * L.tiles_y * L.tiles_z;
   int64_t v_elems_max = 0;
-  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
+  int src_chunks = 0;
+  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch, ++src_chunks) {
     int64_t e = 0;
     for (int32_t s = s0; s < std::min(p.n_src, s0 + kMaxSrcPerLaunch); ++s)
       if (plan.nsub[s] > 0) e += int64_t(p.nrays[s]) * row_stride(plan.nsub[s]);
     v_elems_max = std::max(v_elems_max, e);
   }
+  L.n_launch = src_chunks * ((p.n_bins + kMaxBinsPerLaunch - 1) / kMaxBinsPerLaunch);
   const int32_t nb_max = std::min(kMaxBinsPerLaunch, p.n_bins);
-  const size_t corner_bytes = 256;  // [4][8] floats, then [4][8] u64 (rounded up)
-  const size_t v_bytes = size_t(v_elems_max) * nb_max * sizeof(float);
   // a shared j and a shared (scaled) kappa are gathered from one interleaved copy
-  const bool interleaved = p.j_stride == 0 && p.k_stride == 0;
-  const size_t med_bytes = interleaved ? (size_t(plan.cells) + 1) * sizeof(float2) : 0;
-  const size_t med_pad = (med_bytes + 255) / 256 * 256;
-  char* ws = nullptr;
-  if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&ws), corner_bytes * 2 + med_pad + v_bytes, st))
-    return rc;
-  float* corner = reinterpret_cast<float*>(ws);
-  unsigned long long* corner_q = reinterpret_cast<unsigned long long*>(ws + corner_bytes);
-  float2* med = interleaved ? reinterpret_cast<float2*>(ws + 2 * corner_bytes) : nullptr;
-  float* V = reinterpret_cast<float*>(ws + 2 * corner_bytes + med_pad);
-  hipError_t e;
-  if (interleaved && (e = rtmi::launch_interleave(p.j, p.kap, med, plan.cells, st)) != hipSuccess)
-    return hip_fail(e, "interleave");
-  const int tiles_x = (p.nx + kTile - 1) / kTile, tiles_y = (p.ny + kTile - 1) / kTile,
-            tiles_z = (p.nz + kTile - 1) / kTile;
-  const int tiles = tiles_x * tiles_y * tiles_z;
-  // work-groups per tile of each source chunk's launches
-  std::vector<int> parts_of;
-  bool zeroed = false;
-  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
-    double work = 0.0;
-    for (int32_t s = s0; s < std::min(p.n_src, s0 + kMaxSrcPerLaunch); ++s)
-      work += double(p.nrays[s]) * plan.nsub[s];
-    const int parts = plan.tile_parts > 0 ? plan.tile_parts : auto_tile_parts(work, nb_max, tiles);
-    parts_of.push_back(parts);
-    zeroed = zeroed || parts > 1;
+  L.interleaved = p.j_stride == 0 && p.k_stride == 0;
+  L.sched_bytes = TileSchedule::bytes(L.tiles);
+  L.corner = 0;
+  L.sched = 2 * kCornerBytes;
+  L.med = L.sched + L.sched_bytes * (sched_per_launch ? L.n_launch : 1);
+  L.v = L.med + (L.interleaved ? align256((size_t(plan.cells) + 1) * sizeof(float2)) : 0);
+  L.total = L.v + size_t(v_elems_max) * nb_max * sizeof(float);
+  return L;
+}
+
+// What the tiled path enqueues: kFull (schedules computed in line, the stateless calls),
+// kSchedule (only the schedules, each into its own buffer: plan creation) and kReplay
+// (everything but the schedules, which a plan keeps).
+enum class TiledMode { kFull, kSchedule, kReplay };
+
+int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
+                  const double* det_scale, TiledMode mode = TiledMode::kFull,
+                  char* given_ws = nullptr) {
+  const hipStream_t st = p.stream;
+  const bool per_launch = mode != TiledMode::kFull;
+  const TiledLayout L = tiled_layout(p, plan, per_launch);
+  char* ws = given_ws;
+  if (!ws) {
+    if (mode != TiledMode::kFull) return fail(RTMI_ERR_INVALID_ARG, "a plan's workspace is missing");
+    if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&ws), L.total, st)) return rc;
   }
-  if (zeroed) {   // the parts of a tile add into a zeroed field
+  float* corner = reinterpret_cast<float*>(ws + L.corner);
+  unsigned long long* corner_q = reinterpret_cast<unsigned long long*>(ws + L.corner + kCornerBytes);
+  float2* med = L.interleaved ? reinterpret_cast<float2*>(ws + L.med) : nullptr;
+  float* V = reinterpret_cast<float*>(ws + L.v);
+  hipError_t e;
+  if (mode != TiledMode::kSchedule) {
+    if (L.interleaved && (e = rtmi::launch_interleave(p.j, p.kap, med, plan.cells, st)) != hipSuccess)
+      return hip_fail(e, "interleave");
+    // every tile launch adds into the zeroed field
     const int64_t total = plan.cells * p.n_bins;
     if (plan.det) e = rtmi::launch_fill_zero_u64(out_q, total, st);
     else e = rtmi::launch_fill_zero(p.out, total, st);
     if (e != hipSuccess) return hip_fail(e, "fill");
   }
 
+  int launch = 0;
   for (int32_t b0 = 0; b0 < p.n_bins; b0 += kMaxBinsPerLaunch) {
     const int32_t nb = std::min(kMaxBinsPerLaunch, p.n_bins - b0);
-    for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
+    for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch, ++launch) {
       const int32_t ns = std::min(kMaxSrcPerLaunch, p.n_src - s0);
       rtmi::RecordArgs r;
       rtmi::TileArgs t;
@@ -509,9 +558,9 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       r.blk_begin[ns] = blocks;
       t.pbegin[ns] = patches;
       r.med = med;
-      r.j = p.j + b0 * p.j_stride;
+      r.j = p.j ? p.j + b0 * p.j_stride : nullptr;
       r.j_stride = p.j_stride;
-      r.kap = p.kap + b0 * p.k_stride;
+      r.kap = p.kap ? p.kap + b0 * p.k_stride : nullptr;
       r.k_stride = p.k_stride;
       for (int32_t b = 0; b < nb; ++b) r.kscale[b] = p.kscale ? p.kscale[b0 + b] : 1.0f;
       r.V = V;
@@ -527,17 +576,21 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       r.nz = t.nz = p.nz;
       r.ds = t.ds = p.ds;
       r.n_src = t.n_src = ns;
-      t.out = p.out + b0 * plan.cells;
+      t.out = p.out ? p.out + b0 * plan.cells : nullptr;
       t.out_q = out_q ? out_q + b0 * plan.cells : nullptr;
       t.out_stride = plan.cells;
-      t.tiles_x = tiles_x;
-      t.tiles_y = tiles_y;
-      t.tiles_z = tiles_z;
-      const int parts = parts_of[s0 / kMaxSrcPerLaunch];
-      t.accumulate = (s0 > 0 || zeroed) ? 1 : 0;
-      t.parts = parts;
+      t.tiles_x = L.tiles_x;
+      t.tiles_y = L.tiles_y;
+      t.tiles_z = L.tiles_z;
+      TileSchedule sched;
+      sched.carve(ws + L.sched + (per_launch ? launch * L.sched_bytes : 0), L.tiles);
+      sched.apply(t, plan.item_chunks);
 
-      if ((e = rtmi::launch_fill_zero(corner, 2 * corner_bytes / sizeof(float), st)) != hipSuccess)
+      if (mode != TiledMode::kReplay &&
+          (e = rtmi::launch_tile_schedule(t, L.tiles, st)) != hipSuccess)
+        return hip_fail(e, "tile schedule");
+      if (mode == TiledMode::kSchedule) continue;
+      if ((e = rtmi::launch_fill_zero(corner, 2 * kCornerBytes / sizeof(float), st)) != hipSuccess)
         return hip_fail(e, "fill");
       if (blocks > 0) {
         TimedLaunch tl;
@@ -548,12 +601,12 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       }
       TimedLaunch tl;
       if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl)) != hipSuccess) return hip_fail(e, "timing");
-      if ((e = rtmi::launch_tile(t, nb, plan.det, false, tiles * parts, st)) != hipSuccess)
+      if ((e = rtmi::launch_tile_run(t, nb, plan.det, false, st)) != hipSuccess)
         return hip_fail(e, "tile launch");
       if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
     }
   }
-  if ((e = hipFreeAsync(ws, st)) != hipSuccess) return hip_fail(e, "workspace release");
+  if (!given_ws && (e = hipFreeAsync(ws, st)) != hipSuccess) return hip_fail(e, "workspace release");
   return RTMI_OK;
 }
 
@@ -691,9 +744,16 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
   const size_t med_bytes = ((size_t(plan.cells) + 1) * sizeof(float2) + 255) / 256 * 256;
   const size_t v_bytes = (size_t(v_elems_max) * sizeof(float) + 255) / 256 * 256;
   const size_t c_bytes = size_t(c_elems_max) * sizeof(float2);
+  const int tiles_x = (p.nx + kTile - 1) / kTile, tiles_y = (p.ny + kTile - 1) / kTile,
+            tiles_z = (p.nz + kTile - 1) / kTile;
+  const int tiles = tiles_x * tiles_y * tiles_z;
+  const size_t sched_bytes = TileSchedule::bytes(tiles);
   char* ws = nullptr;
-  if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&ws), corner_bytes + med_bytes + 2 * v_bytes + c_bytes, st))
+  if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&ws),
+                              corner_bytes + med_bytes + 2 * v_bytes + c_bytes + sched_bytes, st))
     return rc;
+  TileSchedule sched;
+  sched.carve(ws + corner_bytes + med_bytes + 2 * v_bytes + c_bytes, tiles);
   float* corner = reinterpret_cast<float*>(ws);  // [0..7] for dL/dj, [8..15] for dL/dkappa
   float2* med = reinterpret_cast<float2*>(ws + corner_bytes);
   float* Vj = reinterpret_cast<float*>(ws + corner_bytes + med_bytes);
@@ -701,9 +761,9 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
   float2* ckpt = reinterpret_cast<float2*>(ws + corner_bytes + med_bytes + 2 * v_bytes);
   hipError_t e;
   if ((e = rtmi::launch_interleave(p.j, p.kap, med, plan.cells, st)) != hipSuccess) return hip_fail(e, "interleave");
-  const int tiles_x = (p.nx + kTile - 1) / kTile, tiles_y = (p.ny + kTile - 1) / kTile,
-            tiles_z = (p.nz + kTile - 1) / kTile;
-  const int tiles = tiles_x * tiles_y * tiles_z;
+  if ((e = rtmi::launch_fill_zero(grad_j, plan.cells, st)) != hipSuccess ||
+      (e = rtmi::launch_fill_zero(grad_k, plan.cells, st)) != hipSuccess)
+    return hip_fail(e, "fill");
 
   for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
     const int32_t ns = std::min(kMaxSrcPerLaunch, p.n_src - s0);
@@ -754,21 +814,157 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
     t.tiles_x = tiles_x;
     t.tiles_y = tiles_y;
     t.tiles_z = tiles_z;
-    t.accumulate = s0 > 0 ? 1 : 0;
-    t.parts = 1;
+    sched.apply(t, 0);
     if ((e = rtmi::launch_fill_zero(corner, 64, st)) != hipSuccess) return hip_fail(e, "fill");
     if (blocks > 0 && (e = rtmi::launch_adjoint_record(r, blocks, st)) != hipSuccess)
       return hip_fail(e, "adjoint launch");
     t.V = Vj;
     t.corner = corner;
     t.out = grad_j;
-    if ((e = rtmi::launch_tile(t, 1, false, false, tiles, st)) != hipSuccess) return hip_fail(e, "tile launch");
+    // one schedule serves both deposits (same rays, same tiles)
+    if ((e = rtmi::launch_tile_schedule(t, tiles, st)) != hipSuccess ||
+        (e = rtmi::launch_tile_run(t, 1, false, false, st)) != hipSuccess)
+      return hip_fail(e, "tile launch");
     t.V = Vk;
     t.corner = corner + 8;
     t.out = grad_k;
-    if ((e = rtmi::launch_tile(t, 1, false, true, tiles, st)) != hipSuccess) return hip_fail(e, "tile launch");
+    if ((e = rtmi::launch_tile_run(t, 1, false, true, st)) != hipSuccess) return hip_fail(e, "tile launch");
   }
   if ((e = hipFreeAsync(ws, st)) != hipSuccess) return hip_fail(e, "workspace release");
+  g_error.clear();
+  return RTMI_OK;
+}
+
+// ---- plans ----
+
+}  // namespace
+
+// A validated problem with its direction tables, workspace and tile schedules, executed
+// any number of times on new maps. Owns everything it points to except the maps and field.
+struct rtmi_plan {
+  int device = 0;
+  std::vector<float> src, kscale;
+  std::vector<int32_t> nrays, caps;
+  rtmi_options opts{};
+  Problem p{};
+  Plan plan;
+  char* ws = nullptr;          // hipMalloc'd
+  size_t ws_bytes = 0;
+  char* table = nullptr;       // explicit direction table, hipMalloc'd
+  unsigned long long* out_q = nullptr;
+  double* det_scale = nullptr;
+};
+
+namespace {
+
+void plan_release(rtmi_plan* P) {
+  if (!P) return;
+  int cur = 0;
+  const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != P->device;
+  if (switch_dev) (void)hipSetDevice(P->device);
+  if (P->ws) (void)hipFree(P->ws);
+  if (P->table) (void)hipFree(P->table);
+  if (switch_dev) (void)hipSetDevice(cur);
+  delete P;
+}
+
+int32_t plan_create(const Problem& given, rtmi_plan** out) {
+  std::unique_ptr<rtmi_plan, void (*)(rtmi_plan*)> P(new rtmi_plan, plan_release);
+  if (hipGetDevice(&P->device) != hipSuccess) return fail(RTMI_ERR_HIP, "no current HIP device");
+  Problem p = given;
+  if (int32_t st = validate(p, &P->plan, false)) return st;
+  if (!P->plan.tiled) return fail(RTMI_ERR_UNSUPPORTED, "plans run the tiled path only");
+  // own copies of the host arrays
+  P->src.assign(p.src, p.src + size_t(p.n_src) * 3);
+  P->nrays.assign(p.nrays, p.nrays + p.n_src);
+  if (p.caps) P->caps.assign(p.caps, p.caps + p.n_src);
+  if (p.kscale) P->kscale.assign(p.kscale, p.kscale + p.n_bins);
+  if (p.opts) {
+    P->opts = *p.opts;
+    P->opts.directions = nullptr;   // uploaded below; the caller's array is not kept
+  }
+  p.src = P->src.data();
+  p.nrays = P->nrays.data();
+  p.caps = p.caps ? P->caps.data() : nullptr;
+  p.kscale = p.kscale ? P->kscale.data() : nullptr;
+  const rtmi_options* user_opts = p.opts;
+  p.opts = p.opts ? &P->opts : nullptr;
+  p.j = nullptr;
+  p.kap = nullptr;
+  p.out = nullptr;
+
+  hipStream_t st = nullptr;
+  hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+  if (e != hipSuccess) return hip_fail(e, "hipStreamCreate");
+  struct StreamGuard {
+    hipStream_t s;
+    ~StreamGuard() { (void)hipStreamDestroy(s); }
+  } guard{st};
+  p.stream = st;
+
+  // direction tables
+  P->plan.tables.resize(p.n_src);
+  if (P->plan.explicit_dirs) {
+    const int32_t n = p.nrays[0];
+    std::vector<float> xyz(user_opts->directions, user_opts->directions + size_t(n) * 3);
+    const HostTable t = build_table(xyz);
+    if ((e = hipMalloc(reinterpret_cast<void**>(&P->table), table_bytes(t))) != hipSuccess)
+      return hip_fail(e, "hipMalloc(directions)");
+    const size_t db = t.dirs.size() * sizeof(float4);
+    if ((e = hipMemcpy(P->table, t.dirs.data(), db, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(P->table + db, t.bounds.data(), t.bounds.size() * sizeof(float),
+                       hipMemcpyHostToDevice)) != hipSuccess)
+      return hip_fail(e, "hipMemcpy(directions)");
+    DevTable dt;
+    dt.dirs = reinterpret_cast<float4*>(P->table);
+    dt.bounds = reinterpret_cast<float*>(P->table + db);
+    for (int32_t s = 0; s < p.n_src; ++s) P->plan.tables[s] = dt;
+  } else {
+    for (int32_t s = 0; s < p.n_src; ++s)
+      if (int32_t rc = get_dirs(p.nrays[s], st, &P->plan.tables[s])) return rc;
+  }
+
+  // workspace: the tiled layout with one schedule per launch, then the fixed-point field
+  const TiledLayout L = tiled_layout(p, P->plan, true);
+  const int64_t total = P->plan.cells * p.n_bins;
+  const size_t det_off = align256(L.total);
+  P->ws_bytes = P->plan.det ? det_off + size_t(total) * 8 + 16 : L.total;
+  if ((e = hipMalloc(reinterpret_cast<void**>(&P->ws), P->ws_bytes)) != hipSuccess)
+    return hip_fail(e, "hipMalloc(plan workspace)");
+  if (P->plan.det) {
+    P->out_q = reinterpret_cast<unsigned long long*>(P->ws + det_off);
+    P->det_scale = reinterpret_cast<double*>(P->out_q + total);
+  }
+  if (int32_t rc = run_tiled(p, P->plan, P->out_q, P->det_scale, TiledMode::kSchedule, P->ws)) return rc;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "plan schedule");
+  p.stream = nullptr;
+  P->p = p;
+  *out = P.release();
+  g_error.clear();
+  return RTMI_OK;
+}
+
+int32_t plan_execute(const rtmi_plan* P, const float* j, const float* kap, float* out, hipStream_t st) {
+  if (!P) return fail(RTMI_ERR_INVALID_ARG, "null plan");
+  if (!j || !kap || !out) return fail(RTMI_ERR_INVALID_ARG, "null map or field pointer");
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess || cur != P->device)
+    return fail(RTMI_ERR_INVALID_ARG, "the plan belongs to device %d, the current device is %d", P->device, cur);
+  Problem p = P->p;
+  p.j = j;
+  p.kap = kap;
+  p.out = out;
+  p.stream = st;
+  hipError_t e;
+  const int64_t total = P->plan.cells * p.n_bins;
+  if (P->plan.det) {
+    const int64_t j_count = p.j_stride ? p.j_stride * (p.n_bins - 1) + P->plan.cells : P->plan.cells;
+    if ((e = rtmi::launch_det_scale(p.j, j_count, P->plan.bound_per_unit_j, P->det_scale, st)) != hipSuccess)
+      return hip_fail(e, "det_scale");
+  }
+  if (int32_t rc = run_tiled(p, P->plan, P->out_q, P->det_scale, TiledMode::kReplay, P->ws)) return rc;
+  if (P->plan.det && (e = rtmi::launch_det_convert(P->out_q, P->det_scale, p.out, total, st)) != hipSuccess)
+    return hip_fail(e, "det_convert");
   g_error.clear();
   return RTMI_OK;
 }
@@ -779,7 +975,7 @@ extern "C" {
 
 const char* rtmi_last_error(void) { return g_error.c_str(); }
 
-int32_t rtmi_version(void) { return 200; }
+int32_t rtmi_version(void) { return 300; }
 
 int64_t rtmi_num_substeps(float step_size, float radiation_velocity, float time_step,
                           int32_t cap) {
@@ -896,6 +1092,35 @@ int32_t rtmi_debug_rays(const float* j_map, const float* kappa_map, int32_t nx, 
   const hipError_t e = rtmi::launch_debug(a, s);
   if (e != hipSuccess) return hip_fail(e, "debug launch");
   g_error.clear();
+  return RTMI_OK;
+}
+
+int32_t rtmi_plan_create(int32_t nx, int32_t ny, int32_t nz, int32_t n_src, const float* source_pos,
+                         const int32_t* num_rays, const int32_t* substep_cap, int32_t n_bins,
+                         int64_t j_bin_stride, int64_t kappa_bin_stride, const float* kappa_scale,
+                         float step_size, float radiation_velocity, float time_step,
+                         const rtmi_options* opts, rtmi_plan** plan) {
+  if (!plan) return fail(RTMI_ERR_INVALID_ARG, "null plan pointer");
+  *plan = nullptr;
+  const Problem p{nullptr, j_bin_stride, nullptr, kappa_bin_stride,
+                  kappa_bin_stride ? nullptr : kappa_scale, n_bins, nx, ny, nz, n_src, source_pos,
+                  num_rays, substep_cap, step_size, radiation_velocity, time_step, nullptr, opts,
+                  nullptr};
+  return plan_create(p, plan);
+}
+
+int32_t rtmi_plan_execute(const rtmi_plan* plan, const float* j_maps, const float* kappa_maps,
+                          float* out_fields, void* stream) {
+  return plan_execute(plan, j_maps, kappa_maps, out_fields, static_cast<hipStream_t>(stream));
+}
+
+int64_t rtmi_plan_workspace_bytes(const rtmi_plan* plan) {
+  if (!plan) return fail(RTMI_ERR_INVALID_ARG, "null plan");
+  return static_cast<int64_t>(plan->ws_bytes);
+}
+
+int32_t rtmi_plan_destroy(rtmi_plan* plan) {
+  plan_release(plan);
   return RTMI_OK;
 }
 

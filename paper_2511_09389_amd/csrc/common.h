@@ -18,6 +18,7 @@ constexpr int kSeg = 4;              // substeps per recomputed segment of the a
 // Per-patch record of the direction table: min x, y, z, max x, y, z, -, -, cone axis
 // x, y, z, cos and sin of the cone's half-angle, -, -, -.
 constexpr int kPatchRec = 16;
+constexpr int kMaxParts = 64;        // work items (work-groups) sharing one output tile
 constexpr int kRowAlign = 8;         // workspace rows are padded to this many substeps
 constexpr int kXcds = 8;             // accelerator complex dies; work-groups go round-robin
 
@@ -84,9 +85,14 @@ struct TileArgs {
   int tiles_x, tiles_y, tiles_z;
   float ds;
   int n_src;
-  int accumulate;             // 0: store the tile; 1: add to the field already there
-  int parts;                  // work-groups per tile; > 1: each adds its share atomically
-                              // into a field the caller zeroed
+  // Schedule, written by the cost and schedule kernels and read by the tile kernel (the
+  // field must be zeroed before the tile kernel adds into it).
+  unsigned long long* tile_cost;  // [tiles] chunks (plus a per-pair charge) per tile
+  int2* item_map;                 // [tiles * kMaxParts] work item -> (tile, part | parts << 16)
+  int* item_total;                // number of work items
+  int* item_next;                 // next unclaimed work item
+  int* item_done;                 // work-groups finished (the last one rewinds the counters)
+  int item_chunks;                // target chunks per work item
   int pbegin[kMaxSrcPerLaunch + 1];  // prefix sums of patch counts over sources
   float sx[kMaxSrcPerLaunch], sy[kMaxSrcPerLaunch], sz[kMaxSrcPerLaunch];
   int nrays[kMaxSrcPerLaunch];
@@ -139,8 +145,11 @@ hipError_t launch_march(const MarchArgs& a, int n_bins, bool shared_j, bool dete
 hipError_t launch_debug(const DebugArgs& a, hipStream_t s);
 hipError_t launch_record(const RecordArgs& a, int n_bins, bool shared_j, bool deterministic,
                          int n_blocks, hipStream_t s);   // uses a.med when it is not null
-hipError_t launch_tile(const TileArgs& a, int n_bins, bool deterministic, bool nearest,
-                       int n_tiles, hipStream_t s);
+// Tile launches: the schedule (per-tile cost, work items; depends on the geometry only)
+// and the persistent tile kernel, which leaves the schedule ready for another run.
+hipError_t launch_tile_schedule(const TileArgs& a, int tiles, hipStream_t s);
+hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool deterministic, bool nearest,
+                           hipStream_t s);
 hipError_t launch_adjoint_record(const AdjointArgs& a, int n_blocks, hipStream_t s);
 hipError_t launch_interleave(const float* j, const float* kap, float2* med, long long cells,
                              hipStream_t s);

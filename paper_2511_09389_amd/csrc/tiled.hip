@@ -23,6 +23,8 @@ namespace rtmi {
 namespace {
 
 constexpr float kBig = 1.0e30f;
+constexpr int kCacheDevices = 64;
+constexpr float kCosConeLimit = -0.99913515f;   // cos(3.1)
 
 // 16-byte vector that needs only 8-byte alignment: two consecutive (j, kappa) voxels.
 typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
@@ -303,47 +305,270 @@ __device__ __forceinline__ TileAxis tile_axis(const Axis& A, int origin, int ext
   return r;
 }
 
-// The tile is accumulated in binary64 (or 64-bit fixed point in the deterministic mode):
-// a voxel next to a source collects thousands of deposits, and binary32 running sums of
-// that length drift by more than the binary32 field is allowed to differ from the exact one.
-// NEAREST: each sample adds its value to its nearest voxel only (the adjoint's kappa
-// deposit) instead of the trilinear stencil.
+// ---- output tiles ----
+//
+// A tile launch runs three kernels. tile_cost_kernel: per tile, the (source, patch) pairs
+// that can reach it and the chunks their rays bring (a chunk is the part of one ray's
+// substep range inside one aligned block of kChunk substeps). tile_schedule_kernel: each
+// tile becomes ceil(chunks / target) work items (at least one, at most kMaxParts); item
+// q of a tile with P items takes the tile's pairs with index = q mod P. tile_kernel: a
+// persistent grid whose work-groups claim items until none are left, so tiles next to
+// sources, several times the mean load, are shared by several compute units while light
+// tiles cost one item each.
+
+// One 16^3 output tile and the positions whose clamped stencil can reach it:
+// [x0 - 1, x0 + ex) per axis, unbounded on the box faces.
+struct TileGeom {
+  int x0, y0, z0, ex, ey, ez;
+  float Ax, Bx, Ay, By, Az, Bz;
+  bool interior;           // touches no box face: the cone test applies
+  float cx, cy, cz, rad;   // sphere around the tile widened by the stencil
+};
+
+__device__ __forceinline__ TileGeom tile_geom(const TileArgs& a, int t) {
+  TileGeom g;
+  const int tz = t % a.tiles_z, ty = (t / a.tiles_z) % a.tiles_y, tx = t / (a.tiles_z * a.tiles_y);
+  g.x0 = tx * kTile;
+  g.y0 = ty * kTile;
+  g.z0 = tz * kTile;
+  g.ex = min(kTile, a.nx - g.x0);
+  g.ey = min(kTile, a.ny - g.y0);
+  g.ez = min(kTile, a.nz - g.z0);
+  g.Ax = g.x0 == 0 ? -kBig : static_cast<float>(g.x0 - 1);
+  g.Bx = g.x0 + g.ex == a.nx ? kBig : static_cast<float>(g.x0 + g.ex);
+  g.Ay = g.y0 == 0 ? -kBig : static_cast<float>(g.y0 - 1);
+  g.By = g.y0 + g.ey == a.ny ? kBig : static_cast<float>(g.y0 + g.ey);
+  g.Az = g.z0 == 0 ? -kBig : static_cast<float>(g.z0 - 1);
+  g.Bz = g.z0 + g.ez == a.nz ? kBig : static_cast<float>(g.z0 + g.ez);
+  g.interior = g.x0 > 0 && g.y0 > 0 && g.z0 > 0 && g.x0 + g.ex < a.nx && g.y0 + g.ey < a.ny &&
+               g.z0 + g.ez < a.nz;
+  g.cx = static_cast<float>(g.x0) - 1.0f + 0.5f * static_cast<float>(g.ex + 1);
+  g.cy = static_cast<float>(g.y0) - 1.0f + 0.5f * static_cast<float>(g.ey + 1);
+  g.cz = static_cast<float>(g.z0) - 1.0f + 0.5f * static_cast<float>(g.ez + 1);
+  g.rad = 0.5f * sqrtf(static_cast<float>((g.ex + 1) * (g.ex + 1) + (g.ey + 1) * (g.ey + 1) +
+                                          (g.ez + 1) * (g.ez + 1))) + 0.01f;
+  return g;
+}
+
+// The launch's sources, staged in LDS once per work-group (the kernel-argument arrays
+// would otherwise be read with per-lane indices).
+struct SrcTable {
+  float4 pos[kMaxSrcPerLaunch];   // x, y, z, distance of the last substep
+  float marg[kMaxSrcPerLaunch];   // position tolerance: rounding of x_k and of 1/n
+  int pbegin[kMaxSrcPerLaunch + 1];
+  int nsub[kMaxSrcPerLaunch];
+  int nrays[kMaxSrcPerLaunch];
+};
+
+__device__ __forceinline__ void load_sources(const TileArgs& a, SrcTable& S, int tid) {
+  if (tid < a.n_src) {
+    const float sx = a.sx[tid], sy = a.sy[tid], sz = a.sz[tid];
+    const float tmax = sample_distance(a.nsub[tid] - 1, a.ds);
+    S.pos[tid] = make_float4(sx, sy, sz, tmax);
+    S.marg[tid] = 5.0e-7f * (fmaxf(fabsf(sx), fmaxf(fabsf(sy), fabsf(sz))) + tmax + 2.0f) + 1.0e-6f;
+    S.nsub[tid] = a.nsub[tid];
+    S.nrays[tid] = a.nrays[tid];
+  }
+  if (tid <= a.n_src) S.pbegin[tid] = a.pbegin[tid];
+}
+
+// Source s of pair p: pbegin[s] <= p < pbegin[s + 1].
+__device__ __forceinline__ int pair_source(const SrcTable& S, int n_src, int p) {
+  int lo = 0, hi = n_src;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (S.pbegin[mid] <= p) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// Can a ray of patch `patch` of source s reach the tile? The bounding box of the patch's
+// segments [0, tmax] (its direction bounds are exact), then, for interior tiles, the
+// cone holding the patch's directions against the sphere around the widened tile.
+__device__ __forceinline__ bool pair_reaches(const TileArgs& a, const SrcTable& S, const TileGeom& g,
+                                             int s, int patch) {
+  const float4 P = S.pos[s];
+  const float sx = P.x, sy = P.y, sz = P.z, tmax = P.w, m = S.marg[s];
+  const float* pb = a.pbounds[s] + static_cast<long long>(patch) * kPatchRec;
+  bool reach = !(sx + fmaxf(0.0f, tmax * pb[3]) + m < g.Ax || sx + fminf(0.0f, tmax * pb[0]) - m >= g.Bx ||
+                 sy + fmaxf(0.0f, tmax * pb[4]) + m < g.Ay || sy + fminf(0.0f, tmax * pb[1]) - m >= g.By ||
+                 sz + fmaxf(0.0f, tmax * pb[5]) + m < g.Az || sz + fminf(0.0f, tmax * pb[2]) - m >= g.Bz);
+  if (reach && g.interior) {
+    const float vx = g.cx - sx, vy = g.cy - sy, vz = g.cz - sz;
+    const float dist = sqrtf(vx * vx + vy * vy + vz * vz);
+    const float rad = g.rad + m;
+    if (dist - rad > tmax + 1.0f) {
+      reach = false;
+    } else if (dist > rad) {
+      // the sphere subtends a half-angle alpha (sin alpha = rad / dist); a direction within
+      // beta of the axis can meet it only if its angle to the centre is below beta + alpha
+      const float sa = fminf(1.0f, rad / dist), ca = sqrtf(fmaxf(0.0f, 1.0f - sa * sa));
+      const float cb = pb[11], sb = pb[12];
+      const float cos_sum = cb * ca - sb * sa, sin_sum = sb * ca + cb * sa;
+      // (beta + alpha beyond ~3.1 rad: the cone covers nearly every direction, keep the pair)
+      if (sin_sum >= 0.0f && cos_sum > kCosConeLimit) {
+        const float c = (pb[8] * vx + pb[9] * vy + pb[10] * vz) / dist;
+        reach = c >= cos_sum - 1.0e-3f;
+      }
+    }
+  }
+  return reach;
+}
+
+// Substep range [ka, kb] of one ray that can touch the tile (kb < ka: none) and its
+// direction (zero for a lane past the source's last ray).
+__device__ __forceinline__ void ray_range(const TileArgs& a, const SrcTable& S, const TileGeom& g,
+                                          int s, int ray, int& ka, int& kb, float4& d) {
+  ka = 0;
+  kb = -1;
+  d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (ray >= S.nrays[s]) return;
+  const float4 P = S.pos[s];
+  const float sx = P.x, sy = P.y, sz = P.z, tmax = P.w, m = S.marg[s];
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  d = a.dirs[s][ray];
+  const float ix = __builtin_amdgcn_rcpf(d.x), iy = __builtin_amdgcn_rcpf(d.y),
+              iz = __builtin_amdgcn_rcpf(d.z);
+  float t0 = 0.0f, t1 = tmax;
+  clip_axis(sx, d.x, ix, g.Ax - m, g.Bx + m, t0, t1);
+  clip_axis(sy, d.y, iy, g.Ay - m, g.By + m, t0, t1);
+  clip_axis(sz, d.z, iz, g.Az - m, g.Bz + m, t0, t1);
+  // Samples collapsed onto a corner voxel (clamped along all three axes) belong to the
+  // record phase. Along a straight ray each axis is unclamped on one interval of t; only
+  // the hull of those intervals can hold samples for the tiles.
+  float h0 = kBig, h1 = -kBig, u0, u1;
+  if (nx > 1) {
+    axis_span(sx, d.x, ix, -m, static_cast<float>(nx - 1) + m, u0, u1);
+    if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
+  }
+  if (ny > 1) {
+    axis_span(sy, d.y, iy, -m, static_cast<float>(ny - 1) + m, u0, u1);
+    if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
+  }
+  if (nz > 1) {
+    axis_span(sz, d.z, iz, -m, static_cast<float>(nz - 1) + m, u0, u1);
+    if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
+  }
+  t0 = fmaxf(t0, h0);
+  t1 = fminf(t1, h1);
+  if (t0 <= t1) {
+    // one substep of margin on each side covers the rounding of t = k ds
+    ka = max(0, static_cast<int>(floorf(t0 / a.ds)) - 1);
+    kb = min(S.nsub[s] - 1, static_cast<int>(fminf(ceilf(t1 / a.ds), 1.0e8f)) + 1);
+  }
+}
+
+__device__ __forceinline__ int range_chunks(int ka, int kb) {
+  return kb >= ka ? kb / kChunk - ka / kChunk + 1 : 0;
+}
+
+// Per tile: chunks of all rays that can reach it, plus kPairCost per reaching pair for
+// the pair's own set-up. One wave per pair when counting.
+constexpr int kCostThreads = 256;
+constexpr int kPairCost = 16;
+
+__global__ void __launch_bounds__(kCostThreads) tile_cost_kernel(const TileArgs a) {
+  // block (t, q): tile t, pairs [q kCostThreads, (q + 1) kCostThreads); the tile's total
+  // is summed into tile_cost[t], zeroed beforehand
+  __shared__ SrcTable S;
+  __shared__ int list[kCostThreads];
+  __shared__ int count;
+  __shared__ unsigned long long total;
+  const int tid = static_cast<int>(threadIdx.x), wave = tid >> 6, lane = tid & 63;
+  load_sources(a, S, tid);
+  if (tid == 0) {
+    count = 0;
+    total = 0ull;
+  }
+  const int t = static_cast<int>(blockIdx.x);
+  const TileGeom g = tile_geom(a, t);
+  const int npairs = a.pbegin[a.n_src];
+  __syncthreads();
+  const int p = static_cast<int>(blockIdx.y) * kCostThreads + tid;
+  if (p < npairs) {
+    const int s = pair_source(S, a.n_src, p);
+    if (pair_reaches(a, S, g, s, p - S.pbegin[s])) list[atomicAdd(&count, 1)] = p;
+  }
+  __syncthreads();
+  unsigned long long sum = 0;
+  for (int i = wave; i < count; i += kCostThreads / 64) {
+    const int q = list[i];
+    const int s = pair_source(S, a.n_src, q);
+    int ka, kb;
+    float4 d;
+    ray_range(a, S, g, s, (q - S.pbegin[s]) * kPatch + lane, ka, kb, d);
+    int c = range_chunks(ka, kb);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+    sum += c > 0 ? static_cast<unsigned long long>(c + kPairCost) : 0ull;
+  }
+  if (lane == 0 && sum) atomicAdd(&total, sum);
+  __syncthreads();
+  if (tid == 0 && total) atomicAdd(a.tile_cost + t, total);
+}
+
+// One work-group: items per tile, their prefix sums and the item -> (tile, part) map;
+// also resets the claim counter of the tile kernel.
+constexpr int kScheduleThreads = 1024;
+
+__global__ void __launch_bounds__(kScheduleThreads) tile_schedule_kernel(const TileArgs a, int n_tiles) {
+  __shared__ int w_sum[kScheduleThreads / 64];
+  __shared__ int carry;
+  const int tid = static_cast<int>(threadIdx.x), wave = tid >> 6, lane = tid & 63;
+  if (tid == 0) carry = 0;
+  __syncthreads();
+  for (int t0 = 0; t0 < n_tiles; t0 += kScheduleThreads) {
+    const int t = t0 + tid;
+    int items = 0;
+    if (t < n_tiles) {
+      const unsigned long long c = a.tile_cost[t];
+      const unsigned long long want = (c + a.item_chunks - 1) / a.item_chunks;
+      items = static_cast<int>(want < 1 ? 1 : (want > kMaxParts ? kMaxParts : want));
+    }
+    int incl = items;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(incl, off, 64);
+      if (lane >= off) incl += o;
+    }
+    if (lane == 63) w_sum[wave] = incl;
+    __syncthreads();
+    int base = carry;
+    for (int w = 0; w < wave; ++w) base += w_sum[w];
+    const int begin = base + incl - items;
+    for (int q = 0; q < items; ++q) a.item_map[begin + q] = make_int2(t, q | (items << 16));
+    __syncthreads();
+    if (tid == kScheduleThreads - 1) carry = begin + items;
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *a.item_total = carry;
+    *a.item_next = 0;
+    *a.item_done = 0;
+  }
+}
+
+
 // Lanes per tile work-group. 512 lets two work-groups share a compute unit (one bin), so
 // one can compute while the other waits at a barrier or on memory.
 template <int NB>
 constexpr int tile_threads() { return kTileThreads; }
 
+// The tile is accumulated in binary64 (or 64-bit fixed point in the deterministic mode):
+// a voxel next to a source collects thousands of deposits, and binary32 running sums of
+// that length drift by more than the binary32 field is allowed to differ from the exact one.
+// NEAREST: each sample adds its value to its nearest voxel only (the adjoint's kappa
+// deposit) instead of the trilinear stencil.
 template <int NB, bool DET, bool NEAREST>
 __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs a) {
   using T = typename std::conditional<DET, unsigned long long, double>::type;
-  __shared__ T acc[NB][kTileVox];
-  const int tid = static_cast<int>(threadIdx.x);
   constexpr int kThreads = tile_threads<NB>();
-  for (int i = tid; i < NB * kTileVox; i += kThreads) (&acc[0][0])[i] = T(0);
-
-  // work-group -> (tile, part): part q of a tile takes the pairs with index = q mod parts
-  const int t = static_cast<int>(blockIdx.x) / a.parts;
-  const int part = static_cast<int>(blockIdx.x) % a.parts;
-  const int tz = t % a.tiles_z, ty = (t / a.tiles_z) % a.tiles_y, tx = t / (a.tiles_z * a.tiles_y);
-  const int x0 = tx * kTile, y0 = ty * kTile, z0 = tz * kTile;
-  const int ex = min(kTile, a.nx - x0), ey = min(kTile, a.ny - y0), ez = min(kTile, a.nz - z0);
-  // positions whose clamped stencil can reach the tile: [x0 - 1, x0 + ex), unbounded on faces
-  const float Ax = x0 == 0 ? -kBig : static_cast<float>(x0 - 1);
-  const float Bx = x0 + ex == a.nx ? kBig : static_cast<float>(x0 + ex);
-  const float Ay = y0 == 0 ? -kBig : static_cast<float>(y0 - 1);
-  const float By = y0 + ey == a.ny ? kBig : static_cast<float>(y0 + ey);
-  const float Az = z0 == 0 ? -kBig : static_cast<float>(z0 - 1);
-  const float Bz = z0 + ez == a.nz ? kBig : static_cast<float>(z0 + ez);
-  const int nx = a.nx, ny = a.ny, nz = a.nz;
-  const float ds = a.ds;
-  double det_scale = 0.0;
-  if constexpr (DET) det_scale = *a.det_scale;
-  const int wave = tid >> 6, lane = tid & 63;
   constexpr int kWaves = kThreads / 64;
+  __shared__ T acc[NB][kTileVox];
+  __shared__ SrcTable S;
   // Records of one batch: record r holds ray (r mod 64) of the pair taken by wave r / 64,
-  // with its substep range, direction and the exclusive prefix of the chunk counts. A
-  // chunk is the part of one ray's range inside one aligned block of kChunk substeps, so
-  // its recorded values arrive in aligned 16-byte loads.
+  // with its substep range, direction and the exclusive prefix of the chunk counts.
   __shared__ int r_excl[kThreads + 1];
   __shared__ int r_k0[kThreads];
   __shared__ int r_k1[kThreads];
@@ -352,255 +577,210 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
   __shared__ float4 b_src[kWaves];        // source position of each wave's pair
   __shared__ long long b_row[kWaves];     // workspace offset of the pair's first ray
   __shared__ int b_vstride[kWaves];
-  const int npairs = a.pbegin[a.n_src];
-  // Tile-interior test for the cone cull: the tile widened by the stencil, as a sphere.
-  const bool interior = x0 > 0 && y0 > 0 && z0 > 0 && x0 + ex < nx && y0 + ey < ny && z0 + ez < nz;
-  const float tcx = static_cast<float>(x0) - 1.0f + 0.5f * static_cast<float>(ex + 1);
-  const float tcy = static_cast<float>(y0) - 1.0f + 0.5f * static_cast<float>(ey + 1);
-  const float tcz = static_cast<float>(z0) - 1.0f + 0.5f * static_cast<float>(ez + 1);
-  const float trad = 0.5f * sqrtf(static_cast<float>((ex + 1) * (ex + 1) + (ey + 1) * (ey + 1) +
-                                                     (ez + 1) * (ez + 1))) + 0.01f;
-  // (source, patch) pairs are culled by the whole work-group, a block at a time; the pairs
-  // that may reach the tile go to a list that is then expanded in batches.
   __shared__ int pair_list[kThreads];
   __shared__ int pair_count;
-  for (int blk0 = 0; blk0 < npairs; blk0 += kThreads) {
-    if (tid == 0) pair_count = 0;
+  __shared__ int2 claimed;
+  const int tid = static_cast<int>(threadIdx.x);
+  const int wave = tid >> 6, lane = tid & 63;
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const float ds = a.ds;
+  double det_scale = 0.0;
+  if constexpr (DET) det_scale = *a.det_scale;
+  load_sources(a, S, tid);
+  const int npairs = a.pbegin[a.n_src];
+  const int n_items = *a.item_total;
+
+  for (;;) {
+    if (tid == 0) {
+      const int item = atomicAdd(a.item_next, 1);
+      claimed = item < n_items ? a.item_map[item] : make_int2(-1, 0);
+    }
+    for (int i = tid; i < NB * kTileVox; i += kThreads) (&acc[0][0])[i] = T(0);
     __syncthreads();
-    {
-      const int p = blk0 + tid;
-      if (p < npairs && p % a.parts == part) {
-        int lo = 0, hi = a.n_src;   // source s: pbegin[s] <= p < pbegin[s + 1]
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (a.pbegin[mid] <= p) lo = mid;
-          else hi = mid;
+    const int t = claimed.x;
+    if (t < 0) {
+      // the last work-group out rewinds the claim counter, so the same schedule serves
+      // the next launch (every work-group has made its final claim by then)
+      if (tid == 0 && atomicAdd(a.item_done, 1) == static_cast<int>(gridDim.x) - 1) {
+        atomicExch(a.item_next, 0);
+        atomicExch(a.item_done, 0);
+      }
+      break;
+    }
+    const int part = claimed.y & 0xffff, parts = claimed.y >> 16;
+    const TileGeom g = tile_geom(a, t);
+    const int x0 = g.x0, y0 = g.y0, z0 = g.z0, ex = g.ex, ey = g.ey, ez = g.ez;
+
+    // The item's pairs (index = part mod parts) that can reach the tile are listed a
+    // block at a time, then expanded kWaves at a time: each wave turns one pair's 64 rays
+    // into records, a work-group-wide prefix sum over their chunk counts follows, and
+    // every lane then takes chunks of any record, so a heavy pair is shared by the whole
+    // work-group instead of one wavefront.
+    for (int blk0 = 0; blk0 < npairs; blk0 += kThreads * parts) {
+      if (tid == 0) pair_count = 0;
+      __syncthreads();
+      {
+        const int p = blk0 + tid * parts + part;
+        if (p < npairs) {
+          const int s = pair_source(S, a.n_src, p);
+          if (pair_reaches(a, S, g, s, p - S.pbegin[s])) pair_list[atomicAdd(&pair_count, 1)] = p;
         }
-        const int s = lo;
-        const int patch = p - a.pbegin[s];
-        const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
-        const float tmax = sample_distance(a.nsub[s] - 1, ds);
-        const float m = 5.0e-7f * (fmaxf(fabsf(sx), fmaxf(fabsf(sy), fabsf(sz))) + tmax + 2.0f) + 1.0e-6f;
-        const float* pb = a.pbounds[s] + patch * kPatchRec;
-        // bounding box of the patch's ray segments [0, tmax] (direction bounds are exact)
-        bool reach = !(sx + fmaxf(0.0f, tmax * pb[3]) + m < Ax || sx + fminf(0.0f, tmax * pb[0]) - m >= Bx ||
-                       sy + fmaxf(0.0f, tmax * pb[4]) + m < Ay || sy + fminf(0.0f, tmax * pb[1]) - m >= By ||
-                       sz + fmaxf(0.0f, tmax * pb[5]) + m < Az || sz + fminf(0.0f, tmax * pb[2]) - m >= Bz);
-        if (reach && interior) {
-          // cone of the patch's directions against the sphere around the widened tile
-          const float vx = tcx - sx, vy = tcy - sy, vz = tcz - sz;
-          const float dist = sqrtf(vx * vx + vy * vy + vz * vz);
-          const float rad = trad + m;
-          if (dist - rad > tmax + 1.0f) {
-            reach = false;
-          } else if (dist > rad) {
-            const float beta = acosf(fminf(1.0f, fmaxf(-1.0f, pb[11])));
-            const float alpha = asinf(fminf(1.0f, rad / dist));
-            if (beta + alpha < 3.1f) {
-              const float c = (pb[8] * vx + pb[9] * vy + pb[10] * vz) / dist;
-              reach = c >= cosf(beta + alpha) - 1.0e-3f;
+      }
+      __syncthreads();
+      const int n_listed = pair_count;
+      for (int b0 = 0; b0 < n_listed; b0 += kWaves) {
+        const int it = b0 + wave;
+        int ka = 0, kb = -1;
+        float4 d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (it < n_listed) {
+          const int p = pair_list[it];
+          const int s = pair_source(S, a.n_src, p);
+          const int patch = p - S.pbegin[s];
+          if (lane == 0) {
+            b_src[wave] = S.pos[s];
+            b_row[wave] = a.vbase[s] + static_cast<long long>(patch) * kPatch * a.vstride[s];
+            b_vstride[wave] = a.vstride[s];
+          }
+          ray_range(a, S, g, s, patch * kPatch + lane, ka, kb, d);
+        }
+        const int chunks = range_chunks(ka, kb);
+        // inclusive prefix sum of the chunk counts across the wavefront
+        int incl = chunks;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+          const int o = __shfl_up(incl, off, 64);
+          if (lane >= off) incl += o;
+        }
+        if (lane == 63) w_tot[wave] = incl;
+        r_k0[tid] = ka;
+        r_k1[tid] = kb;
+        r_dir[tid] = d;
+        __syncthreads();
+        int off = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kWaves; ++w) {
+          const int v = w_tot[w];
+          off += w < wave ? v : 0;
+          total += v;
+        }
+        r_excl[tid + 1] = off + incl;
+        if (tid == 0) r_excl[0] = 0;
+        __syncthreads();
+
+        for (int i = tid; i < total; i += kThreads) {
+          // owner record o: r_excl[o] <= i < r_excl[o + 1]
+          int lo = 0, hi = kThreads;
+          while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (r_excl[mid] <= i) lo = mid;
+            else hi = mid;
+          }
+          const int o = lo, ow = o >> 6;
+          const int ka_o = r_k0[o], kb_o = r_k1[o];
+          const int kblk = (ka_o / kChunk + (i - r_excl[o])) * kChunk;
+          const int kbeg = max(ka_o, kblk), kend = min(kb_o, kblk + kChunk - 1);
+          const float4 dd = r_dir[o];
+          const float4 src = b_src[ow];
+          const float* vrow = a.V + b_row[ow] + static_cast<long long>(o & 63) * b_vstride[ow];
+          // the chunk's recorded values, fetched before any of them is needed
+          float vv[NB][kChunk];
+#pragma unroll
+          for (int b = 0; b < NB; ++b) {
+            const float4* src4 = reinterpret_cast<const float4*>(vrow + b * a.v_bin_stride + kblk);
+#pragma unroll
+            for (int q = 0; q < kChunk / 4; ++q) {
+              const float4 f = src4[q];
+              vv[b][4 * q] = f.x;
+              vv[b][4 * q + 1] = f.y;
+              vv[b][4 * q + 2] = f.z;
+              vv[b][4 * q + 3] = f.w;
+            }
+          }
+          // Each sample adds its eight weighted corners straight to the tile: no per-lane
+          // state to flush, and no branch that diverges with where each ray stands.
+#pragma unroll
+          for (int t = 0; t < kChunk; ++t) {
+            const int k = kblk + t;
+            const float dist = sample_distance(k, ds);
+            const float x = sample_axis(src.x, dist, dd.x);
+            const float y = sample_axis(src.y, dist, dd.y);
+            const float z = sample_axis(src.z, dist, dd.z);
+            // outside this ray's range for the tile, or collapsed onto one corner voxel of
+            // the box (summed by the record phase)
+            // (bitwise tests: one branch per sample, not a chain of short-circuit branches)
+            const int clamped = static_cast<int>(axis_clamped(x, nx)) + static_cast<int>(axis_clamped(y, ny)) +
+                                static_cast<int>(axis_clamped(z, nz));
+            if ((k < kbeg) | (k > kend) | (clamped == 3)) continue;
+            const Axis X = axis_stencil(x, nx);
+            const Axis Y = axis_stencil(y, ny);
+            const Axis Z = axis_stencil(z, nz);
+            if constexpr (NEAREST) {
+              const int lx = X.nearest - x0, ly = Y.nearest - y0, lz = Z.nearest - z0;
+              if ((static_cast<unsigned>(lx) >= static_cast<unsigned>(ex)) |
+                  (static_cast<unsigned>(ly) >= static_cast<unsigned>(ey)) |
+                  (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
+                continue;
+              const int li = (lx * kTile + ly) * kTile + lz;
+#pragma unroll
+              for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][t], det_scale));
+            } else {
+              const TileAxis tx = tile_axis(X, x0, ex, kTile * kTile);
+              const TileAxis ty = tile_axis(Y, y0, ey, kTile);
+              const TileAxis tz = tile_axis(Z, z0, ez, 1);
+              if (!(tx.any & ty.any & tz.any)) continue;
+#pragma unroll
+              for (int c = 0; c < 8; ++c) {
+                const float w = (tx.w[c >> 2] * ty.w[(c >> 1) & 1]) * tz.w[c & 1];
+                const int li = tx.off[c >> 2] + ty.off[(c >> 1) & 1] + tz.off[c & 1];
+#pragma unroll
+                for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][t] * w, det_scale));
+              }
             }
           }
         }
-        if (reach) pair_list[atomicAdd(&pair_count, 1)] = p;
+        __syncthreads();   // the records are rewritten by the next batch
       }
     }
-    __syncthreads();
-    const int n_items = pair_count;
-    // The listed pairs are expanded kWaves at a time: each wave turns one pair's 64 rays
-    // into records (substep range, direction), a work-group-wide prefix sum over the
-    // records' chunk counts follows, and then every lane takes chunks of any record, so
-    // a heavy pair is shared by the whole work-group instead of one wavefront.
-    for (int b0 = 0; b0 < n_items; b0 += kWaves) {
-      const int it = b0 + wave;
-      int ka = 0, kb = -1;
-      float4 d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-      if (it < n_items) {
-        const int p = pair_list[it];
-        int s = 0;
-        while (s + 1 < a.n_src && p >= a.pbegin[s + 1]) ++s;
-        const int patch = p - a.pbegin[s];
-        const int nsub = a.nsub[s];
-        const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
-        const float tmax = sample_distance(nsub - 1, ds);
-        const float m = 5.0e-7f * (fmaxf(fabsf(sx), fmaxf(fabsf(sy), fabsf(sz))) + tmax + 2.0f) + 1.0e-6f;
-        if (lane == 0) {
-          b_src[wave] = make_float4(sx, sy, sz, 0.0f);
-          b_row[wave] = a.vbase[s] + static_cast<long long>(patch) * kPatch * a.vstride[s];
-          b_vstride[wave] = a.vstride[s];
-        }
-        // this lane's ray: the substep range that can reach the tile
-        const int ray = patch * kPatch + lane;
-        if (ray < a.nrays[s]) {
-          d = a.dirs[s][ray];
-          const float ix = __builtin_amdgcn_rcpf(d.x), iy = __builtin_amdgcn_rcpf(d.y),
-                      iz = __builtin_amdgcn_rcpf(d.z);
-          float t0 = 0.0f, t1 = tmax;
-          clip_axis(sx, d.x, ix, Ax - m, Bx + m, t0, t1);
-          clip_axis(sy, d.y, iy, Ay - m, By + m, t0, t1);
-          clip_axis(sz, d.z, iz, Az - m, Bz + m, t0, t1);
-          // Samples collapsed onto a corner voxel (clamped along all three axes) belong to
-          // the record phase. Along a straight ray each axis is unclamped on one interval
-          // of t; only the hull of those intervals can hold samples for this kernel.
-          float h0 = kBig, h1 = -kBig, u0, u1;
-          if (nx > 1) {
-            axis_span(sx, d.x, ix, -m, static_cast<float>(nx - 1) + m, u0, u1);
-            if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
-          }
-          if (ny > 1) {
-            axis_span(sy, d.y, iy, -m, static_cast<float>(ny - 1) + m, u0, u1);
-            if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
-          }
-          if (nz > 1) {
-            axis_span(sz, d.z, iz, -m, static_cast<float>(nz - 1) + m, u0, u1);
-            if (u0 <= u1) { h0 = fminf(h0, u0); h1 = fmaxf(h1, u1); }
-          }
-          t0 = fmaxf(t0, h0);
-          t1 = fminf(t1, h1);
-          if (t0 <= t1) {
-            // one substep of margin on each side covers the rounding of t = k ds
-            ka = max(0, static_cast<int>(floorf(t0 / ds)) - 1);
-            kb = min(nsub - 1, static_cast<int>(fminf(ceilf(t1 / ds), 1.0e8f)) + 1);
-          }
-        }
-      }
-      const int chunks = kb >= ka ? kb / kChunk - ka / kChunk + 1 : 0;
-      // inclusive prefix sum of the chunk counts across the wavefront
-      int incl = chunks;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int o = __shfl_up(incl, off, 64);
-        if (lane >= off) incl += o;
-      }
-      if (lane == 63) w_tot[wave] = incl;
-      r_k0[tid] = ka;
-      r_k1[tid] = kb;
-      r_dir[tid] = d;
-      __syncthreads();
-      int off = 0, total = 0;
-#pragma unroll
-      for (int w = 0; w < kWaves; ++w) {
-        const int v = w_tot[w];
-        off += w < wave ? v : 0;
-        total += v;
-      }
-      r_excl[tid + 1] = off + incl;
-      if (tid == 0) r_excl[0] = 0;
-      __syncthreads();
 
-      for (int i = tid; i < total; i += kThreads) {
-        // owner record o: r_excl[o] <= i < r_excl[o + 1]
-        int lo = 0, hi = kThreads;
-        while (hi - lo > 1) {
-          const int mid = (lo + hi) >> 1;
-          if (r_excl[mid] <= i) lo = mid;
-          else hi = mid;
-        }
-        const int o = lo, ow = o >> 6;
-        const int ka_o = r_k0[o], kb_o = r_k1[o];
-        const int kblk = (ka_o / kChunk + (i - r_excl[o])) * kChunk;
-        const int kbeg = max(ka_o, kblk), kend = min(kb_o, kblk + kChunk - 1);
-        const float4 dd = r_dir[o];
-        const float4 src = b_src[ow];
-        const float* vrow = a.V + b_row[ow] + static_cast<long long>(o & 63) * b_vstride[ow];
-        // the chunk's recorded values, fetched before any of them is needed
-        float vv[NB][kChunk];
+    // the corner voxels of the box also receive the record phase's per-corner sums
+    for (int i = tid; i < kTileVox; i += kThreads) {
+      const int lx = i / (kTile * kTile), ly = (i / kTile) % kTile, lz = i % kTile;
+      if (lx >= ex || ly >= ey || lz >= ez) continue;
+      const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+      const long long voxel = (static_cast<long long>(gx) * ny + gy) * nz + gz;
+      const bool cx_any = (gx == 0 || gx == nx - 1), cy_any = (gy == 0 || gy == ny - 1),
+                 cz_any = (gz == 0 || gz == nz - 1);
 #pragma unroll
-        for (int b = 0; b < NB; ++b) {
-          const float4* src4 = reinterpret_cast<const float4*>(vrow + b * a.v_bin_stride + kblk);
-#pragma unroll
-          for (int q = 0; q < kChunk / 4; ++q) {
-            const float4 f = src4[q];
-            vv[b][4 * q] = f.x;
-            vv[b][4 * q + 1] = f.y;
-            vv[b][4 * q + 2] = f.z;
-            vv[b][4 * q + 3] = f.w;
-          }
-        }
-        // Each sample adds its eight weighted corners straight to the tile: no per-lane
-        // state to flush, and no branch that diverges with where each ray stands.
-#pragma unroll
-        for (int t = 0; t < kChunk; ++t) {
-          const int k = kblk + t;
-          const float dist = sample_distance(k, ds);
-          const float x = sample_axis(src.x, dist, dd.x);
-          const float y = sample_axis(src.y, dist, dd.y);
-          const float z = sample_axis(src.z, dist, dd.z);
-          // outside this ray's range for the tile, or collapsed onto one corner voxel of
-          // the box (summed by the record phase)
-          // (bitwise tests: one branch per sample, not a chain of short-circuit branches)
-          const int clamped = static_cast<int>(axis_clamped(x, nx)) + static_cast<int>(axis_clamped(y, ny)) +
-                              static_cast<int>(axis_clamped(z, nz));
-          if ((k < kbeg) | (k > kend) | (clamped == 3)) continue;
-          const Axis X = axis_stencil(x, nx);
-          const Axis Y = axis_stencil(y, ny);
-          const Axis Z = axis_stencil(z, nz);
-          if constexpr (NEAREST) {
-            const int lx = X.nearest - x0, ly = Y.nearest - y0, lz = Z.nearest - z0;
-            if ((static_cast<unsigned>(lx) >= static_cast<unsigned>(ex)) |
-                (static_cast<unsigned>(ly) >= static_cast<unsigned>(ey)) |
-                (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
-              continue;
-            const int li = (lx * kTile + ly) * kTile + lz;
-#pragma unroll
-            for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][t], det_scale));
-          } else {
-            const TileAxis tx = tile_axis(X, x0, ex, kTile * kTile);
-            const TileAxis ty = tile_axis(Y, y0, ey, kTile);
-            const TileAxis tz = tile_axis(Z, z0, ez, 1);
-            if (!(tx.any & ty.any & tz.any)) continue;
-#pragma unroll
-            for (int c = 0; c < 8; ++c) {
-              const float w = (tx.w[c >> 2] * ty.w[(c >> 1) & 1]) * tz.w[c & 1];
-              const int li = tx.off[c >> 2] + ty.off[(c >> 1) & 1] + tz.off[c & 1];
-#pragma unroll
-              for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][t] * w, det_scale));
+      for (int b = 0; b < NB; ++b) {
+        T val = acc[b][i];
+        if (cx_any && cy_any && cz_any && part == 0) {
+          for (int c = 0; c < 8; ++c) {
+            const int vx = (c & 4) ? nx - 1 : 0, vy = (c & 2) ? ny - 1 : 0, vz = (c & 1) ? nz - 1 : 0;
+            if (vx == gx && vy == gy && vz == gz) {
+              if constexpr (DET) val += a.corner_q[b * 8 + c];
+              else val += a.corner[b * 8 + c];
             }
           }
         }
-      }
-      __syncthreads();   // the records are rewritten by the next batch
-    }
-  }
-  __syncthreads();
-
-  // the corner voxels of the box also receive the record phase's per-corner sums
-  for (int i = tid; i < kTileVox; i += kThreads) {
-    const int lx = i / (kTile * kTile), ly = (i / kTile) % kTile, lz = i % kTile;
-    if (lx >= ex || ly >= ey || lz >= ez) continue;
-    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-    const long long voxel = (static_cast<long long>(gx) * ny + gy) * nz + gz;
-    const bool cx_any = (gx == 0 || gx == nx - 1), cy_any = (gy == 0 || gy == ny - 1),
-               cz_any = (gz == 0 || gz == nz - 1);
-#pragma unroll
-    for (int b = 0; b < NB; ++b) {
-      T val = acc[b][i];
-      if (cx_any && cy_any && cz_any && part == 0) {
-        for (int c = 0; c < 8; ++c) {
-          const int vx = (c & 4) ? nx - 1 : 0, vy = (c & 2) ? ny - 1 : 0, vz = (c & 1) ? nz - 1 : 0;
-          if (vx == gx && vy == gy && vz == gz) {
-            if constexpr (DET) val += a.corner_q[b * 8 + c];
-            else val += a.corner[b * 8 + c];
+        // The field was zeroed before the launch. A tile served by one item adds its sum
+        // with a plain read-modify-write; items sharing a tile add atomically (consecutive
+        // lanes hold consecutive z, so the adds of a wave coalesce).
+        if constexpr (DET) {
+          unsigned long long* o = a.out_q + b * a.out_stride + voxel;
+          if (val != 0ull) {
+            if (parts > 1) atomicAdd(o, val);
+            else *o += val;
+          }
+        } else {
+          float* o = a.out + b * a.out_stride + voxel;
+          if (val != 0.0) {
+            if (parts > 1) unsafeAtomicAdd(o, static_cast<float>(val));
+            else *o = static_cast<float>(static_cast<double>(*o) + val);
           }
         }
       }
-      if constexpr (DET) {
-        unsigned long long* o = a.out_q + b * a.out_stride + voxel;
-        if (a.parts > 1) {
-          if (val != 0ull) atomicAdd(o, val);
-        } else {
-          *o = a.accumulate ? *o + val : val;
-        }
-      } else {
-        float* o = a.out + b * a.out_stride + voxel;
-        if (a.parts > 1) {
-          // consecutive lanes hold consecutive z: the adds of a wave coalesce
-          if (val != 0.0) unsafeAtomicAdd(o, static_cast<float>(val));
-        } else {
-          *o = static_cast<float>(a.accumulate ? static_cast<double>(*o) + val : val);
-        }
-      }
     }
+    __syncthreads();   // the tile is cleared for the next item
   }
 }
 
@@ -621,17 +801,36 @@ hipError_t launch_record_nb(const RecordArgs& a, bool shared_j, bool det, int bl
   return hipGetLastError();
 }
 
-template <int NB>
-hipError_t launch_tile_nb(const TileArgs& a, bool det, bool nearest, int tiles, hipStream_t s) {
-  const dim3 g(tiles), b(tile_threads<NB>());
-  if (nearest) {
-    if (det) hipLaunchKernelGGL((tile_kernel<NB, true, true>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((tile_kernel<NB, false, true>), g, b, 0, s, a);
-  } else {
-    if (det) hipLaunchKernelGGL((tile_kernel<NB, true, false>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((tile_kernel<NB, false, false>), g, b, 0, s, a);
+// Work-groups of a persistent grid: as many as fit on the device at once (any surplus
+// simply starts later and finds no work left).
+template <typename K>
+int resident_groups(K kernel, int threads, int* cache) {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kCacheDevices) dev = 0;
+  if (cache[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+      per_cu = 1;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 1;
+    cache[dev] = per_cu * cus;
   }
+  return cache[dev];
+}
+
+template <int NB, bool DET, bool NEAREST>
+hipError_t launch_tile_variant(const TileArgs& a, hipStream_t s) {
+  static int cache[kCacheDevices] = {0};   // one per kernel variant and device
+  const auto kernel = tile_kernel<NB, DET, NEAREST>;
+  const int groups = resident_groups(kernel, tile_threads<NB>(), cache);
+  hipLaunchKernelGGL(kernel, dim3(groups), dim3(tile_threads<NB>()), 0, s, a);
   return hipGetLastError();
+}
+
+template <int NB>
+hipError_t launch_tile_nb(const TileArgs& a, bool det, bool nearest, hipStream_t s) {
+  if (nearest) return det ? launch_tile_variant<NB, true, true>(a, s) : launch_tile_variant<NB, false, true>(a, s);
+  return det ? launch_tile_variant<NB, true, false>(a, s) : launch_tile_variant<NB, false, false>(a, s);
 }
 
 }  // namespace
@@ -656,13 +855,24 @@ hipError_t launch_interleave(const float* j, const float* kap, float2* med, long
   return hipGetLastError();
 }
 
-hipError_t launch_tile(const TileArgs& a, int n_bins, bool det, bool nearest, int tiles,
-                       hipStream_t s) {
+hipError_t launch_tile_schedule(const TileArgs& a, int tiles, hipStream_t s) {
+  hipError_t e = launch_fill_zero_u64(a.tile_cost, tiles, s);
+  if (e != hipSuccess) return e;
+  const int npairs = a.pbegin[a.n_src];
+  if (npairs > 0) {   // (without rays every tile keeps a zero cost: one empty item)
+    const dim3 grid(tiles, (npairs + kCostThreads - 1) / kCostThreads);
+    hipLaunchKernelGGL(tile_cost_kernel, grid, dim3(kCostThreads), 0, s, a);
+  }
+  hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kScheduleThreads), 0, s, a, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool det, bool nearest, hipStream_t s) {
   switch (n_bins) {
-    case 1: return launch_tile_nb<1>(a, det, nearest, tiles, s);
-    case 2: return launch_tile_nb<2>(a, det, nearest, tiles, s);
-    case 3: return launch_tile_nb<3>(a, det, nearest, tiles, s);
-    case 4: return launch_tile_nb<4>(a, det, nearest, tiles, s);
+    case 1: return launch_tile_nb<1>(a, det, nearest, s);
+    case 2: return launch_tile_nb<2>(a, det, nearest, s);
+    case 3: return launch_tile_nb<3>(a, det, nearest, s);
+    case 4: return launch_tile_nb<4>(a, det, nearest, s);
     default: return hipErrorInvalidValue;
   }
 }

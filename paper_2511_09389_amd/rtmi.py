@@ -40,7 +40,7 @@ class RtmiError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("accum_mode", ctypes.c_int32), ("directions", ctypes.c_void_p),
                 ("ray_weight", ctypes.c_float), ("path", ctypes.c_int32),
-                ("tile_parts", ctypes.c_int32)]
+                ("tile_item_chunks", ctypes.c_int32)]
 
 
 def _load():
@@ -62,6 +62,11 @@ def _load():
                                   F32, P, ctypes.POINTER(Options), P]),
         "rtmi_debug_rays": (I32, [P, P, I32, I32, I32, P, I32, F32, F32, F32, I32, P, P, P]),
         "rtmi_trace_vjp": (I32, [P, P, I32, I32, I32, I32, P, P, P, F32, F32, F32, P, P, P, P]),
+        "rtmi_plan_create": (I32, [I32, I32, I32, I32, P, P, P, I32, I64, I64, P, F32, F32, F32,
+                                   ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_void_p)]),
+        "rtmi_plan_execute": (I32, [P, P, P, P, P]),
+        "rtmi_plan_workspace_bytes": (I64, [P]),
+        "rtmi_plan_destroy": (I32, [P]),
         "rtmi_timing_enable": (I32, [I32]),
         "rtmi_timing_read": (I32, [I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     }
@@ -181,7 +186,7 @@ def trace_multi(j_map, kappa_map, source_pos, num_rays, step_size, radiation_vel
 
 def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
                time_step, kappa_scale=None, substep_cap=None, out=None, deterministic=False,
-               directions=None, ray_weight=0.0, path=PATH_TILED, tile_parts=0):
+               directions=None, ray_weight=0.0, path=PATH_TILED, tile_item_chunks=0):
     """Frequency bins as a batch axis. j_maps / kappa_maps are 3-D (shared by all bins) or
     4-D [B][nx][ny][nz]; a 3-D kappa with kappa_scale gives kappa_b = kappa * scale[b].
     Returns a [B][nx][ny][nz] float32 tensor."""
@@ -206,7 +211,7 @@ def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_ve
     src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
     out = _new_field((n_bins,) + grid, j_maps) if out is None else out
     opts = Options(ACCUM_DETERMINISTIC if deterministic else ACCUM_ATOMIC, None, float(ray_weight),
-                   int(path), int(tile_parts))
+                   int(path), int(tile_item_chunks))
     dirs = None
     if directions is not None:
         dirs = _host_f32(directions, 3)
@@ -222,6 +227,79 @@ def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_ve
             step_size, radiation_velocity, time_step, _dev(out, "out", 4), ctypes.byref(opts),
             _stream(j_maps.device)))
     return out
+
+
+class Plan:
+    """The batched march prepared once (rtmi_plan_*): sources with their own N_Omega and
+    substep caps, times bins, as trace_bins computes them. execute() only enqueues kernels
+    on the current stream, so it can be captured in a torch.cuda.CUDAGraph and replayed.
+    Executions of one plan must be stream-ordered (they share its workspace)."""
+
+    def __init__(self, grid, source_pos, num_rays, step_size, radiation_velocity, time_step,
+                 n_bins=1, kappa_scale=None, per_bin_j=False, per_bin_kappa=False,
+                 substep_cap=None, deterministic=False, directions=None, ray_weight=0.0,
+                 tile_item_chunks=0, device=None):
+        self.grid = tuple(int(v) for v in grid)
+        cells = self.grid[0] * self.grid[1] * self.grid[2]
+        src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
+        scale = None
+        if kappa_scale is not None:
+            if per_bin_kappa:
+                raise ValueError("kappa_scale applies to a shared kappa only")
+            scale = _host_f32(kappa_scale).ravel()
+            if scale.size != n_bins:
+                raise ValueError("kappa_scale must have one entry per bin")
+        self.n_bins = int(n_bins)
+        self.per_bin_j, self.per_bin_kappa = bool(per_bin_j), bool(per_bin_kappa)
+        opts = Options(ACCUM_DETERMINISTIC if deterministic else ACCUM_ATOMIC, None,
+                       float(ray_weight), PATH_TILED, int(tile_item_chunks))
+        dirs = None
+        if directions is not None:
+            dirs = _host_f32(directions, 3)
+            opts.directions = dirs.ctypes.data
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        handle = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(lib.rtmi_plan_create(
+                self.grid[0], self.grid[1], self.grid[2], src.shape[0],
+                src.ctypes.data_as(ctypes.c_void_p), nr.ctypes.data_as(ctypes.c_void_p),
+                None if cap is None else cap.ctypes.data_as(ctypes.c_void_p), self.n_bins,
+                cells if per_bin_j else 0, cells if per_bin_kappa else 0,
+                None if scale is None else scale.ctypes.data_as(ctypes.c_void_p),
+                step_size, radiation_velocity, time_step, ctypes.byref(opts), ctypes.byref(handle)))
+        self._handle = handle
+
+    @property
+    def workspace_bytes(self):
+        return int(lib.rtmi_plan_workspace_bytes(self._handle))
+
+    def execute(self, j_maps, kappa_maps, out=None):
+        if self._handle is None:
+            raise RuntimeError("plan is closed")
+        for t, per_bin, name in ((j_maps, self.per_bin_j, "j_maps"), (kappa_maps, self.per_bin_kappa, "kappa_maps")):
+            want = ((self.n_bins,) + self.grid) if per_bin else self.grid
+            if tuple(t.shape) != want:
+                raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {want}")
+        if out is None:
+            out = _new_field((self.n_bins,) + self.grid, j_maps)
+        elif tuple(out.shape) != (self.n_bins,) + self.grid:
+            raise ValueError(f"out has shape {tuple(out.shape)}, expected {(self.n_bins,) + self.grid}")
+        with torch.cuda.device(self.device):
+            _check(lib.rtmi_plan_execute(self._handle, _dev(j_maps, "j_maps", (3, 4)),
+                                         _dev(kappa_maps, "kappa_maps", (3, 4)), _dev(out, "out", 4),
+                                         _stream(self.device)))
+        return out
+
+    def close(self):
+        if getattr(self, "_handle", None) is not None:
+            lib.rtmi_plan_destroy(self._handle)
+            self._handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def trace_vjp(j_map, kappa_map, source_pos, num_rays, step_size, radiation_velocity, time_step,
