@@ -15,6 +15,9 @@ What is computed (paper Sec. 2, Eq. (2) and the paragraphs after it):
   * the multi-source routine is the sum over sources; frequency bins are independent
     copies of the problem (Sec. 2, "Frequency-bin agnosticism").
 
+The surrogate module holds the FP64 reference of the small convolutional network that can
+stand in for the march (not part of the paper; the march stays its fallback).
+
 Readings of points the paper leaves open are listed in march.py and in the design notes.
 Every function is pinned by tests against closed forms, invariants and brute force.
 Parity unpinned: the paper's exact Fibonacci variant, and any field values the paper
