@@ -197,6 +197,51 @@ int64_t rtmi_plan_workspace_bytes(const rtmi_plan* plan);
 /* Frees the plan (NULL is accepted). No execution of it may still be pending. */
 int32_t rtmi_plan_destroy(rtmi_plan* plan);
 
+/* ---- Learned surrogate (not part of the paper; the march is its fallback) ----
+ *
+ * Building blocks of a small 3-D convolutional network that predicts the march's field
+ * from its inputs: 3x3x3 "same" convolutions with zero padding over 32 channels, bf16
+ * operands on the matrix cores with fp32 accumulation, GELU (error-function form) and
+ * residual connections, their gradients, a squared-error loss and an Adam step.
+ * Layout: activations channels-last bf16 [n][d][h][w][32] (DEVICE; a channel count
+ * below 32 is zero-padded by the caller); weights bf16 [27][32 co][32 ci] with
+ * tap = ((dz+1)*3 + (dy+1))*3 + (dx+1), the input read at voxel + (dz, dy, dx); bias fp32
+ * [32]. All pointers are DEVICE memory owned by the caller; calls enqueue on `stream`
+ * and return RTMI_ERR_* on bad arguments without enqueueing.
+ *
+ * forward: z = conv(x, w) + bias; y = (gelu ? GELU(z) : z) + residual (bf16, or NULL);
+ *   writes y (bf16) and, if z != NULL, z (fp32, for the backward pass). */
+int32_t rtmi_conv3d_forward(const void* x, const void* w, const float* bias,
+                            const void* residual, int32_t gelu, int32_t n, int32_t d,
+                            int32_t h, int32_t w_dim, void* y, float* z, void* stream);
+
+/* backward-data: g = conv^T(dz, w) + residual (fp32, or NULL), i.e.
+ *   g[u][ci] = sum_tap sum_co w[tap][co][ci] dz[u - off(tap)][co] + residual[u][ci];
+ *   writes g to dh (fp32, or NULL) and g * GELU'(zprev) (or g when zprev is NULL) to
+ *   dz_prev (bf16, or NULL). */
+int32_t rtmi_conv3d_backward_data(const void* dz, const void* w, const float* residual,
+                                  const float* zprev, int32_t n, int32_t d, int32_t h,
+                                  int32_t w_dim, float* dh, void* dz_prev, void* stream);
+
+/* backward-weight: dw[tap][co][ci] += sum_v dz[v][co] x[v + off(tap)][ci] and
+ *   db[co] += sum_v dz[v][co] (fp32; the caller zeroes them). Needs w_dim in {16, 32, 48,
+ *   64}, else RTMI_ERR_UNSUPPORTED. */
+int32_t rtmi_conv3d_backward_weight(const void* x, const void* dz, int32_t n, int32_t d,
+                                    int32_t h, int32_t w_dim, float* dw, float* db,
+                                    void* stream);
+
+/* Squared error of channel 0 of y (bf16 [n_voxels][32]) against target (fp32
+ * [n_voxels]): *loss += scale * sum (y - t)^2, and dz (bf16 [n_voxels][32], overwritten)
+ * = its gradient in channel 0, zero in the others. */
+int32_t rtmi_mse_loss(const void* y, const float* target, int64_t n_voxels, float scale,
+                      void* dz, float* loss, void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) on fp32 weights w with moments m, v and
+ * gradient g (count elements each); also writes the bf16 copy w_bf16 when not NULL. */
+int32_t rtmi_adam_step(float* w, float* m, float* v, const float* g, void* w_bf16,
+                       int64_t count, float lr, float beta1, float beta2, float eps,
+                       int32_t step, void* stream);
+
 /* Adjoint of rtmi_trace_multi (Sec. 4: gradients of a loss through the tracer, here
  * written out by the chain rule on Eq. (2) instead of automatic differentiation): given
  * grad_field = dL/dJ (DEVICE float[nx][ny][nz]), writes dL/dj to grad_j and dL/dkappa to

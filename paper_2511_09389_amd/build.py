@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librtmi.so")
-SOURCES = ["api.hip", "march.hip", "tiled.hip", "adjoint.hip"]
+SOURCES = ["api.hip", "march.hip", "tiled.hip", "adjoint.hip", "conv.hip"]
 
 
 def hipcc():

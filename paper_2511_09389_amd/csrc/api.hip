@@ -53,6 +53,13 @@ int64_t substeps(float ds, float c, float dt, int32_t cap) {
   return static_cast<int64_t>(n);
 }
 
+int32_t check_conv_shape(int32_t n, int32_t d, int32_t h, int32_t w) {
+  if (n < 1 || d < 1 || h < 1 || w < 1) return fail(RTMI_ERR_SHAPE, "conv extents must be >= 1");
+  if (int64_t(n) * d * h * w * rtmi::kConvChannels > (int64_t(1) << 40))
+    return fail(RTMI_ERR_SHAPE, "conv tensor too large");
+  return RTMI_OK;
+}
+
 int32_t check_scalars(float ds, float c, float dt) {
   if (!std::isfinite(ds) || !std::isfinite(c) || !std::isfinite(dt))
     return fail(RTMI_ERR_NONFINITE, "step_size, radiation_velocity and time_step must be finite");
@@ -1121,6 +1128,105 @@ int64_t rtmi_plan_workspace_bytes(const rtmi_plan* plan) {
 
 int32_t rtmi_plan_destroy(rtmi_plan* plan) {
   plan_release(plan);
+  return RTMI_OK;
+}
+
+// ---- surrogate network ----
+
+int32_t rtmi_conv3d_forward(const void* x, const void* w, const float* bias, const void* residual,
+                            int32_t gelu, int32_t n, int32_t d, int32_t h, int32_t w_dim, void* y,
+                            float* z, void* stream) {
+  if (!x || !w || !y) return fail(RTMI_ERR_INVALID_ARG, "null x, w or y pointer");
+  if (int32_t st = check_conv_shape(n, d, h, w_dim)) return st;
+  rtmi::ConvArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.x = x;
+  a.w = w;
+  a.bias = bias;
+  a.residual = residual;
+  a.gelu = gelu != 0;
+  a.z = z;
+  a.y = y;
+  a.n = n;
+  a.d = d;
+  a.h = h;
+  a.w_dim = w_dim;
+  const hipError_t e = rtmi::launch_conv(a, false, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "conv forward launch");
+  g_error.clear();
+  return RTMI_OK;
+}
+
+int32_t rtmi_conv3d_backward_data(const void* dz, const void* w, const float* residual,
+                                  const float* zprev, int32_t n, int32_t d, int32_t h,
+                                  int32_t w_dim, float* dh, void* dz_prev, void* stream) {
+  if (!dz || !w) return fail(RTMI_ERR_INVALID_ARG, "null dz or w pointer");
+  if (!dh && !dz_prev) return fail(RTMI_ERR_INVALID_ARG, "neither dh nor dz_prev requested");
+  if (int32_t st = check_conv_shape(n, d, h, w_dim)) return st;
+  rtmi::ConvArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.x = dz;
+  a.w = w;
+  a.residual_f32 = residual;
+  a.zprev = zprev;
+  a.dh = dh;
+  a.y = dz_prev;
+  a.n = n;
+  a.d = d;
+  a.h = h;
+  a.w_dim = w_dim;
+  const hipError_t e = rtmi::launch_conv(a, true, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "conv backward-data launch");
+  g_error.clear();
+  return RTMI_OK;
+}
+
+int32_t rtmi_conv3d_backward_weight(const void* x, const void* dz, int32_t n, int32_t d, int32_t h,
+                                    int32_t w_dim, float* dw, float* db, void* stream) {
+  if (!x || !dz || !dw || !db) return fail(RTMI_ERR_INVALID_ARG, "null x, dz, dw or db pointer");
+  if (int32_t st = check_conv_shape(n, d, h, w_dim)) return st;
+  if (w_dim % 16 != 0 || w_dim > 64)
+    return fail(RTMI_ERR_UNSUPPORTED, "backward-weight needs an x extent of 16, 32, 48 or 64 (got %d)", w_dim);
+  rtmi::ConvArgs a;
+  std::memset(&a, 0, sizeof a);
+  a.x = x;
+  a.dz = dz;
+  a.dw = dw;
+  a.db = db;
+  a.n = n;
+  a.d = d;
+  a.h = h;
+  a.w_dim = w_dim;
+  const hipError_t e = rtmi::launch_wgrad(a, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "conv backward-weight launch");
+  g_error.clear();
+  return RTMI_OK;
+}
+
+int32_t rtmi_mse_loss(const void* y, const float* target, int64_t n_voxels, float scale, void* dz,
+                      float* loss, void* stream) {
+  if (!y || !target || !dz || !loss) return fail(RTMI_ERR_INVALID_ARG, "null pointer");
+  if (n_voxels < 1) return fail(RTMI_ERR_INVALID_ARG, "n_voxels must be >= 1");
+  if (!std::isfinite(scale)) return fail(RTMI_ERR_NONFINITE, "scale is not finite");
+  const hipError_t e = rtmi::launch_mse(static_cast<const unsigned short*>(y), target, n_voxels, scale,
+                                        static_cast<unsigned short*>(dz), loss, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "mse launch");
+  g_error.clear();
+  return RTMI_OK;
+}
+
+int32_t rtmi_adam_step(float* w, float* m, float* v, const float* g, void* w_bf16, int64_t count,
+                       float lr, float beta1, float beta2, float eps, int32_t step, void* stream) {
+  if (!w || !m || !v || !g) return fail(RTMI_ERR_INVALID_ARG, "null pointer");
+  if (count < 1 || step < 1) return fail(RTMI_ERR_INVALID_ARG, "count and step must be >= 1");
+  if (!(beta1 >= 0.0f && beta1 < 1.0f && beta2 >= 0.0f && beta2 < 1.0f && eps > 0.0f && std::isfinite(lr)))
+    return fail(RTMI_ERR_INVALID_ARG, "bad Adam hyper-parameters");
+  const float c1 = static_cast<float>(1.0 - std::pow(double(beta1), step));
+  const float c2 = static_cast<float>(1.0 - std::pow(double(beta2), step));
+  const hipError_t e = rtmi::launch_adam(w, m, v, g, static_cast<unsigned short*>(w_bf16), count, lr, beta1,
+                                         beta2, eps, c1, c2, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "adam launch");
+  g_error.clear();
   return RTMI_OK;
 }
 

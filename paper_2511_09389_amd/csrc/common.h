@@ -145,6 +145,34 @@ hipError_t launch_march(const MarchArgs& a, int n_bins, bool shared_j, bool dete
 hipError_t launch_debug(const DebugArgs& a, hipStream_t s);
 hipError_t launch_record(const RecordArgs& a, int n_bins, bool shared_j, bool deterministic,
                          int n_blocks, hipStream_t s);   // uses a.med when it is not null
+// Surrogate network: 3x3x3 convolutions over channels-last bf16 activations.
+constexpr int kConvChannels = 32;
+
+struct ConvArgs {
+  const void* x;              // bf16 [n][d][h][w][32]: input (forward), dz (backward-data)
+  const void* w;              // bf16 [27][32][32] forward weights
+  const float* bias;          // forward, or null
+  const void* residual;       // forward: bf16 tensor added after the activation, or null
+  int gelu;                   // forward: apply GELU to conv + bias
+  float* z;                   // forward: fp32 pre-activation out, or null
+  void* y;                    // forward: bf16 out; backward-data: bf16 dz of the previous layer
+  const float* residual_f32;  // backward-data: fp32 gradient added to the result, or null
+  const float* zprev;         // backward-data: previous layer's pre-activation (GELU'), or null
+  float* dh;                  // backward-data: fp32 gradient out, or null
+  const void* dz;             // backward-weight: bf16 dz [n][d][h][w][32]
+  float* dw;                  // backward-weight: fp32 [27][32][32], accumulated
+  float* db;                  // backward-weight: fp32 [32], accumulated
+  int n, d, h, w_dim;
+};
+
+hipError_t launch_conv(const ConvArgs& a, bool backward, hipStream_t s);
+hipError_t launch_wgrad(const ConvArgs& a, hipStream_t s);
+hipError_t launch_mse(const unsigned short* y, const float* target, long long nvox, float scale,
+                      unsigned short* dz, float* loss, hipStream_t s);
+hipError_t launch_adam(float* w, float* m, float* v, const float* g, unsigned short* w_bf16,
+                       long long count, float lr, float b1, float b2, float eps, float c1, float c2,
+                       hipStream_t s);
+
 // Tile launches: the schedule (per-tile cost, work items; depends on the geometry only)
 // and the persistent tile kernel, which leaves the schedule ready for another run.
 hipError_t launch_tile_schedule(const TileArgs& a, int tiles, hipStream_t s);

@@ -67,6 +67,11 @@ def _load():
         "rtmi_plan_execute": (I32, [P, P, P, P, P]),
         "rtmi_plan_workspace_bytes": (I64, [P]),
         "rtmi_plan_destroy": (I32, [P]),
+        "rtmi_conv3d_forward": (I32, [P, P, P, P, I32, I32, I32, I32, I32, P, P, P]),
+        "rtmi_conv3d_backward_data": (I32, [P, P, P, P, I32, I32, I32, I32, P, P, P]),
+        "rtmi_conv3d_backward_weight": (I32, [P, P, I32, I32, I32, I32, P, P, P]),
+        "rtmi_mse_loss": (I32, [P, P, I64, F32, P, P, P]),
+        "rtmi_adam_step": (I32, [P, P, P, P, P, I64, F32, F32, F32, F32, I32, P]),
         "rtmi_timing_enable": (I32, [I32]),
         "rtmi_timing_read": (I32, [I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     }
@@ -337,6 +342,77 @@ def debug_rays(j_map, kappa_map, source_pos, num_rays, step_size, radiation_velo
                                    _dev(rays, "out_rays", 2), _dev(tau, "out_tau", 2),
                                    _stream(j_map.device)))
     return rays, tau
+
+
+# ---- surrogate network building blocks (channels-last, 32 channels) ----
+
+CONV_CHANNELS = 32
+
+
+def _act(t, name, dtype, ndim=5):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on a HIP device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if ndim is not None and (t.dim() != ndim or t.shape[-1] != CONV_CHANNELS):
+        raise ValueError(f"{name} must be [n][d][h][w][{CONV_CHANNELS}] (got {tuple(t.shape)})")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _opt(t, name, dtype, ndim=5):
+    return None if t is None else _act(t, name, dtype, ndim)
+
+
+def conv3d_forward(x, w, bias=None, residual=None, gelu=False, z=None, y=None):
+    """y = act(conv(x, w) + bias) + residual, bf16 channels-last; z (fp32) if given."""
+    n, d, h, wd, _ = x.shape
+    y = torch.empty_like(x) if y is None else y
+    with torch.cuda.device(x.device):
+        _check(lib.rtmi_conv3d_forward(_act(x, "x", torch.bfloat16), _act(w, "w", torch.bfloat16, None),
+                                       _opt(bias, "bias", torch.float32, None),
+                                       _opt(residual, "residual", torch.bfloat16), int(bool(gelu)),
+                                       n, d, h, wd, _act(y, "y", torch.bfloat16),
+                                       _opt(z, "z", torch.float32), _stream(x.device)))
+    return y
+
+
+def conv3d_backward_data(dz, w, residual=None, zprev=None, dh=None, dz_prev=None):
+    n, d, h, wd, _ = dz.shape
+    with torch.cuda.device(dz.device):
+        _check(lib.rtmi_conv3d_backward_data(_act(dz, "dz", torch.bfloat16), _act(w, "w", torch.bfloat16, None),
+                                             _opt(residual, "residual", torch.float32),
+                                             _opt(zprev, "zprev", torch.float32), n, d, h, wd,
+                                             _opt(dh, "dh", torch.float32),
+                                             _opt(dz_prev, "dz_prev", torch.bfloat16), _stream(dz.device)))
+    return dh, dz_prev
+
+
+def conv3d_backward_weight(x, dz, dw, db):
+    n, d, h, wd, _ = x.shape
+    with torch.cuda.device(x.device):
+        _check(lib.rtmi_conv3d_backward_weight(_act(x, "x", torch.bfloat16), _act(dz, "dz", torch.bfloat16),
+                                               n, d, h, wd, _act(dw, "dw", torch.float32, None),
+                                               _act(db, "db", torch.float32, None), _stream(x.device)))
+    return dw, db
+
+
+def mse_loss(y, target, scale, dz, loss):
+    nvox = target.numel()
+    with torch.cuda.device(y.device):
+        _check(lib.rtmi_mse_loss(_act(y, "y", torch.bfloat16), _act(target, "target", torch.float32, None),
+                                 nvox, float(scale), _act(dz, "dz", torch.bfloat16),
+                                 _act(loss, "loss", torch.float32, None), _stream(y.device)))
+    return loss
+
+
+def adam_step(w, m, v, g, w_bf16, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
+    with torch.cuda.device(w.device):
+        _check(lib.rtmi_adam_step(_act(w, "w", torch.float32, None), _act(m, "m", torch.float32, None),
+                                  _act(v, "v", torch.float32, None), _act(g, "g", torch.float32, None),
+                                  _opt(w_bf16, "w_bf16", torch.bfloat16, None), w.numel(), float(lr),
+                                  float(beta1), float(beta2), float(eps), int(step), _stream(w.device)))
 
 
 def timing_enable(on=True):
