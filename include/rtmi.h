@@ -236,6 +236,24 @@ int32_t rtmi_conv3d_backward_weight(const void* x, const void* dz, int32_t n, in
 int32_t rtmi_mse_loss(const void* y, const float* target, int64_t n_voxels, float scale,
                       void* dz, float* loss, void* stream);
 
+/* Network input of one sample (cells voxels; DEVICE fp32 j, kappa and `cheap`, the march
+ * with few rays). First scale_sums (DEVICE fp32 [2]) is reset and scale_sums[0] = sum of
+ * cheap^2, giving the sample's scale s = sqrt(scale_sums[0] / cells); then x (bf16
+ * [cells][32], overwritten) = ((log kappa - stats[0]) * stats[1], j * stats[2], cheap / s,
+ * (log(cheap + stats[5]) - stats[3]) * stats[4], 0, ...). stats: HOST float[6], stats[5] > 0. */
+int32_t rtmi_surrogate_features(const float* j, const float* kappa, const float* cheap,
+                                int64_t cells, const float* stats, float* scale_sums, void* x,
+                                void* stream);
+
+/* Prediction from the network's output y (bf16 [cells][32], channel 0 read) and the
+ * scale_sums that rtmi_surrogate_features left: field = max(0, cheap + s y) (fp32,
+ * overwritten); check_sums[0] += sum (field - cheap)^2 and check_sums[1] += sum cheap^2
+ * (DEVICE fp32 [2]): the relative L2 distance from the cheap field that the fallback test
+ * reads. */
+int32_t rtmi_surrogate_output(const void* y, const float* cheap, int64_t cells,
+                              const float* scale_sums, float* field, float* check_sums,
+                              void* stream);
+
 /* One Adam step (bias-corrected, step >= 1) on fp32 weights w with moments m, v and
  * gradient g (count elements each); also writes the bf16 copy w_bf16 when not NULL. */
 int32_t rtmi_adam_step(float* w, float* m, float* v, const float* g, void* w_bf16,

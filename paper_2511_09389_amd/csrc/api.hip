@@ -1215,6 +1215,34 @@ int32_t rtmi_mse_loss(const void* y, const float* target, int64_t n_voxels, floa
   return RTMI_OK;
 }
 
+int32_t rtmi_surrogate_features(const float* j, const float* kappa, const float* cheap,
+                                int64_t cells, const float* stats, float* scale_sums, void* x,
+                                void* stream) {
+  if (!j || !kappa || !cheap || !stats || !scale_sums || !x) return fail(RTMI_ERR_INVALID_ARG, "null pointer");
+  if (cells < 1) return fail(RTMI_ERR_INVALID_ARG, "cells must be >= 1");
+  for (int i = 0; i < 6; ++i)
+    if (!std::isfinite(stats[i])) return fail(RTMI_ERR_NONFINITE, "stats[%d] is not finite", i);
+  if (!(stats[5] > 0.0f)) return fail(RTMI_ERR_INVALID_ARG, "stats[5] (floor) must be > 0");
+  const rtmi::SurrogateStats st{stats[0], stats[1], stats[2], stats[3], stats[4], stats[5]};
+  const hipError_t e = rtmi::launch_features(j, kappa, cheap, cells, st, scale_sums,
+                                             static_cast<unsigned short*>(x), static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "features launch");
+  g_error.clear();
+  return RTMI_OK;
+}
+
+int32_t rtmi_surrogate_output(const void* y, const float* cheap, int64_t cells, const float* scale_sums,
+                              float* field, float* check_sums, void* stream) {
+  if (!y || !cheap || !scale_sums || !field || !check_sums) return fail(RTMI_ERR_INVALID_ARG, "null pointer");
+  if (cells < 1) return fail(RTMI_ERR_INVALID_ARG, "cells must be >= 1");
+  const hipError_t e = rtmi::launch_surrogate_output(static_cast<const unsigned short*>(y), cheap, cells,
+                                                     scale_sums, field, check_sums,
+                                                     static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "surrogate output launch");
+  g_error.clear();
+  return RTMI_OK;
+}
+
 int32_t rtmi_adam_step(float* w, float* m, float* v, const float* g, void* w_bf16, int64_t count,
                        float lr, float beta1, float beta2, float eps, int32_t step, void* stream) {
   if (!w || !m || !v || !g) return fail(RTMI_ERR_INVALID_ARG, "null pointer");

@@ -165,6 +165,18 @@ struct ConvArgs {
   int n, d, h, w_dim;
 };
 
+// Input standardisation of the surrogate (fixed from its training set).
+struct SurrogateStats {
+  float log_kappa_mean, log_kappa_inv_std;
+  float j_inv_scale;
+  float log_cheap_mean, log_cheap_inv_std;
+  float floor;                // added to the cheap field before the log
+};
+
+hipError_t launch_features(const float* j, const float* kap, const float* cheap, long long cells,
+                           const SurrogateStats& st, float* sums, unsigned short* x, hipStream_t s);
+hipError_t launch_surrogate_output(const unsigned short* y, const float* cheap, long long cells,
+                                   const float* sums, float* field, float* check, hipStream_t s);
 hipError_t launch_conv(const ConvArgs& a, bool backward, hipStream_t s);
 hipError_t launch_wgrad(const ConvArgs& a, hipStream_t s);
 hipError_t launch_mse(const unsigned short* y, const float* target, long long nvox, float scale,

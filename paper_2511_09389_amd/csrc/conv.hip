@@ -231,6 +231,72 @@ __global__ void adam_kernel(float* __restrict__ w, float* __restrict__ m, float*
   }
 }
 
+// sums[0] += sum of cheap^2 over the sample (the scale s = sqrt(sums[0] / cells) of the
+// linear features and of the prediction).
+__global__ void sumsq_kernel(const float* __restrict__ cheap, long long cells, float* __restrict__ sums) {
+  float part = 0.0f;
+  for (long long v = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; v < cells;
+       v += static_cast<long long>(gridDim.x) * blockDim.x) {
+    const float c = fmaxf(cheap[v], 0.0f);
+    part += c * c;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+  if ((threadIdx.x & 63) == 0 && part != 0.0f) unsafeAtomicAdd(sums, part);
+}
+
+__global__ void fill_sums_kernel(float* sums) {
+  if (threadIdx.x < 2) sums[threadIdx.x] = 0.0f;
+}
+
+__device__ __forceinline__ float sample_scale(const float* sums, long long cells) {
+  return fmaxf(sqrtf(sums[0] / static_cast<float>(cells)), 1e-30f);
+}
+
+// Network input of one sample: channel 0 standardised log kappa, 1 scaled j, 2 the cheap
+// (few-ray) field over its scale s, 3 the standardised log of the cheap field, the rest 0.
+__global__ void features_kernel(const float* __restrict__ j, const float* __restrict__ kap,
+                                const float* __restrict__ cheap, long long cells, SurrogateStats st,
+                                const float* __restrict__ sums, unsigned short* __restrict__ x) {
+  const float inv_s = 1.0f / sample_scale(sums, cells);
+  for (long long v = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; v < cells;
+       v += static_cast<long long>(gridDim.x) * blockDim.x) {
+    const float c = fmaxf(cheap[v], 0.0f);
+    const float f[4] = {(logf(fmaxf(kap[v], 1e-30f)) - st.log_kappa_mean) * st.log_kappa_inv_std,
+                        j[v] * st.j_inv_scale, c * inv_s,
+                        (logf(c + st.floor) - st.log_cheap_mean) * st.log_cheap_inv_std};
+#pragma unroll
+    for (int ch = 0; ch < kC; ++ch) x[v * kC + ch] = ch < 4 ? f32_to_bf16(f[ch]) : 0;
+  }
+}
+
+// Prediction: the network's channel 0 corrects the cheap field in units of its scale,
+// J = max(0, cheap + s y); also sums, for the error check, (J - cheap)^2 and cheap^2 into
+// check[0], check[1].
+__global__ void output_kernel(const unsigned short* __restrict__ y, const float* __restrict__ cheap,
+                              long long cells, const float* __restrict__ sums, float* __restrict__ field,
+                              float* __restrict__ check) {
+  const float scale = sample_scale(sums, cells);
+  float s0 = 0.0f, s1 = 0.0f;
+  for (long long v = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; v < cells;
+       v += static_cast<long long>(gridDim.x) * blockDim.x) {
+    const float c = fmaxf(cheap[v], 0.0f);
+    const float J = fmaxf(c + scale * bf16_to_f32(y[v * kC]), 0.0f);
+    field[v] = J;
+    s0 += (J - c) * (J - c);
+    s1 += c * c;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    s0 += __shfl_xor(s0, off, 64);
+    s1 += __shfl_xor(s1, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    unsafeAtomicAdd(check, s0);
+    unsafeAtomicAdd(check + 1, s1);
+  }
+}
+
 int grid_for(long long work, int per_block) {
   long long g = (work + per_block - 1) / per_block;
   return static_cast<int>(g < 1 ? 1 : (g > 4096 ? 4096 : g));
@@ -256,6 +322,22 @@ hipError_t launch_wgrad(const ConvArgs& a, hipStream_t s) {
 hipError_t launch_mse(const unsigned short* y, const float* target, long long nvox, float scale,
                       unsigned short* dz, float* loss, hipStream_t s) {
   hipLaunchKernelGGL(mse_kernel, dim3(grid_for(nvox, 256 * 4)), dim3(256), 0, s, y, target, nvox, scale, dz, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_features(const float* j, const float* kap, const float* cheap, long long cells,
+                           const SurrogateStats& st, float* sums, unsigned short* x, hipStream_t s) {
+  hipLaunchKernelGGL(fill_sums_kernel, dim3(1), dim3(64), 0, s, sums);
+  hipLaunchKernelGGL(sumsq_kernel, dim3(grid_for(cells, 256 * 4)), dim3(256), 0, s, cheap, cells, sums);
+  hipLaunchKernelGGL(features_kernel, dim3(grid_for(cells, 256 * 4)), dim3(256), 0, s, j, kap, cheap, cells, st,
+                     sums, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_surrogate_output(const unsigned short* y, const float* cheap, long long cells, const float* sums,
+                                   float* field, float* check, hipStream_t s) {
+  hipLaunchKernelGGL(output_kernel, dim3(grid_for(cells, 256 * 4)), dim3(256), 0, s, y, cheap, cells, sums,
+                     field, check);
   return hipGetLastError();
 }
 

@@ -72,6 +72,8 @@ def _load():
         "rtmi_conv3d_backward_weight": (I32, [P, P, I32, I32, I32, I32, P, P, P]),
         "rtmi_mse_loss": (I32, [P, P, I64, F32, P, P, P]),
         "rtmi_adam_step": (I32, [P, P, P, P, P, I64, F32, F32, F32, F32, I32, P]),
+        "rtmi_surrogate_features": (I32, [P, P, P, I64, P, P, P, P]),
+        "rtmi_surrogate_output": (I32, [P, P, I64, P, P, P, P]),
         "rtmi_timing_enable": (I32, [I32]),
         "rtmi_timing_read": (I32, [I32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     }
@@ -413,6 +415,33 @@ def adam_step(w, m, v, g, w_bf16, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
                                   _act(v, "v", torch.float32, None), _act(g, "g", torch.float32, None),
                                   _opt(w_bf16, "w_bf16", torch.bfloat16, None), w.numel(), float(lr),
                                   float(beta1), float(beta2), float(eps), int(step), _stream(w.device)))
+
+
+def surrogate_features(j, kappa, cheap, stats, x=None, scale_sums=None):
+    """(x, scale_sums): bf16 [1][d][h][w][32] network input from fp32 j, kappa and the
+    cheap field (3-D), and the device sums that fix the sample's scale."""
+    d, h, w = j.shape
+    x = torch.empty((1, d, h, w, CONV_CHANNELS), dtype=torch.bfloat16, device=j.device) if x is None else x
+    scale_sums = torch.empty(2, dtype=torch.float32, device=j.device) if scale_sums is None else scale_sums
+    st = np.ascontiguousarray(np.asarray(stats, np.float32).reshape(6))
+    with torch.cuda.device(j.device):
+        _check(lib.rtmi_surrogate_features(_dev(j, "j", 3), _dev(kappa, "kappa", 3), _dev(cheap, "cheap", 3),
+                                           j.numel(), st.ctypes.data_as(ctypes.c_void_p),
+                                           _act(scale_sums, "scale_sums", torch.float32, None),
+                                           _act(x, "x", torch.bfloat16), _stream(j.device)))
+    return x, scale_sums
+
+
+def surrogate_output(y, cheap, scale_sums, field=None, check=None):
+    """(field, check sums): prediction from the network output and the error-check sums."""
+    field = torch.empty_like(cheap) if field is None else field
+    check = torch.zeros(2, dtype=torch.float32, device=cheap.device) if check is None else check
+    with torch.cuda.device(cheap.device):
+        _check(lib.rtmi_surrogate_output(_act(y, "y", torch.bfloat16), _dev(cheap, "cheap", 3), cheap.numel(),
+                                         _act(scale_sums, "scale_sums", torch.float32, None),
+                                         _dev(field, "field", 3), _act(check, "check", torch.float32, None),
+                                         _stream(cheap.device)))
+    return field, check
 
 
 def timing_enable(on=True):
