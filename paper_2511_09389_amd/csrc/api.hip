@@ -468,9 +468,31 @@ struct TiledLayout {
   int tiles_x = 0, tiles_y = 0, tiles_z = 0, tiles = 0;
   int n_launch = 0;
   bool interleaved = false;
-  size_t corner = 0, sched = 0, med = 0, v = 0, total = 0;   // byte offsets / size
+  size_t corner = 0, sched = 0, med = 0, v = 0, p = 0, segtot = 0, total = 0;   // byte offsets / size
   size_t sched_bytes = 0;
+  std::vector<int> seg_len;   // per source chunk: substeps per record run (0: whole rays)
 };
+
+// Substeps per record run for a launch of `rays` rays of at most max_nsub substeps: the
+// rays are cut into runs when they alone would give the device less than one wave per
+// SIMD, keeping runs at least two gather chunks long. (With a wave per SIMD already, more
+// runs measured slower: the gathers, not the latency of one ray's chain, bound the
+// kernel, and the fixup pass costs extra traffic.)
+int record_run_length(int64_t rays, int32_t max_nsub) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    cus = (hipGetDevice(&dev) == hipSuccess &&
+           hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ? v : 256;
+  }
+  if (rays < 1 || max_nsub < 1) return 0;
+  const int64_t target = int64_t(cus) * 4 * 64;
+  int runs = static_cast<int>(std::min<int64_t>(8, (target + rays - 1) / rays));
+  while (runs > 1 && (max_nsub + runs - 1) / runs < 2 * kRowAlign) --runs;
+  if (runs <= 1) return 0;
+  const int len = (max_nsub + runs - 1) / runs;
+  return (len + kRowAlign - 1) / kRowAlign * kRowAlign;
+}
 
 constexpr size_t kCornerBytes = 256;   // [4][8] floats, then (next 256 B) [4][8] u64
 
@@ -480,13 +502,26 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
   L.tiles_y = (p.ny + kTile - 1) / kTile;
   L.tiles_z = (p.nz + kTile - 1) / kTile;
   L.tiles = L.tiles_x * L.tiles_y * L.tiles_z;
-  int64_t v_elems_max = 0;
+  int64_t v_elems_max = 0, p_elems_max = 0, t_elems_max = 0;
   int src_chunks = 0;
   for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch, ++src_chunks) {
-    int64_t e = 0;
+    int64_t e = 0, rays = 0;
+    int32_t max_nsub = 0;
     for (int32_t s = s0; s < std::min(p.n_src, s0 + kMaxSrcPerLaunch); ++s)
-      if (plan.nsub[s] > 0) e += int64_t(p.nrays[s]) * row_stride(plan.nsub[s]);
+      if (plan.nsub[s] > 0) {
+        e += int64_t(p.nrays[s]) * row_stride(plan.nsub[s]);
+        rays += p.nrays[s];
+        max_nsub = std::max(max_nsub, plan.nsub[s]);
+      }
+    const int len = record_run_length(rays, max_nsub);
+    L.seg_len.push_back(len);
+    int64_t t = 0;
+    if (len > 0)
+      for (int32_t s = s0; s < std::min(p.n_src, s0 + kMaxSrcPerLaunch); ++s)
+        if (plan.nsub[s] > 0) t += int64_t(p.nrays[s]) * ((plan.nsub[s] + len - 1) / len);
     v_elems_max = std::max(v_elems_max, e);
+    p_elems_max = std::max(p_elems_max, len > 0 ? e : int64_t(0));
+    t_elems_max = std::max(t_elems_max, t);
   }
   L.n_launch = src_chunks * ((p.n_bins + kMaxBinsPerLaunch - 1) / kMaxBinsPerLaunch);
   const int32_t nb_max = std::min(kMaxBinsPerLaunch, p.n_bins);
@@ -497,7 +532,9 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
   L.sched = 2 * kCornerBytes;
   L.med = L.sched + L.sched_bytes * (sched_per_launch ? L.n_launch : 1);
   L.v = L.med + (L.interleaved ? align256((size_t(plan.cells) + 1) * sizeof(float2)) : 0);
-  L.total = L.v + size_t(v_elems_max) * nb_max * sizeof(float);
+  L.p = L.v + align256(size_t(v_elems_max) * nb_max * sizeof(float));
+  L.segtot = L.p + align256(size_t(p_elems_max) * nb_max * sizeof(float));
+  L.total = L.segtot + size_t(t_elems_max) * nb_max * sizeof(float2);
   return L;
 }
 
@@ -521,6 +558,8 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
   unsigned long long* corner_q = reinterpret_cast<unsigned long long*>(ws + L.corner + kCornerBytes);
   float2* med = L.interleaved ? reinterpret_cast<float2*>(ws + L.med) : nullptr;
   float* V = reinterpret_cast<float*>(ws + L.v);
+  float* Prow = reinterpret_cast<float*>(ws + L.p);
+  float2* segtot = reinterpret_cast<float2*>(ws + L.segtot);
   hipError_t e;
   if (mode != TiledMode::kSchedule) {
     if (L.interleaved && (e = rtmi::launch_interleave(p.j, p.kap, med, plan.cells, st)) != hipSuccess)
@@ -541,12 +580,20 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       rtmi::TileArgs t;
       std::memset(&r, 0, sizeof r);
       std::memset(&t, 0, sizeof t);
-      int64_t v_elems = 0;
-      int blocks = 0, patches = 0;
+      int64_t v_elems = 0, t_elems = 0;
+      int blocks = 0, patches = 0, fix_waves = 0;
+      const int seg_len = L.seg_len[s0 / kMaxSrcPerLaunch];
+      r.seg_len = seg_len;
       for (int32_t i = 0; i < ns; ++i) {
         const int32_t s = s0 + i;
         const int32_t nr = plan.nsub[s] > 0 ? p.nrays[s] : 0;
+        const int nseg = (seg_len > 0 && nr > 0) ? (plan.nsub[s] + seg_len - 1) / seg_len : 1;
         r.blk_begin[i] = blocks;
+        r.fbegin[i] = fix_waves;
+        r.nseg[i] = nseg;
+        r.sbase[i] = t_elems;
+        t_elems += int64_t(nr) * nseg;
+        fix_waves += nr * (nseg - 1);
         t.pbegin[i] = patches;
         r.sx[i] = t.sx[i] = p.src[3 * s];
         r.sy[i] = t.sy[i] = p.src[3 * s + 1];
@@ -559,11 +606,14 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
         r.dirs[i] = t.dirs[i] = plan.tables[s].dirs;
         t.pbounds[i] = plan.tables[s].bounds;
         v_elems += int64_t(nr) * row_stride(plan.nsub[s]);
-        blocks += (nr + kBlock - 1) / kBlock;
+        blocks += nseg * ((nr + kBlock - 1) / kBlock);
         patches += (nr + kPatch - 1) / kPatch;
       }
       r.blk_begin[ns] = blocks;
+      r.fbegin[ns] = fix_waves;
       t.pbegin[ns] = patches;
+      r.P = seg_len > 0 ? Prow : nullptr;
+      r.segtot = seg_len > 0 ? segtot : nullptr;
       r.med = med;
       r.j = p.j ? p.j + b0 * p.j_stride : nullptr;
       r.j_stride = p.j_stride;
@@ -604,6 +654,8 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
         if ((e = timed_begin(st, RTMI_KERNEL_RECORD, &tl)) != hipSuccess) return hip_fail(e, "timing");
         if ((e = rtmi::launch_record(r, nb, p.j_stride == 0, plan.det, blocks, st)) != hipSuccess)
           return hip_fail(e, "record launch");
+        if (fix_waves > 0 && (e = rtmi::launch_fixup(r, nb, plan.det, fix_waves, st)) != hipSuccess)
+          return hip_fail(e, "record fixup launch");
         if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
       }
       TimedLaunch tl;

@@ -69,6 +69,17 @@ struct RecordArgs {
   int vstride[kMaxSrcPerLaunch];
   long long vbase[kMaxSrcPerLaunch];
   const float4* dirs[kMaxSrcPerLaunch];
+  // Segments: with seg_len > 0 each ray's substeps are cut into runs of seg_len (a
+  // multiple of kRowAlign) marched by separate lanes from I = 0, E = 1. Eq. (2) is linear
+  // in the entry state (I0, E0): I_k = I0 P_k + E0 Q_k with P, Q the run's values from
+  // (0, 1), so a later pass (fixup) turns the stored wray Q_k and P_k into the deposit
+  // values once the runs' end states are chained.
+  int seg_len;                // 0: whole rays
+  int nseg[kMaxSrcPerLaunch]; // runs per ray
+  float* P;                   // rows like V: P_k of runs after the first
+  float2* segtot;             // [(sbase + ray * nseg + run) * NB + bin]: (Q, P) at the run's end
+  long long sbase[kMaxSrcPerLaunch];
+  int fbegin[kMaxSrcPerLaunch + 1];  // prefix sums over sources of nrays * (nseg - 1)
 };
 
 // Phase 2: tile-owned accumulation of the recorded deposit values.
@@ -143,6 +154,8 @@ struct DebugArgs {
 hipError_t launch_march(const MarchArgs& a, int n_bins, bool shared_j, bool deterministic,
                         int n_blocks, hipStream_t s);
 hipError_t launch_debug(const DebugArgs& a, hipStream_t s);
+// Deposit values of the runs after the first (segment mode): one wave per run.
+hipError_t launch_fixup(const RecordArgs& a, int n_bins, bool deterministic, int waves, hipStream_t s);
 hipError_t launch_record(const RecordArgs& a, int n_bins, bool shared_j, bool deterministic,
                          int n_blocks, hipStream_t s);   // uses a.med when it is not null
 // Surrogate network: 3x3x3 convolutions over channels-last bf16 activations.

@@ -59,16 +59,24 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
   const int blk = (static_cast<int>(blockIdx.x) % kXcds) * per_xcd + static_cast<int>(blockIdx.x) / kXcds;
   int s = 0;
   while (s + 1 < a.n_src && blk >= a.blk_begin[s + 1]) ++s;
-  const int ray = (blk - a.blk_begin[s]) * kBlock + tid;
+  // blocks of a source: run-major, then ray blocks
+  const int rblocks = (a.nrays[s] + kBlock - 1) / kBlock;
+  const int seg = (a.seg_len > 0 && rblocks > 0) ? (blk - a.blk_begin[s]) / rblocks : 0;
+  const int ray = ((blk - a.blk_begin[s]) - seg * rblocks) * kBlock + tid;
   if (blk < nblk && ray < a.nrays[s]) {
     const float4 d = a.dirs[s][ray];
     const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
     const float wray = a.wray[s];
-    const int nsub = a.nsub[s];
+    const int k_begin = a.seg_len > 0 ? seg * a.seg_len : 0;
+    const int nsub = a.seg_len > 0 ? min(a.nsub[s], k_begin + a.seg_len) : a.nsub[s];   // run end
     const float ds = a.ds;
     const int nx = a.nx, ny = a.ny, nz = a.nz, nyz = ny * nz;
     const bool shared_k = (a.k_stride == 0);
     float* vrow = a.V + a.vbase[s] + static_cast<long long>(ray) * a.vstride[s];
+    // runs after the first keep their attenuation P_k, and their samples collapsed onto a
+    // box corner are summed by the fixup, which knows the entry state
+    float* prow = seg > 0 ? a.P + a.vbase[s] + static_cast<long long>(ray) * a.vstride[s] : nullptr;
+    const bool tails_here = seg == 0;
     double det_scale = 0.0;
     if constexpr (DET) det_scale = *a.det_scale;
 
@@ -91,7 +99,8 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
     // placed at the loop head and every iteration also waits for the previous stores.
     __builtin_amdgcn_s_waitcnt(0);
 
-    for (int k0 = 0; k0 < nsub; k0 += C) {
+    float pprev[C][NB];
+    for (int k0 = k_begin; k0 < nsub; k0 += C) {
       float jv[C][NB][8];
       float kv[C][NB];
       float fx[C], fy[C], fz[C];
@@ -152,9 +161,16 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
           for (int q = 0; q < C / 4; ++q)
             dst[q] = make_float4(vprev[4 * q][b], vprev[4 * q + 1][b], vprev[4 * q + 2][b],
                                  vprev[4 * q + 3][b]);
+          if (prow) {
+            float4* pdst = reinterpret_cast<float4*>(prow + b * a.v_bin_stride + kprev);
+#pragma unroll
+            for (int q = 0; q < C / 4; ++q)
+              pdst[q] = make_float4(pprev[4 * q][b], pprev[4 * q + 1][b], pprev[4 * q + 2][b],
+                                    pprev[4 * q + 3][b]);
+          }
         }
       }
-      float vout[C][NB];
+      float vout[C][NB], pout[C][NB];
 #pragma unroll
       for (int t = 0; t < C; ++t) {
         const float wx[2] = {1.0f - fx[t], fx[t]};
@@ -171,7 +187,7 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
           jk[b] = acc;
         }
         const bool live = (k0 + t) < nsub;
-        const bool collapsed = live && cid[t] >= 0;
+        const bool collapsed = tails_here && live && cid[t] >= 0;
         // A ray can pass several corner regions (a source outside the box, a ray that
         // misses it): hand the running sum over whenever the corner changes.
         if (collapsed && cid[t] != corner) {
@@ -206,12 +222,16 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
             v = 0.0f;
           }
           vout[t][b] = live ? v : 0.0f;
+          pout[t][b] = live ? E[b] : 0.0f;
         }
       }
 #pragma unroll
       for (int t = 0; t < C; ++t)
 #pragma unroll
-        for (int b = 0; b < NB; ++b) vprev[t][b] = vout[t][b];
+        for (int b = 0; b < NB; ++b) {
+          vprev[t][b] = vout[t][b];
+          pprev[t][b] = pout[t][b];
+        }
       kprev = k0;
     }
     // the last chunk, in whole 16-byte pieces (rows are padded to a multiple of 8 substeps)
@@ -223,7 +243,19 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
         for (int q = 0; q < C / 4; ++q)
           dst[q] = make_float4(vprev[4 * q][b], vprev[4 * q + 1][b], vprev[4 * q + 2][b],
                                vprev[4 * q + 3][b]);
+        if (prow) {
+          float4* pdst = reinterpret_cast<float4*>(prow + b * a.v_bin_stride + kprev);
+#pragma unroll
+          for (int q = 0; q < C / 4; ++q)
+            pdst[q] = make_float4(pprev[4 * q][b], pprev[4 * q + 1][b], pprev[4 * q + 2][b],
+                                  pprev[4 * q + 3][b]);
+        }
       }
+    }
+    if (a.seg_len > 0) {   // the run's end state, in units of wray for Q
+      float2* st = a.segtot + (a.sbase[s] + static_cast<long long>(ray) * a.nseg[s] + seg) * NB;
+#pragma unroll
+      for (int b = 0; b < NB; ++b) st[b] = make_float2(I[b], E[b]);
     }
     if (corner >= 0) {
 #pragma unroll
@@ -232,6 +264,86 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
           atomicAdd(&ctail_q[b][corner], static_cast<unsigned long long>(tail_q[b]));
         else
           atomicAdd(&ctail[b][corner], tail[b]);
+      }
+    }
+  }
+  __syncthreads();
+  if (tid < NB * 8) {
+    const int b = tid / 8, c = tid % 8;
+    if constexpr (DET) {
+      if (ctail_q[b][c] != 0ull) atomicAdd(a.corner_q + b * 8 + c, ctail_q[b][c]);
+    } else {
+      if (ctail[b][c] != 0.0f) unsafeAtomicAdd(a.corner + b * 8 + c, ctail[b][c]);
+    }
+  }
+}
+
+// Segment mode: deposit values of the runs after the first. One wave per (ray, run): the
+// entry state (I0, E0) chains the earlier runs' end states, then each lane takes samples
+// of the run, v_k = E0 (wray Q_k) + I0 wray P_k; samples collapsed onto a box corner go
+// to the corner sums instead (the tile kernel skips them).
+constexpr int kFixupThreads = 256;
+
+template <int NB, bool DET>
+__global__ void __launch_bounds__(kFixupThreads) fixup_kernel(const RecordArgs a) {
+  __shared__ float ctail[NB][8];
+  __shared__ unsigned long long ctail_q[NB][8];
+  const int tid = static_cast<int>(threadIdx.x), lane = tid & 63;
+  if (tid < NB * 8) {
+    ctail[tid / 8][tid % 8] = 0.0f;
+    ctail_q[tid / 8][tid % 8] = 0ull;
+  }
+  __syncthreads();
+  const int w = static_cast<int>(blockIdx.x) * (kFixupThreads / 64) + (tid >> 6);
+  if (w < a.fbegin[a.n_src]) {
+    int s = 0;
+    while (s + 1 < a.n_src && w >= a.fbegin[s + 1]) ++s;
+    const int local = w - a.fbegin[s];
+    const int nrays = a.nrays[s];
+    const int seg = 1 + local / nrays, ray = local % nrays;
+    const float2* st = a.segtot + (a.sbase[s] + static_cast<long long>(ray) * a.nseg[s]) * NB;
+    float I0[NB], E0[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+      I0[b] = 0.0f;
+      E0[b] = 1.0f;
+    }
+    for (int r = 0; r < seg; ++r) {
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float2 qp = st[r * NB + b];
+        I0[b] = I0[b] * qp.y + E0[b] * qp.x;
+        E0[b] = E0[b] * qp.y;
+      }
+    }
+    const float wray = a.wray[s];
+    const float4 d = a.dirs[s][ray];
+    const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
+    const int k_begin = seg * a.seg_len, k_end = min(a.nsub[s], k_begin + a.seg_len);
+    const long long row = a.vbase[s] + static_cast<long long>(ray) * a.vstride[s];
+    double det_scale = 0.0;
+    if constexpr (DET) det_scale = *a.det_scale;
+    for (int k = k_begin + lane; k < k_end; k += 64) {
+      const float dist = sample_distance(k, a.ds);
+      const float x = sample_axis(sx, dist, d.x);
+      const float y = sample_axis(sy, dist, d.y);
+      const float z = sample_axis(sz, dist, d.z);
+      const bool collapsed = axis_clamped(x, a.nx) && axis_clamped(y, a.ny) && axis_clamped(z, a.nz);
+      const int cid = (x >= 0.0f ? 4 : 0) | (y >= 0.0f ? 2 : 0) | (z >= 0.0f ? 1 : 0);
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        float* v = a.V + row + b * a.v_bin_stride + k;
+        const float p = a.P[row + b * a.v_bin_stride + k];
+        const float val = E0[b] * *v + I0[b] * (wray * p);
+        if (collapsed) {
+          if constexpr (DET)
+            atomicAdd(&ctail_q[b][cid], static_cast<unsigned long long>(__double2ll_rn(static_cast<double>(val) * det_scale)));
+          else
+            atomicAdd(&ctail[b][cid], val);
+          *v = 0.0f;
+        } else {
+          *v = val;
+        }
       }
     }
   }
@@ -834,6 +946,24 @@ hipError_t launch_tile_nb(const TileArgs& a, bool det, bool nearest, hipStream_t
 }
 
 }  // namespace
+
+template <int NB>
+void launch_fixup_nb(const RecordArgs& a, bool det, dim3 grid, hipStream_t s) {
+  if (det) hipLaunchKernelGGL((fixup_kernel<NB, true>), grid, dim3(kFixupThreads), 0, s, a);
+  else hipLaunchKernelGGL((fixup_kernel<NB, false>), grid, dim3(kFixupThreads), 0, s, a);
+}
+
+hipError_t launch_fixup(const RecordArgs& a, int n_bins, bool det, int waves, hipStream_t s) {
+  const dim3 grid((waves + kFixupThreads / 64 - 1) / (kFixupThreads / 64));
+  switch (n_bins) {
+    case 1: launch_fixup_nb<1>(a, det, grid, s); break;
+    case 2: launch_fixup_nb<2>(a, det, grid, s); break;
+    case 3: launch_fixup_nb<3>(a, det, grid, s); break;
+    case 4: launch_fixup_nb<4>(a, det, grid, s); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_record(const RecordArgs& a, int n_bins, bool shared_j, bool det, int blocks,
                          hipStream_t s) {
