@@ -86,9 +86,10 @@ typedef struct rtmi_options {
  *  RTMI_PATH_TILED: two kernels. A record kernel runs each ray's recurrence and writes
  *    the deposit value of every substep to a workspace; a tile kernel then lets each
  *    work-group own a 16^3 block of the output, accumulate the deposits landing in it
- *    in LDS and store it once. Workspace: 4 bytes per (ray, substep, bin), taken from a
- *    stream-ordered pool the library owns per device (allocated on first use, then
- *    reused; see rtmi_reserve).
+ *    in LDS and add it to the field. Workspace: 4 bytes per (ray, substep, bin), plus
+ *    64 bytes per voxel (a gather table of j and kappa) when j and kappa are shared by
+ *    the bins, taken from a stream-ordered pool the library owns per device (allocated
+ *    on first use, then reused; see rtmi_reserve).
  *  RTMI_PATH_DIRECT: one kernel; each lane sums its ray's consecutive deposits into a
  *    2x2x2 register window and flushes it with global atomics. No workspace. */
 enum { RTMI_PATH_TILED = 0, RTMI_PATH_DIRECT = 1 };

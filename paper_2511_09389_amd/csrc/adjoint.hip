@@ -17,8 +17,6 @@
 namespace rtmi {
 namespace {
 
-typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
-
 struct SampleAD {
   float j;      // trilinear j
   float kap;    // nearest kappa
@@ -42,22 +40,25 @@ __device__ __forceinline__ SampleAD adjoint_sample(const AdjointArgs& a, float s
   const float wx[2] = {X.w0, X.w1};
   const float wy[2] = {Y.w0, Y.w1};
   const float wz[2] = {Z.w0, Z.w1};
-  const bool zsame = Z.lo == Z.hi;
-  const int nsel = (X.nearest == X.hi ? 4 : 0) | (Y.nearest == Y.hi ? 2 : 0);
-  const bool zsel = Z.nearest == Z.hi && !zsame;
+  // j and kappa from the gather table's line of the lower corner; a collapsed axis takes
+  // weight 1 on its lower corner (the table's upper corner may be another voxel there)
+  const float4* line = a.med + 4ll * (static_cast<long long>(X.lo) * nyz + Y.lo * nz + Z.lo);
+  const float4 j0 = line[0], j1 = line[1], k0v = line[2], k1v = line[3];
+  const float jc[8] = {j0.x, j0.y, j0.z, j0.w, j1.x, j1.y, j1.z, j1.w};
+  const float kc[8] = {k0v.x, k0v.y, k0v.z, k0v.w, k1v.x, k1v.y, k1v.z, k1v.w};
+  const float cx[2] = {X.lo == X.hi ? 1.0f : X.w0, X.lo == X.hi ? 0.0f : X.w1};
+  const float cy[2] = {Y.lo == Y.hi ? 1.0f : Y.w0, Y.lo == Y.hi ? 0.0f : Y.w1};
+  const float cz[2] = {Z.lo == Z.hi ? 1.0f : Z.w0, Z.lo == Z.hi ? 0.0f : Z.w1};
+  const int nsel = (X.nearest != X.lo ? 4 : 0) | (Y.nearest != Y.lo ? 2 : 0) | (Z.nearest != Z.lo ? 1 : 0);
   SampleAD r;
   r.j = 0.0f;
-  r.kap = 0.0f;
+  r.kap = kc[0];
   float gsum = 0.0f;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int col = ox[q >> 1] + oy[q & 1];
-    const f4a8 v = *reinterpret_cast<const f4a8*>(a.med + col + oz[0]);
-    const float w01 = wx[q >> 1] * wy[q & 1];
-    const float j0 = v.x, j1 = zsame ? v.x : v.z;
-    r.j += w01 * wz[0] * j0 + w01 * wz[1] * j1;
-    if ((q << 1) == nsel) r.kap = zsel ? v.w : v.y;
-    gsum += w01 * wz[0] * a.grad[col + oz[0]] + w01 * wz[1] * a.grad[col + oz[1]];
+  for (int c = 0; c < 8; ++c) {
+    r.j += (cx[c >> 2] * cy[(c >> 1) & 1]) * cz[c & 1] * jc[c];
+    r.kap = c == nsel ? kc[c] : r.kap;
+    gsum += (wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1] * a.grad[ox[c >> 2] + oy[(c >> 1) & 1] + oz[c & 1]];
   }
   r.g = wray * gsum;
   const bool out3 = axis_clamped(x, nx) && axis_clamped(y, ny) && axis_clamped(z, nz);

@@ -531,7 +531,7 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
   L.corner = 0;
   L.sched = 2 * kCornerBytes;
   L.med = L.sched + L.sched_bytes * (sched_per_launch ? L.n_launch : 1);
-  L.v = L.med + (L.interleaved ? align256((size_t(plan.cells) + 1) * sizeof(float2)) : 0);
+  L.v = L.med + (L.interleaved ? align256(size_t(plan.cells) * 4 * sizeof(float4)) : 0);
   L.p = L.v + align256(size_t(v_elems_max) * nb_max * sizeof(float));
   L.segtot = L.p + align256(size_t(p_elems_max) * nb_max * sizeof(float));
   L.total = L.segtot + size_t(t_elems_max) * nb_max * sizeof(float2);
@@ -556,14 +556,14 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
   }
   float* corner = reinterpret_cast<float*>(ws + L.corner);
   unsigned long long* corner_q = reinterpret_cast<unsigned long long*>(ws + L.corner + kCornerBytes);
-  float2* med = L.interleaved ? reinterpret_cast<float2*>(ws + L.med) : nullptr;
+  float4* med = L.interleaved ? reinterpret_cast<float4*>(ws + L.med) : nullptr;
   float* V = reinterpret_cast<float*>(ws + L.v);
   float* Prow = reinterpret_cast<float*>(ws + L.p);
   float2* segtot = reinterpret_cast<float2*>(ws + L.segtot);
   hipError_t e;
   if (mode != TiledMode::kSchedule) {
-    if (L.interleaved && (e = rtmi::launch_interleave(p.j, p.kap, med, plan.cells, st)) != hipSuccess)
-      return hip_fail(e, "interleave");
+    if (L.interleaved && (e = rtmi::launch_cell_table(p.j, p.kap, med, p.nx, p.ny, p.nz, st)) != hipSuccess)
+      return hip_fail(e, "gather table");
     // every tile launch adds into the zeroed field
     const int64_t total = plan.cells * p.n_bins;
     if (plan.det) e = rtmi::launch_fill_zero_u64(out_q, total, st);
@@ -800,7 +800,7 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
     c_elems_max = std::max(c_elems_max, c);
   }
   const size_t corner_bytes = 256;
-  const size_t med_bytes = ((size_t(plan.cells) + 1) * sizeof(float2) + 255) / 256 * 256;
+  const size_t med_bytes = align256(size_t(plan.cells) * 4 * sizeof(float4));
   const size_t v_bytes = (size_t(v_elems_max) * sizeof(float) + 255) / 256 * 256;
   const size_t c_bytes = size_t(c_elems_max) * sizeof(float2);
   const int tiles_x = (p.nx + kTile - 1) / kTile, tiles_y = (p.ny + kTile - 1) / kTile,
@@ -814,12 +814,13 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
   TileSchedule sched;
   sched.carve(ws + corner_bytes + med_bytes + 2 * v_bytes + c_bytes, tiles);
   float* corner = reinterpret_cast<float*>(ws);  // [0..7] for dL/dj, [8..15] for dL/dkappa
-  float2* med = reinterpret_cast<float2*>(ws + corner_bytes);
+  float4* med = reinterpret_cast<float4*>(ws + corner_bytes);
   float* Vj = reinterpret_cast<float*>(ws + corner_bytes + med_bytes);
   float* Vk = reinterpret_cast<float*>(ws + corner_bytes + med_bytes + v_bytes);
   float2* ckpt = reinterpret_cast<float2*>(ws + corner_bytes + med_bytes + 2 * v_bytes);
   hipError_t e;
-  if ((e = rtmi::launch_interleave(p.j, p.kap, med, plan.cells, st)) != hipSuccess) return hip_fail(e, "interleave");
+  if ((e = rtmi::launch_cell_table(p.j, p.kap, med, p.nx, p.ny, p.nz, st)) != hipSuccess)
+    return hip_fail(e, "gather table");
   if ((e = rtmi::launch_fill_zero(grad_j, plan.cells, st)) != hipSuccess ||
       (e = rtmi::launch_fill_zero(grad_k, plan.cells, st)) != hipSuccess)
     return hip_fail(e, "fill");

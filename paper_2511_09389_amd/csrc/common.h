@@ -47,7 +47,7 @@ struct MarchArgs {
 
 // Phase 1 of the two-phase march: per-ray recurrence, deposit values to the workspace.
 struct RecordArgs {
-  const float2* med;          // (j, kappa) interleaved, one padding voxel at the end; or null
+  const float4* med;          // gather table (8 corners of j, then of kappa, per voxel), or null
   const float* j;
   long long j_stride;
   const float* kap;
@@ -116,7 +116,7 @@ struct TileArgs {
 
 // Adjoint of the march: per-ray reverse sweep with checkpointed recomputation.
 struct AdjointArgs {
-  const float2* med;          // (j, kappa) interleaved, one padding voxel at the end
+  const float4* med;          // gather table: 8 corners of j, then of kappa, per voxel
   const float* grad;          // dL/dJ, [nx][ny][nz]
   float* Vj;                  // rows: dL/dj contribution of each sample (I-bar E ds)
   float* Vk;                  // rows: dL/dkappa of each sample, deposited at its nearest voxel
@@ -204,7 +204,8 @@ hipError_t launch_tile_schedule(const TileArgs& a, int tiles, hipStream_t s);
 hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool deterministic, bool nearest,
                            hipStream_t s);
 hipError_t launch_adjoint_record(const AdjointArgs& a, int n_blocks, hipStream_t s);
-hipError_t launch_interleave(const float* j, const float* kap, float2* med, long long cells,
+// Gather table of j and kappa (64 bytes per voxel) for the record and adjoint kernels.
+hipError_t launch_cell_table(const float* j, const float* kap, float4* table, int nx, int ny, int nz,
                              hipStream_t s);
 hipError_t launch_fill_zero(float* p, long long n, hipStream_t s);
 hipError_t launch_fill_zero_u64(unsigned long long* p, long long n, hipStream_t s);

@@ -26,20 +26,36 @@ constexpr float kBig = 1.0e30f;
 constexpr int kCacheDevices = 64;
 constexpr float kCosConeLimit = -0.99913515f;   // cos(3.1)
 
-// 16-byte vector that needs only 8-byte alignment: two consecutive (j, kappa) voxels.
-typedef float f4a8 __attribute__((ext_vector_type(4), aligned(8)));
-
-__global__ void interleave_kernel(const float* __restrict__ j, const float* __restrict__ kap,
-                                  float2* __restrict__ med, long long cells) {
+// The gather table of a shared j and a shared (unscaled) kappa: for every voxel (x, y, z),
+// the eight corners (x + cx, y + cy, z + cz), clamped to the box, of j and then of kappa,
+// 64 bytes (one cache line) per voxel, corner c = (cx << 2) | (cy << 1) | cz. A sample
+// reads its stencil and its nearest kappa (always one of the corners) from the one line of
+// its lower corner: four lines per sample become one. The lines of the voxels on the upper
+// faces repeat clamped corners; a collapsed axis (lower = upper corner) takes weight 1 on
+// its lower corner.
+__global__ void cell_table_kernel(const float* __restrict__ j, const float* __restrict__ kap,
+                                  float4* __restrict__ table, int nx, int ny, int nz) {
+  const long long cells = static_cast<long long>(nx) * ny * nz;
   const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
-  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i <= cells;
-       i += stride)
-    med[i] = i < cells ? make_float2(j[i], kap[i]) : make_float2(0.0f, 0.0f);
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < cells; i += stride) {
+    const int z = static_cast<int>(i % nz), y = static_cast<int>((i / nz) % ny);
+    const int x = static_cast<int>(i / (static_cast<long long>(ny) * nz));
+    float jc[8], kc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int xx = min(x + (c >> 2), nx - 1), yy = min(y + ((c >> 1) & 1), ny - 1), zz = min(z + (c & 1), nz - 1);
+      const long long v = (static_cast<long long>(xx) * ny + yy) * nz + zz;
+      jc[c] = j[v];
+      kc[c] = kap[v];
+    }
+    table[4 * i] = make_float4(jc[0], jc[1], jc[2], jc[3]);
+    table[4 * i + 1] = make_float4(jc[4], jc[5], jc[6], jc[7]);
+    table[4 * i + 2] = make_float4(kc[0], kc[1], kc[2], kc[3]);
+    table[4 * i + 3] = make_float4(kc[4], kc[5], kc[6], kc[7]);
+  }
 }
 
-// MED: j and kappa come interleaved from a.med (a shared j and a shared, scaled kappa);
-// one 16-byte load returns (j, kappa) of the two z-corners of one (x, y) column, and the
-// nearest voxel, always one of the eight corners, supplies kappa without a ninth load.
+// MED: j and kappa come from the gather table a.med (one 64-byte line per sample).
 template <int NB, bool SHARED_J, bool DET, bool MED>
 __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
   constexpr int C = SHARED_J ? 8 : 4;
@@ -120,17 +136,21 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
         const int oy[2] = {Y.lo * nz, Y.hi * nz};
         const int oz[2] = {Z.lo, Z.hi};
         if constexpr (MED) {
-          const bool zsame = Z.lo == Z.hi;
-          const int nsel = ((X.nearest == X.hi ? 4 : 0) | (Y.nearest == Y.hi ? 2 : 0));
-          const bool zsel = Z.nearest == Z.hi && !zsame;
-          float kn = 0.0f;
+          const float4* line = a.med + 4ll * (static_cast<long long>(X.lo) * nyz + Y.lo * nz + Z.lo);
+          const float4 j0 = line[0], j1 = line[1], k0v = line[2], k1v = line[3];
+          jv[t][0][0] = j0.x;
+          jv[t][0][1] = j0.y;
+          jv[t][0][2] = j0.z;
+          jv[t][0][3] = j0.w;
+          jv[t][0][4] = j1.x;
+          jv[t][0][5] = j1.y;
+          jv[t][0][6] = j1.z;
+          jv[t][0][7] = j1.w;
+          const int nsel = (X.nearest != X.lo ? 4 : 0) | (Y.nearest != Y.lo ? 2 : 0) | (Z.nearest != Z.lo ? 1 : 0);
+          const float kc[8] = {k0v.x, k0v.y, k0v.z, k0v.w, k1v.x, k1v.y, k1v.z, k1v.w};
+          float kn = kc[0];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const f4a8 v = *reinterpret_cast<const f4a8*>(a.med + ox[q >> 1] + oy[q & 1] + oz[0]);
-            jv[t][0][2 * q] = v.x;
-            jv[t][0][2 * q + 1] = zsame ? v.x : v.z;
-            if ((q << 1) == nsel) kn = zsel ? v.w : v.y;
-          }
+          for (int q = 1; q < 8; ++q) kn = q == nsel ? kc[q] : kn;
           kv[t][0] = kn;
         } else {
           const int nearest = X.nearest * nyz + Y.nearest * nz + Z.nearest;
@@ -147,9 +167,10 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
             kv[t][b] = a.kap[b * a.k_stride + nearest];
           }
         }
-        fx[t] = X.w1;
-        fy[t] = Y.w1;
-        fz[t] = Z.w1;
+        // (the gather table's upper corner of a collapsed axis may be another voxel)
+        fx[t] = (MED && X.lo == X.hi) ? 0.0f : X.w1;
+        fy[t] = (MED && Y.lo == Y.hi) ? 0.0f : Y.w1;
+        fz[t] = (MED && Z.lo == Z.hi) ? 0.0f : Z.w1;
         const bool out3 = axis_clamped(x, nx) && axis_clamped(y, ny) && axis_clamped(z, nz);
         cid[t] = out3 ? ((x >= 0.0f ? 4 : 0) | (y >= 0.0f ? 2 : 0) | (z >= 0.0f ? 1 : 0)) : -1;
       }
@@ -976,12 +997,13 @@ hipError_t launch_record(const RecordArgs& a, int n_bins, bool shared_j, bool de
   }
 }
 
-hipError_t launch_interleave(const float* j, const float* kap, float2* med, long long cells,
+hipError_t launch_cell_table(const float* j, const float* kap, float4* table, int nx, int ny, int nz,
                              hipStream_t s) {
-  long long blocks = (cells + 1 + kBlock * 4 - 1) / (kBlock * 4);
-  blocks = blocks < 1 ? 1 : (blocks > 8192 ? 8192 : blocks);
-  hipLaunchKernelGGL(interleave_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, j,
-                     kap, med, cells);
+  const long long cells = static_cast<long long>(nx) * ny * nz;
+  long long blocks = (cells + kBlock * 4 - 1) / (kBlock * 4);
+  blocks = blocks < 1 ? 1 : (blocks > 16384 ? 16384 : blocks);
+  hipLaunchKernelGGL(cell_table_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, j, kap, table,
+                     nx, ny, nz);
   return hipGetLastError();
 }
 
