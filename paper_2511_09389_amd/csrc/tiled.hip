@@ -414,8 +414,8 @@ __device__ __forceinline__ T tile_value(float v, double scale) {
     return static_cast<T>(v);
 }
 
-// One axis of a sample's stencil as seen from a tile: both corners' offsets in the LDS
-// block, clamped into the tile, and their weights, zero for a corner outside the tile
+// One axis of a sample's stencil as seen from a tile: both corners' tile coordinates,
+// clamped into the tile, and their weights, zero for a corner outside the tile
 // (another tile owns it). An axis whose two corners coincide carries its whole weight
 // on the lower one.
 struct TileAxis {
@@ -424,7 +424,7 @@ struct TileAxis {
   bool any;   // some corner of this axis lies in the tile
 };
 
-__device__ __forceinline__ TileAxis tile_axis(const Axis& A, int origin, int extent, int stride) {
+__device__ __forceinline__ TileAxis tile_axis(const Axis& A, int origin, int extent) {
   TileAxis r;
   const bool same = A.lo == A.hi;
   const int l0 = A.lo - origin, l1 = A.hi - origin;
@@ -432,10 +432,18 @@ __device__ __forceinline__ TileAxis tile_axis(const Axis& A, int origin, int ext
   const bool in1 = static_cast<unsigned>(l1) < static_cast<unsigned>(extent) && !same;
   r.w[0] = in0 ? (same ? 1.0f : A.w0) : 0.0f;
   r.w[1] = in1 ? A.w1 : 0.0f;
-  r.off[0] = min(max(l0, 0), extent - 1) * stride;
-  r.off[1] = min(max(l1, 0), extent - 1) * stride;
+  r.off[0] = min(max(l0, 0), extent - 1);
+  r.off[1] = min(max(l1, 0), extent - 1);
   r.any = in0 | in1;
   return r;
+}
+
+// Slot of tile voxel (lx, ly, lz) in the LDS accumulator. Row-major order would put
+// lx in no bank bit (a 256-element stride) and ly in one, so lanes whose samples differ
+// mainly in x would queue on one bank; XOR-ing lz with a hash of (lx, ly) spreads them
+// over the banks and stays a permutation within each z-row.
+__device__ __forceinline__ int tile_slot(int lx, int ly, int lz) {
+  return (lx * kTile + ly) * kTile + (lz ^ ((lx + 3 * ly) & (kTile - 1)));
 }
 
 // ---- output tiles ----
@@ -853,18 +861,18 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
                   (static_cast<unsigned>(ly) >= static_cast<unsigned>(ey)) |
                   (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
                 continue;
-              const int li = (lx * kTile + ly) * kTile + lz;
+              const int li = tile_slot(lx, ly, lz);
 #pragma unroll
               for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][t], det_scale));
             } else {
-              const TileAxis tx = tile_axis(X, x0, ex, kTile * kTile);
-              const TileAxis ty = tile_axis(Y, y0, ey, kTile);
-              const TileAxis tz = tile_axis(Z, z0, ez, 1);
+              const TileAxis tx = tile_axis(X, x0, ex);
+              const TileAxis ty = tile_axis(Y, y0, ey);
+              const TileAxis tz = tile_axis(Z, z0, ez);
               if (!(tx.any & ty.any & tz.any)) continue;
 #pragma unroll
               for (int c = 0; c < 8; ++c) {
                 const float w = (tx.w[c >> 2] * ty.w[(c >> 1) & 1]) * tz.w[c & 1];
-                const int li = tx.off[c >> 2] + ty.off[(c >> 1) & 1] + tz.off[c & 1];
+                const int li = tile_slot(tx.off[c >> 2], ty.off[(c >> 1) & 1], tz.off[c & 1]);
 #pragma unroll
                 for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][t] * w, det_scale));
               }
@@ -885,7 +893,7 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
                  cz_any = (gz == 0 || gz == nz - 1);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        T val = acc[b][i];
+        T val = acc[b][tile_slot(lx, ly, lz)];
         if (cx_any && cy_any && cz_any && part == 0) {
           for (int c = 0; c < 8; ++c) {
             const int vx = (c & 4) ? nx - 1 : 0, vy = (c & 2) ? ny - 1 : 0, vz = (c & 1) ? nz - 1 : 0;
