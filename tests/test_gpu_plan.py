@@ -162,3 +162,28 @@ def test_autotune_picks_and_caches(rt, dev, batch, tmp_path, monkeypatch):
     want = rt.trace_bins(j, k, w.source_pos, rays, w.step_size, w.radiation_velocity, w.time_step,
                          kappa_scale=scale, substep_cap=caps)
     assert rel_l2(plan.execute(j, k), want) < 1e-6
+
+
+def test_plan_per_bin_maps(rt, dev, batch):
+    """Per-bin j and kappa maps (bin strides = nx*ny*nz) through a plan equal trace_bins."""
+    w, rays, caps, scale, j, k = batch
+    jb = torch.stack([j, 0.5 * j, 2.0 * j]).contiguous()
+    kb = torch.stack([k, 0.3 * k, 1.7 * k]).contiguous()
+    want = rt.trace_bins(jb, kb, w.source_pos, rays, w.step_size, w.radiation_velocity, w.time_step,
+                         substep_cap=caps, deterministic=True)
+    plan = rt.Plan(w.shape, w.source_pos, rays, w.step_size, w.radiation_velocity, w.time_step,
+                   n_bins=3, per_bin_j=True, per_bin_kappa=True, substep_cap=caps, deterministic=True)
+    got = plan.execute(jb, kb)
+    assert torch.equal(got.view(torch.int32), want.view(torch.int32))
+
+
+@pytest.mark.parametrize("chunks", [1, 100, 100000])
+def test_schedule_does_not_change_the_bits(rt, dev, batch, chunks):
+    """In the deterministic mode the work-item size (1 chunk: every tile split into the
+    maximum number of items; 100000: one item per tile) leaves the field bit for bit."""
+    w, rays, caps, scale, j, k = batch
+    want = rt.trace_bins(j, k, w.source_pos, rays, w.step_size, w.radiation_velocity, w.time_step,
+                         kappa_scale=scale, substep_cap=caps, deterministic=True)
+    got = rt.trace_bins(j, k, w.source_pos, rays, w.step_size, w.radiation_velocity, w.time_step,
+                        kappa_scale=scale, substep_cap=caps, deterministic=True, tile_item_chunks=chunks)
+    assert torch.equal(got.view(torch.int32), want.view(torch.int32))
