@@ -499,6 +499,8 @@ struct SrcTable {
   int pbegin[kMaxSrcPerLaunch + 1];
   int nsub[kMaxSrcPerLaunch];
   int nrays[kMaxSrcPerLaunch];
+  const float* pbounds[kMaxSrcPerLaunch];
+  const float4* dirs[kMaxSrcPerLaunch];
 };
 
 __device__ __forceinline__ void load_sources(const TileArgs& a, SrcTable& S, int tid) {
@@ -509,6 +511,8 @@ __device__ __forceinline__ void load_sources(const TileArgs& a, SrcTable& S, int
     S.marg[tid] = 5.0e-7f * (fmaxf(fabsf(sx), fmaxf(fabsf(sy), fabsf(sz))) + tmax + 2.0f) + 1.0e-6f;
     S.nsub[tid] = a.nsub[tid];
     S.nrays[tid] = a.nrays[tid];
+    S.pbounds[tid] = a.pbounds[tid];
+    S.dirs[tid] = a.dirs[tid];
   }
   if (tid <= a.n_src) S.pbegin[tid] = a.pbegin[tid];
 }
@@ -531,7 +535,7 @@ __device__ __forceinline__ bool pair_reaches(const TileArgs& a, const SrcTable& 
                                              int s, int patch) {
   const float4 P = S.pos[s];
   const float sx = P.x, sy = P.y, sz = P.z, tmax = P.w, m = S.marg[s];
-  const float* pb = a.pbounds[s] + static_cast<long long>(patch) * kPatchRec;
+  const float* pb = S.pbounds[s] + static_cast<long long>(patch) * kPatchRec;
   bool reach = !(sx + fmaxf(0.0f, tmax * pb[3]) + m < g.Ax || sx + fminf(0.0f, tmax * pb[0]) - m >= g.Bx ||
                  sy + fmaxf(0.0f, tmax * pb[4]) + m < g.Ay || sy + fminf(0.0f, tmax * pb[1]) - m >= g.By ||
                  sz + fmaxf(0.0f, tmax * pb[5]) + m < g.Az || sz + fminf(0.0f, tmax * pb[2]) - m >= g.Bz);
@@ -568,7 +572,7 @@ __device__ __forceinline__ void ray_range(const TileArgs& a, const SrcTable& S, 
   const float4 P = S.pos[s];
   const float sx = P.x, sy = P.y, sz = P.z, tmax = P.w, m = S.marg[s];
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  d = a.dirs[s][ray];
+  d = S.dirs[s][ray];
   const float ix = __builtin_amdgcn_rcpf(d.x), iy = __builtin_amdgcn_rcpf(d.y),
               iz = __builtin_amdgcn_rcpf(d.z);
   float t0 = 0.0f, t1 = tmax;
@@ -607,13 +611,15 @@ __device__ __forceinline__ int range_chunks(int ka, int kb) {
 // Per tile: chunks of all rays that can reach it, plus kPairCost per reaching pair for
 // the pair's own set-up. One wave per pair when counting.
 constexpr int kCostThreads = 256;
+constexpr int kCostPairs = 64;
 constexpr int kPairCost = 16;
 
 __global__ void __launch_bounds__(kCostThreads) tile_cost_kernel(const TileArgs a) {
-  // block (t, q): tile t, pairs [q kCostThreads, (q + 1) kCostThreads); the tile's total
-  // is summed into tile_cost[t], zeroed beforehand
+  // block (t, q): tile t, pairs [q kCostPairs, (q + 1) kCostPairs); the tile's total is
+  // summed into tile_cost[t], zeroed beforehand. Blocks hold few pairs because next to a
+  // source every pair of a block reaches the tile and each needs its rays' ranges.
   __shared__ SrcTable S;
-  __shared__ int list[kCostThreads];
+  __shared__ int list[kCostPairs];
   __shared__ int count;
   __shared__ unsigned long long total;
   const int tid = static_cast<int>(threadIdx.x), wave = tid >> 6, lane = tid & 63;
@@ -625,24 +631,45 @@ __global__ void __launch_bounds__(kCostThreads) tile_cost_kernel(const TileArgs 
   const int t = static_cast<int>(blockIdx.x);
   const TileGeom g = tile_geom(a, t);
   const int npairs = a.pbegin[a.n_src];
-  __syncthreads();
-  const int p = static_cast<int>(blockIdx.y) * kCostThreads + tid;
-  if (p < npairs) {
-    const int s = pair_source(S, a.n_src, p);
-    if (pair_reaches(a, S, g, s, p - S.pbegin[s])) list[atomicAdd(&count, 1)] = p;
-  }
-  __syncthreads();
+  const int nblocks = (npairs + kCostPairs - 1) / kCostPairs;
   unsigned long long sum = 0;
-  for (int i = wave; i < count; i += kCostThreads / 64) {
-    const int q = list[i];
-    const int s = pair_source(S, a.n_src, q);
-    int ka, kb;
-    float4 d;
-    ray_range(a, S, g, s, (q - S.pbegin[s]) * kPatch + lane, ka, kb, d);
-    int c = range_chunks(ka, kb);
+  // (blocks beyond the grid's y extent, 65535, are taken in turn)
+  for (int q0 = static_cast<int>(blockIdx.y); q0 < nblocks; q0 += static_cast<int>(gridDim.y)) {
+    __syncthreads();
+    if (tid == 0) count = 0;
+    __syncthreads();
+    const int p = q0 * kCostPairs + tid;
+    if (tid < kCostPairs && p < npairs) {
+      const int s = pair_source(S, a.n_src, p);
+      if (pair_reaches(a, S, g, s, p - S.pbegin[s])) list[atomicAdd(&count, 1)] = p;
+    }
+    __syncthreads();
+    // A tile next to a source keeps every pair of the block: each wave then counts many
+    // pairs, four at a time so that their direction loads overlap.
+    constexpr int kWavesC = kCostThreads / 64, kUnroll = 4;
+    for (int i0 = wave; i0 < count; i0 += kWavesC * kUnroll) {
+      int c[kUnroll];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
-    sum += c > 0 ? static_cast<unsigned long long>(c + kPairCost) : 0ull;
+      for (int u = 0; u < kUnroll; ++u) {
+        const int i = i0 + u * kWavesC;
+        c[u] = 0;
+        if (i < count) {
+          const int q = list[i];
+          const int s = pair_source(S, a.n_src, q);
+          int ka, kb;
+          float4 d;
+          ray_range(a, S, g, s, (q - S.pbegin[s]) * kPatch + lane, ka, kb, d);
+          c[u] = range_chunks(ka, kb);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        int cu = c[u];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) cu += __shfl_xor(cu, off, 64);
+        sum += cu > 0 ? static_cast<unsigned long long>(cu + kPairCost) : 0ull;
+      }
+    }
   }
   if (lane == 0 && sum) atomicAdd(&total, sum);
   __syncthreads();
@@ -1020,7 +1047,8 @@ hipError_t launch_tile_schedule(const TileArgs& a, int tiles, hipStream_t s) {
   if (e != hipSuccess) return e;
   const int npairs = a.pbegin[a.n_src];
   if (npairs > 0) {   // (without rays every tile keeps a zero cost: one empty item)
-    const dim3 grid(tiles, (npairs + kCostThreads - 1) / kCostThreads);
+    const int nblocks = (npairs + kCostPairs - 1) / kCostPairs;
+    const dim3 grid(tiles, nblocks < 65535 ? nblocks : 65535);
     hipLaunchKernelGGL(tile_cost_kernel, grid, dim3(kCostThreads), 0, s, a);
   }
   hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kScheduleThreads), 0, s, a, tiles);
