@@ -543,12 +543,54 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
 // (everything but the schedules, which a plan keeps).
 enum class TiledMode { kFull, kSchedule, kReplay };
 
+// One (bin chunk, source chunk) launch of the tiled path.
+struct LaunchArgs {
+  rtmi::RecordArgs r;
+  rtmi::TileArgs t;
+  int32_t nb;
+  int blocks;
+  int fix_waves;
+};
+
+// A second stream of the device (default priority), forked from and joined to the
+// caller's stream with events, for work that only depends on the geometry.
+struct SideStream {
+  hipStream_t stream = nullptr;
+  hipEvent_t fork = nullptr, done = nullptr;
+  hipError_t open(hipStream_t from) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    {
+      static std::mutex mu;
+      static std::map<int, hipStream_t> streams;
+      std::lock_guard<std::mutex> lock(mu);
+      auto it = streams.find(dev);
+      if (it == streams.end()) {
+        hipStream_t s = nullptr;
+        if ((e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking)) != hipSuccess) return e;
+        it = streams.emplace(dev, s).first;
+      }
+      stream = it->second;
+    }
+    if ((e = hipEventCreateWithFlags(&fork, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&done, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventRecord(fork, from)) != hipSuccess) return e;
+    return hipStreamWaitEvent(stream, fork, 0);
+  }
+  // marks the end of the side work; the caller's stream waits on `done` where needed
+  hipError_t join(hipStream_t) { return hipEventRecord(done, stream); }
+  ~SideStream() {
+    if (fork) (void)hipEventDestroy(fork);
+    if (done) (void)hipEventDestroy(done);
+  }
+};
+
 int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
                   const double* det_scale, TiledMode mode = TiledMode::kFull,
                   char* given_ws = nullptr) {
   const hipStream_t st = p.stream;
-  const bool per_launch = mode != TiledMode::kFull;
-  const TiledLayout L = tiled_layout(p, plan, per_launch);
+  const TiledLayout L = tiled_layout(p, plan, true);
   char* ws = given_ws;
   if (!ws) {
     if (mode != TiledMode::kFull) return fail(RTMI_ERR_INVALID_ARG, "a plan's workspace is missing");
@@ -561,16 +603,8 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
   float* Prow = reinterpret_cast<float*>(ws + L.p);
   float2* segtot = reinterpret_cast<float2*>(ws + L.segtot);
   hipError_t e;
-  if (mode != TiledMode::kSchedule) {
-    if (L.interleaved && (e = rtmi::launch_cell_table(p.j, p.kap, med, p.nx, p.ny, p.nz, st)) != hipSuccess)
-      return hip_fail(e, "gather table");
-    // every tile launch adds into the zeroed field
-    const int64_t total = plan.cells * p.n_bins;
-    if (plan.det) e = rtmi::launch_fill_zero_u64(out_q, total, st);
-    else e = rtmi::launch_fill_zero(p.out, total, st);
-    if (e != hipSuccess) return hip_fail(e, "fill");
-  }
 
+  std::vector<LaunchArgs> launches;
   int launch = 0;
   for (int32_t b0 = 0; b0 < p.n_bins; b0 += kMaxBinsPerLaunch) {
     const int32_t nb = std::min(kMaxBinsPerLaunch, p.n_bins - b0);
@@ -640,30 +674,55 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       t.tiles_y = L.tiles_y;
       t.tiles_z = L.tiles_z;
       TileSchedule sched;
-      sched.carve(ws + L.sched + (per_launch ? launch * L.sched_bytes : 0), L.tiles);
+      sched.carve(ws + L.sched + launch * L.sched_bytes, L.tiles);
       sched.apply(t, plan.item_chunks);
+      launches.push_back({r, t, nb, blocks, fix_waves});
+    }
+  }
 
-      if (mode != TiledMode::kReplay &&
-          (e = rtmi::launch_tile_schedule(t, L.tiles, st)) != hipSuccess)
+  // The schedules depend on the geometry only. A stateless call computes them on a side
+  // stream, overlapped with the gather table and the first record pass; the first tile
+  // pass waits for them.
+  hipStream_t sched_st = st;
+  SideStream side;
+  if (mode == TiledMode::kFull && side.open(st) == hipSuccess) sched_st = side.stream;
+  if (mode != TiledMode::kReplay)
+    for (const LaunchArgs& l : launches)
+      if ((e = rtmi::launch_tile_schedule(l.t, L.tiles, sched_st)) != hipSuccess)
         return hip_fail(e, "tile schedule");
-      if (mode == TiledMode::kSchedule) continue;
-      if ((e = rtmi::launch_fill_zero(corner, 2 * kCornerBytes / sizeof(float), st)) != hipSuccess)
-        return hip_fail(e, "fill");
-      if (blocks > 0) {
-        TimedLaunch tl;
-        if ((e = timed_begin(st, RTMI_KERNEL_RECORD, &tl)) != hipSuccess) return hip_fail(e, "timing");
-        if ((e = rtmi::launch_record(r, nb, p.j_stride == 0, plan.det, blocks, st)) != hipSuccess)
-          return hip_fail(e, "record launch");
-        if (fix_waves > 0 && (e = rtmi::launch_fixup(r, nb, plan.det, fix_waves, st)) != hipSuccess)
-          return hip_fail(e, "record fixup launch");
-        if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
-      }
+  if (mode == TiledMode::kSchedule) return RTMI_OK;
+  if (sched_st != st && (e = side.join(st)) != hipSuccess) return hip_fail(e, "side stream");
+
+  if (L.interleaved && (e = rtmi::launch_cell_table(p.j, p.kap, med, p.nx, p.ny, p.nz, st)) != hipSuccess)
+    return hip_fail(e, "gather table");
+  {   // every tile launch adds into the zeroed field
+    const int64_t total = plan.cells * p.n_bins;
+    if (plan.det) e = rtmi::launch_fill_zero_u64(out_q, total, st);
+    else e = rtmi::launch_fill_zero(p.out, total, st);
+    if (e != hipSuccess) return hip_fail(e, "fill");
+  }
+  bool joined = sched_st == st;
+  for (const LaunchArgs& l : launches) {
+    if ((e = rtmi::launch_fill_zero(corner, 2 * kCornerBytes / sizeof(float), st)) != hipSuccess)
+      return hip_fail(e, "fill");
+    if (l.blocks > 0) {
       TimedLaunch tl;
-      if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl)) != hipSuccess) return hip_fail(e, "timing");
-      if ((e = rtmi::launch_tile_run(t, nb, plan.det, false, st)) != hipSuccess)
-        return hip_fail(e, "tile launch");
+      if ((e = timed_begin(st, RTMI_KERNEL_RECORD, &tl)) != hipSuccess) return hip_fail(e, "timing");
+      if ((e = rtmi::launch_record(l.r, l.nb, p.j_stride == 0, plan.det, l.blocks, st)) != hipSuccess)
+        return hip_fail(e, "record launch");
+      if (l.fix_waves > 0 && (e = rtmi::launch_fixup(l.r, l.nb, plan.det, l.fix_waves, st)) != hipSuccess)
+        return hip_fail(e, "record fixup launch");
       if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
     }
+    if (!joined) {
+      if ((e = hipStreamWaitEvent(st, side.done, 0)) != hipSuccess) return hip_fail(e, "side stream");
+      joined = true;
+    }
+    TimedLaunch tl;
+    if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl)) != hipSuccess) return hip_fail(e, "timing");
+    if ((e = rtmi::launch_tile_run(l.t, l.nb, plan.det, false, st)) != hipSuccess)
+      return hip_fail(e, "tile launch");
+    if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
   }
   if (!given_ws && (e = hipFreeAsync(ws, st)) != hipSuccess) return hip_fail(e, "workspace release");
   return RTMI_OK;
