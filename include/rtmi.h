@@ -89,7 +89,10 @@ typedef struct rtmi_options {
  *    in LDS and add it to the field. Workspace: 4 bytes per (ray, substep, bin), plus
  *    64 bytes per voxel (a gather table of j and kappa) when j and kappa are shared by
  *    the bins, taken from a stream-ordered pool the library owns per device (allocated
- *    on first use, then reused; see rtmi_reserve).
+ *    on first use, then reused; see rtmi_reserve). The tile schedules, which depend on
+ *    the geometry only, run on a library-owned stream of the same device, ordered by
+ *    events after the caller's earlier work on `stream` and before the tile pass; the
+ *    call's results are still ordered on `stream` like any other enqueued work.
  *  RTMI_PATH_DIRECT: one kernel; each lane sums its ray's consecutive deposits into a
  *    2x2x2 register window and flushes it with global atomics. No workspace. */
 enum { RTMI_PATH_TILED = 0, RTMI_PATH_DIRECT = 1 };
