@@ -84,8 +84,8 @@ __global__ void __launch_bounds__(kBlock) adjoint_record_kernel(const AdjointArg
     const float wray = a.wray[s];
     const int nsub = a.nsub[s];
     const float ds = a.ds;
-    float* vj = a.Vj + a.vbase[s] + static_cast<long long>(ray) * a.vstride[s];
-    float* vk = a.Vk + a.vbase[s] + static_cast<long long>(ray) * a.vstride[s];
+    const long long vb = a.vbase[s];
+    const int vn = a.nrays[s];
     float2* ck = a.ckpt + a.cbase[s] + static_cast<long long>(ray) * a.cstride[s];
     const int nseg = (nsub + kSeg - 1) / kSeg;
 
@@ -159,8 +159,9 @@ __global__ void __launch_bounds__(kBlock) adjoint_record_kernel(const AdjointArg
           outk[t] = vkv;
         }
       }
-      *reinterpret_cast<float4*>(vj + seg * kSeg) = make_float4(outj[0], outj[1], outj[2], outj[3]);
-      *reinterpret_cast<float4*>(vk + seg * kSeg) = make_float4(outk[0], outk[1], outk[2], outk[3]);
+      const long long slot = row_slot(vb, vn, ray, seg * kSeg);
+      *reinterpret_cast<float4*>(a.Vj + slot) = make_float4(outj[0], outj[1], outj[2], outj[3]);
+      *reinterpret_cast<float4*>(a.Vk + slot) = make_float4(outk[0], outk[1], outk[2], outk[3]);
     }
     if (corner >= 0) {
       atomicAdd(&ctail[0][corner], tail_j);

@@ -635,7 +635,6 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
         r.wray[i] = ray_weight(p, plan, s);
         r.nrays[i] = t.nrays[i] = nr;
         r.nsub[i] = t.nsub[i] = plan.nsub[s];
-        r.vstride[i] = t.vstride[i] = static_cast<int>(row_stride(plan.nsub[s]));
         r.vbase[i] = t.vbase[i] = v_elems;
         r.dirs[i] = t.dirs[i] = plan.tables[s].dirs;
         t.pbounds[i] = plan.tables[s].bounds;
@@ -903,7 +902,6 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
       r.wray[i] = ray_weight(p, plan, s);
       r.nrays[i] = t.nrays[i] = nr;
       r.nsub[i] = t.nsub[i] = plan.nsub[s];
-      r.vstride[i] = t.vstride[i] = static_cast<int>(row_stride(plan.nsub[s]));
       r.vbase[i] = t.vbase[i] = v_elems;
       r.cstride[i] = (plan.nsub[s] + rtmi::kSeg - 1) / rtmi::kSeg;
       r.cbase[i] = c_elems;

@@ -66,7 +66,6 @@ struct RecordArgs {
   float wray[kMaxSrcPerLaunch];
   int nrays[kMaxSrcPerLaunch];
   int nsub[kMaxSrcPerLaunch];
-  int vstride[kMaxSrcPerLaunch];
   long long vbase[kMaxSrcPerLaunch];
   const float4* dirs[kMaxSrcPerLaunch];
   // Segments: with seg_len > 0 each ray's substeps are cut into runs of seg_len (a
@@ -108,7 +107,6 @@ struct TileArgs {
   float sx[kMaxSrcPerLaunch], sy[kMaxSrcPerLaunch], sz[kMaxSrcPerLaunch];
   int nrays[kMaxSrcPerLaunch];
   int nsub[kMaxSrcPerLaunch];
-  int vstride[kMaxSrcPerLaunch];
   long long vbase[kMaxSrcPerLaunch];
   const float4* dirs[kMaxSrcPerLaunch];
   const float* pbounds[kMaxSrcPerLaunch];  // per patch: kPatchRec floats (bounds and cone)
@@ -131,7 +129,6 @@ struct AdjointArgs {
   float wray[kMaxSrcPerLaunch];
   int nrays[kMaxSrcPerLaunch];
   int nsub[kMaxSrcPerLaunch];
-  int vstride[kMaxSrcPerLaunch];
   long long vbase[kMaxSrcPerLaunch];
   int cstride[kMaxSrcPerLaunch];
   long long cbase[kMaxSrcPerLaunch];

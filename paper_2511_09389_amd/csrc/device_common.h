@@ -44,4 +44,12 @@ __device__ __forceinline__ bool axis_clamped(float x, int n) {
   return x < 0.0f || x >= static_cast<float>(n - 1);
 }
 
+// Workspace rows of one source: the value of (ray, substep k) sits at
+//   base + ((k / 8) * nrays + ray) * 8 + k % 8,
+// so the rays of a wavefront write one 8-substep chunk as one contiguous run, and a
+// chunk of one ray is 32 contiguous, 32-byte-aligned bytes.
+__device__ __forceinline__ long long row_slot(long long base, int nrays, int ray, int k) {
+  return base + (static_cast<long long>(k >> 3) * nrays + ray) * 8 + (k & 7);
+}
+
 }  // namespace rtmi

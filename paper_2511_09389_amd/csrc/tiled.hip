@@ -88,10 +88,11 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
     const float ds = a.ds;
     const int nx = a.nx, ny = a.ny, nz = a.nz, nyz = ny * nz;
     const bool shared_k = (a.k_stride == 0);
-    float* vrow = a.V + a.vbase[s] + static_cast<long long>(ray) * a.vstride[s];
+    const long long vb = a.vbase[s];
+    const int vn = a.nrays[s];
     // runs after the first keep their attenuation P_k, and their samples collapsed onto a
     // box corner are summed by the fixup, which knows the entry state
-    float* prow = seg > 0 ? a.P + a.vbase[s] + static_cast<long long>(ray) * a.vstride[s] : nullptr;
+    float* prow = seg > 0 ? a.P : nullptr;
     const bool tails_here = seg == 0;
     double det_scale = 0.0;
     if constexpr (DET) det_scale = *a.det_scale;
@@ -177,13 +178,13 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
       if (kprev >= 0) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
-          float4* dst = reinterpret_cast<float4*>(vrow + b * a.v_bin_stride + kprev);
+          float4* dst = reinterpret_cast<float4*>(a.V + b * a.v_bin_stride + row_slot(vb, vn, ray, kprev));
 #pragma unroll
           for (int q = 0; q < C / 4; ++q)
             dst[q] = make_float4(vprev[4 * q][b], vprev[4 * q + 1][b], vprev[4 * q + 2][b],
                                  vprev[4 * q + 3][b]);
           if (prow) {
-            float4* pdst = reinterpret_cast<float4*>(prow + b * a.v_bin_stride + kprev);
+            float4* pdst = reinterpret_cast<float4*>(prow + b * a.v_bin_stride + row_slot(vb, vn, ray, kprev));
 #pragma unroll
             for (int q = 0; q < C / 4; ++q)
               pdst[q] = make_float4(pprev[4 * q][b], pprev[4 * q + 1][b], pprev[4 * q + 2][b],
@@ -259,13 +260,13 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
     if (kprev >= 0) {
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        float4* dst = reinterpret_cast<float4*>(vrow + b * a.v_bin_stride + kprev);
+        float4* dst = reinterpret_cast<float4*>(a.V + b * a.v_bin_stride + row_slot(vb, vn, ray, kprev));
 #pragma unroll
         for (int q = 0; q < C / 4; ++q)
           dst[q] = make_float4(vprev[4 * q][b], vprev[4 * q + 1][b], vprev[4 * q + 2][b],
                                vprev[4 * q + 3][b]);
         if (prow) {
-          float4* pdst = reinterpret_cast<float4*>(prow + b * a.v_bin_stride + kprev);
+          float4* pdst = reinterpret_cast<float4*>(prow + b * a.v_bin_stride + row_slot(vb, vn, ray, kprev));
 #pragma unroll
           for (int q = 0; q < C / 4; ++q)
             pdst[q] = make_float4(pprev[4 * q][b], pprev[4 * q + 1][b], pprev[4 * q + 2][b],
@@ -341,7 +342,7 @@ __global__ void __launch_bounds__(kFixupThreads) fixup_kernel(const RecordArgs a
     const float4 d = a.dirs[s][ray];
     const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
     const int k_begin = seg * a.seg_len, k_end = min(a.nsub[s], k_begin + a.seg_len);
-    const long long row = a.vbase[s] + static_cast<long long>(ray) * a.vstride[s];
+    const long long vb = a.vbase[s];
     double det_scale = 0.0;
     if constexpr (DET) det_scale = *a.det_scale;
     for (int k = k_begin + lane; k < k_end; k += 64) {
@@ -353,8 +354,9 @@ __global__ void __launch_bounds__(kFixupThreads) fixup_kernel(const RecordArgs a
       const int cid = (x >= 0.0f ? 4 : 0) | (y >= 0.0f ? 2 : 0) | (z >= 0.0f ? 1 : 0);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        float* v = a.V + row + b * a.v_bin_stride + k;
-        const float p = a.P[row + b * a.v_bin_stride + k];
+        const long long slot = row_slot(vb, nrays, ray, k) + b * a.v_bin_stride;
+        float* v = a.V + slot;
+        const float p = a.P[slot];
         const float val = E0[b] * *v + I0[b] * (wray * p);
         if (collapsed) {
           if constexpr (DET)
@@ -743,8 +745,9 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
   __shared__ float4 r_dir[kThreads];
   __shared__ int w_tot[kWaves];
   __shared__ float4 b_src[kWaves];        // source position of each wave's pair
-  __shared__ long long b_row[kWaves];     // workspace offset of the pair's first ray
-  __shared__ int b_vstride[kWaves];
+  __shared__ long long b_row[kWaves];     // workspace base of the pair's source
+  __shared__ int b_nrays[kWaves];         // its ray count (the rows' chunk stride)
+  __shared__ int b_ray0[kWaves];          // the pair's first ray
   __shared__ int pair_list[kThreads];
   __shared__ int pair_count;
   __shared__ int2 claimed;
@@ -806,8 +809,9 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
           const int patch = p - S.pbegin[s];
           if (lane == 0) {
             b_src[wave] = S.pos[s];
-            b_row[wave] = a.vbase[s] + static_cast<long long>(patch) * kPatch * a.vstride[s];
-            b_vstride[wave] = a.vstride[s];
+            b_row[wave] = a.vbase[s];
+            b_nrays[wave] = a.nrays[s];
+            b_ray0[wave] = patch * kPatch;
           }
           ray_range(a, S, g, s, patch * kPatch + lane, ka, kb, d);
         }
@@ -849,12 +853,12 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
           const int kbeg = max(ka_o, kblk), kend = min(kb_o, kblk + kChunk - 1);
           const float4 dd = r_dir[o];
           const float4 src = b_src[ow];
-          const float* vrow = a.V + b_row[ow] + static_cast<long long>(o & 63) * b_vstride[ow];
+          const float* vrow = a.V + row_slot(b_row[ow], b_nrays[ow], b_ray0[ow] + (o & 63), kblk);
           // the chunk's recorded values, fetched before any of them is needed
           float vv[NB][kChunk];
 #pragma unroll
           for (int b = 0; b < NB; ++b) {
-            const float4* src4 = reinterpret_cast<const float4*>(vrow + b * a.v_bin_stride + kblk);
+            const float4* src4 = reinterpret_cast<const float4*>(vrow + b * a.v_bin_stride);
 #pragma unroll
             for (int q = 0; q < kChunk / 4; ++q) {
               const float4 f = src4[q];
