@@ -35,23 +35,25 @@ constexpr float kCosConeLimit = -0.99913515f;   // cos(3.1)
 // its lower corner.
 __global__ void cell_table_kernel(const float* __restrict__ j, const float* __restrict__ kap,
                                   float4* __restrict__ table, int nx, int ny, int nz) {
+  // four lanes per voxel, one 16-byte quarter of its line each (j corners 0-3, 4-7, then
+  // kappa corners 0-3, 4-7), so a wavefront's stores are one contiguous kilobyte
   const long long cells = static_cast<long long>(nx) * ny * nz;
   const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
-  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < cells; i += stride) {
-    const int z = static_cast<int>(i % nz), y = static_cast<int>((i / nz) % ny);
-    const int x = static_cast<int>(i / (static_cast<long long>(ny) * nz));
-    float jc[8], kc[8];
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < 4 * cells; i += stride) {
+    const long long v = i >> 2;
+    const int q = static_cast<int>(i & 3);
+    const int z = static_cast<int>(v % nz), y = static_cast<int>((v / nz) % ny);
+    const int x = static_cast<int>(v / (static_cast<long long>(ny) * nz));
+    const float* src = (q < 2) ? j : kap;
+    const int cx = q & 1;   // corners 4 (q & 1) .. 4 (q & 1) + 3 share cx
+    const long long xx = min(x + cx, nx - 1);
+    float f[4];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      const int xx = min(x + (c >> 2), nx - 1), yy = min(y + ((c >> 1) & 1), ny - 1), zz = min(z + (c & 1), nz - 1);
-      const long long v = (static_cast<long long>(xx) * ny + yy) * nz + zz;
-      jc[c] = j[v];
-      kc[c] = kap[v];
+    for (int c = 0; c < 4; ++c) {
+      const int yy = min(y + (c >> 1), ny - 1), zz = min(z + (c & 1), nz - 1);
+      f[c] = src[(xx * ny + yy) * nz + zz];
     }
-    table[4 * i] = make_float4(jc[0], jc[1], jc[2], jc[3]);
-    table[4 * i + 1] = make_float4(jc[4], jc[5], jc[6], jc[7]);
-    table[4 * i + 2] = make_float4(kc[0], kc[1], kc[2], kc[3]);
-    table[4 * i + 3] = make_float4(kc[4], kc[5], kc[6], kc[7]);
+    table[i] = make_float4(f[0], f[1], f[2], f[3]);
   }
 }
 
@@ -1039,7 +1041,7 @@ hipError_t launch_record(const RecordArgs& a, int n_bins, bool shared_j, bool de
 hipError_t launch_cell_table(const float* j, const float* kap, float4* table, int nx, int ny, int nz,
                              hipStream_t s) {
   const long long cells = static_cast<long long>(nx) * ny * nz;
-  long long blocks = (cells + kBlock * 4 - 1) / (kBlock * 4);
+  long long blocks = (4 * cells + kBlock * 4 - 1) / (kBlock * 4);
   blocks = blocks < 1 ? 1 : (blocks > 16384 ? 16384 : blocks);
   hipLaunchKernelGGL(cell_table_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, j, kap, table,
                      nx, ny, nz);
