@@ -155,11 +155,19 @@ def main():
              (("record", rtmi.KERNEL_RECORD), ("tile", rtmi.KERNEL_TILE))}
     rtmi.timing_enable(False)
 
-    # The same step as a plan (geometry set up once, outside the timing) captured in one
-    # HIP graph and replayed: what a time-stepping caller with fixed sources runs.
+    # The same step as a plan (geometry set up once, outside the timing, with the tile
+    # work-item size picked by the autotuner) captured in one HIP graph and replayed: what
+    # a time-stepping caller with fixed sources runs.
+    import tempfile
+    from paper_2511_09389_amd import autotune
+    os.environ.setdefault("RTMI_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "rtmi_bench_tune.json"))
+    best_chunks, tune_ms = autotune.tune_item_chunks(j, kap, w.source_pos, w.num_rays, w.step_size,
+                                                     w.radiation_velocity, w.time_step, n_bins=w.n_bins,
+                                                     kappa_scale=w.kappa_scale, substep_cap=w.substep_cap,
+                                                     reps=3)
     plan = rtmi.Plan(w.shape, w.source_pos, w.num_rays, w.step_size, w.radiation_velocity,
                      w.time_step, n_bins=w.n_bins, kappa_scale=w.kappa_scale,
-                     substep_cap=w.substep_cap)
+                     substep_cap=w.substep_cap, tile_item_chunks=best_chunks)
     side = torch.cuda.Stream()
     side.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(side):
@@ -178,6 +186,8 @@ def main():
     torch.cuda.synchronize()
     g1 = time.perf_counter()
     plan_graph = {"ms_per_step": 1e3 * (g1 - g0) / args.steps, "value": units * args.steps / (g1 - g0),
+                  "tile_item_chunks": best_chunks,
+                  "autotune_ms": {str(c): round(t, 4) for c, t in tune_ms.items()},
                   "note": "plan made once (tables, workspace, tile schedule), step replayed as one graph"}
     del graph
     plan.close()
