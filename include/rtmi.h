@@ -228,8 +228,9 @@ int32_t rtmi_conv3d_backward_data(const void* dz, const void* w, const float* re
                                   int32_t w_dim, float* dh, void* dz_prev, void* stream);
 
 /* backward-weight: dw[tap][co][ci] += sum_v dz[v][co] x[v + off(tap)][ci] and
- *   db[co] += sum_v dz[v][co] (fp32; the caller zeroes them). Needs w_dim in {16, 32, 48,
- *   64}, else RTMI_ERR_UNSUPPORTED. */
+ *   db[co] += sum_v dz[v][co] (fp32; the caller zeroes them). Needs w_dim a multiple of
+ *   16, else RTMI_ERR_UNSUPPORTED. Uses 256 bytes per voxel of scratch from the library's
+ *   stream-ordered pool. */
 int32_t rtmi_conv3d_backward_weight(const void* x, const void* dz, int32_t n, int32_t d,
                                     int32_t h, int32_t w_dim, float* dw, float* db,
                                     void* stream);

@@ -1295,8 +1295,8 @@ int32_t rtmi_conv3d_backward_weight(const void* x, const void* dz, int32_t n, in
                                     int32_t w_dim, float* dw, float* db, void* stream) {
   if (!x || !dz || !dw || !db) return fail(RTMI_ERR_INVALID_ARG, "null x, dz, dw or db pointer");
   if (int32_t st = check_conv_shape(n, d, h, w_dim)) return st;
-  if (w_dim % 16 != 0 || w_dim > 64)
-    return fail(RTMI_ERR_UNSUPPORTED, "backward-weight needs an x extent of 16, 32, 48 or 64 (got %d)", w_dim);
+  if (w_dim % 16 != 0)
+    return fail(RTMI_ERR_UNSUPPORTED, "backward-weight needs an x extent that is a multiple of 16 (got %d)", w_dim);
   rtmi::ConvArgs a;
   std::memset(&a, 0, sizeof a);
   a.x = x;
@@ -1307,8 +1307,13 @@ int32_t rtmi_conv3d_backward_weight(const void* x, const void* dz, int32_t n, in
   a.d = d;
   a.h = h;
   a.w_dim = w_dim;
-  const hipError_t e = rtmi::launch_wgrad(a, static_cast<hipStream_t>(stream));
+  const hipStream_t st = static_cast<hipStream_t>(stream);
+  const size_t nvox = size_t(n) * d * h * w_dim;
+  unsigned short* scratch = nullptr;   // channel-major copies: x three times, dz once
+  if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&scratch), nvox * rtmi::kConvChannels * 4 * 2, st)) return rc;
+  hipError_t e = rtmi::launch_wgrad(a, scratch, scratch + nvox * rtmi::kConvChannels * 3, st);
   if (e != hipSuccess) return hip_fail(e, "conv backward-weight launch");
+  if ((e = hipFreeAsync(scratch, st)) != hipSuccess) return hip_fail(e, "workspace release");
   g_error.clear();
   return RTMI_OK;
 }

@@ -8,9 +8,9 @@
 // transposed for the backward-data pass, where dx[u][ci] = sum W[tap][co][ci]
 // dz[u - off(tap)][co]). The A operand (8 consecutive channels of one voxel) is one
 // 16-byte load straight from global memory.
-// wgrad_kernel: dW[tap][co][ci] = sum_v dz[v][co] x[v + off(tap)][ci]; the K dimension is
-// voxels, so an x-row of dz and the nine neighbouring rows of x (three shifted copies
-// each) are staged transposed in LDS; three waves own the taps with dx = -1, 0, +1.
+// wgrad: dW[tap][co][ci] = sum_v dz[v][co] x[v + off(tap)][ci], a GEMM over the voxels on
+// channel-major copies of dz and of x (three, shifted by dx = -1, 0, +1), so that a row
+// shift is a whole number of rows and every operand an aligned 16-byte load.
 #include "common.h"
 
 namespace rtmi {
@@ -120,80 +120,92 @@ __global__ void __launch_bounds__(kConvThreads) conv_kernel(const ConvArgs a) {
   }
 }
 
-// dW (and db) of one layer; rows = (n, z, y) x-rows of length a.w_dim (a multiple of 16,
-// at most kMaxRow).
-constexpr int kMaxRow = 64;
-constexpr int kWgradThreads = 192;
+// Weight gradient, dW[tap][co][ci] = sum_v dz[v][co] x[v + off(tap)][ci]: a GEMM whose K
+// dimension is the voxels, while the matrix cores want eight consecutive K values per
+// lane. So dz and x are first copied channel-major (x three times, shifted by dx = -1, 0,
+// +1 within its row, zero past the row's ends); a row shift by (dz, dy) is then a whole
+// number of rows and every operand is one aligned 16-byte load.
+constexpr int kTrVox = 64;      // voxels per transpose block
+constexpr int kTrThreads = 256;
 
-__global__ void __launch_bounds__(kWgradThreads) wgrad_kernel(const ConvArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned short dzT[kC][kMaxRow];       // [co][x]
-  __shared__ __attribute__((aligned(16))) unsigned short xs[3][kC][kMaxRow];     // [dx+1][ci][x]
-  __shared__ float db_part[kC];
-  const int tid = static_cast<int>(threadIdx.x), lane = tid & 63, wave = tid >> 6;   // wave: dx + 1
-  const unsigned short* X = static_cast<const unsigned short*>(a.x);
-  const unsigned short* DZ = static_cast<const unsigned short*>(a.dz);
-  const int D = a.d, H = a.h, Wd = a.w_dim;
-  const long long rows = static_cast<long long>(a.n) * D * H;
-  const int kb_count = Wd / 16;
-  if (tid < kC) db_part[tid] = 0.0f;
-  f32x16 acc[9];
-#pragma unroll
-  for (int t = 0; t < 9; ++t)
-#pragma unroll
-    for (int i = 0; i < 16; ++i) acc[t][i] = 0.0f;
-  float db_acc = 0.0f;
-
-  for (long long row = blockIdx.x; row < rows; row += gridDim.x) {
-    const int y = static_cast<int>(row % H);
-    const int z = static_cast<int>((row / H) % D);
-    const long long n = row / (static_cast<long long>(H) * D);
+__global__ void __launch_bounds__(kTrThreads) wgrad_transpose_kernel(
+    const unsigned short* __restrict__ x, const unsigned short* __restrict__ dz, long long nvox,
+    int w_dim, unsigned short* __restrict__ xc, unsigned short* __restrict__ dzc, float* __restrict__ db) {
+  __shared__ unsigned short tx[kTrVox + 2][kC + 2];   // voxels v0 - 1 .. v0 + 64
+  __shared__ unsigned short tz[kTrVox][kC + 2];
+  const int tid = static_cast<int>(threadIdx.x);
+  float db_part = 0.0f;
+  for (long long v0 = static_cast<long long>(blockIdx.x) * kTrVox; v0 < nvox;
+       v0 += static_cast<long long>(gridDim.x) * kTrVox) {
     __syncthreads();
-    // dz of the row, transposed
-    for (int i = tid; i < Wd * kC; i += kWgradThreads) {
-      const int x = i / kC, c = i % kC;
-      dzT[c][x] = DZ[(row * Wd + x) * kC + c];
+    for (int i = tid; i < (kTrVox + 2) * kC; i += kTrThreads) {
+      const long long v = v0 - 1 + i / kC;
+      tx[i / kC][i % kC] = (v >= 0 && v < nvox) ? x[v * kC + i % kC] : 0;
+    }
+    for (int i = tid; i < kTrVox * kC; i += kTrThreads) {
+      const long long v = v0 + i / kC;
+      tz[i / kC][i % kC] = v < nvox ? dz[v * kC + i % kC] : 0;
     }
     __syncthreads();
-    if (tid < kC) {
-      float s = 0.0f;
-      for (int x = 0; x < Wd; ++x) s += bf16_to_f32(dzT[tid][x]);
-      db_acc += s;
-    }
+    for (int i = tid; i < kC * kTrVox; i += kTrThreads) {
+      const int c = i / kTrVox, jv = i % kTrVox;
+      const long long v = v0 + jv;
+      if (v >= nvox) continue;
+      dzc[c * nvox + v] = tz[jv][c];
+      const int xpos = static_cast<int>(v % w_dim);
 #pragma unroll
-    for (int t = 0; t < 9; ++t) {
-      const int oz = t / 3 - 1, oy = t % 3 - 1;
-      const int zz = z + oz, yy = y + oy;
-      const bool row_in = zz >= 0 && zz < D && yy >= 0 && yy < H;
-      const long long src_row = (n * D + zz) * H + yy;
-      __syncthreads();
-      // the neighbouring row at (dz, dy), in three copies shifted by dx = -1, 0, +1
-      for (int i = tid; i < 3 * Wd * kC; i += kWgradThreads) {
-        const int s = i / (Wd * kC), rem = i % (Wd * kC), x = rem / kC, c = rem % kC;
-        const int xx = x + s - 1;
-        unsigned short v = 0;
-        if (row_in && xx >= 0 && xx < Wd) v = X[(src_row * Wd + xx) * kC + c];
-        xs[s][c][x] = v;
+      for (int sh = 0; sh < 3; ++sh) {
+        const int xx = xpos + sh - 1;
+        xc[(sh * kC + c) * nvox + v] = (xx >= 0 && xx < w_dim) ? tx[jv + sh][c] : 0;
       }
-      __syncthreads();
-      const int col = lane & 31, kg = lane >> 5;
-      for (int kb = 0; kb < kb_count; ++kb) {
-        const u16x8 av = *reinterpret_cast<const u16x8*>(&dzT[col][kb * 16 + kg * 8]);
-        const u16x8 bv = *reinterpret_cast<const u16x8*>(&xs[wave][col][kb * 16 + kg * 8]);
-        acc[t] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc[t], 0, 0, 0);
+    }
+    if (tid < kC)
+      for (int jv = 0; jv < kTrVox && v0 + jv < nvox; ++jv) db_part += bf16_to_f32(tz[jv][tid]);
+  }
+  if (tid < kC && db_part != 0.0f) unsafeAtomicAdd(db + tid, db_part);
+}
+
+constexpr int kGemmThreads = 256;   // four waves; wave w owns the taps w, w + 4, ...
+constexpr int kTapsPerWave = 7;
+
+__global__ void __launch_bounds__(kGemmThreads) wgrad_gemm_kernel(
+    const unsigned short* __restrict__ xc, const unsigned short* __restrict__ dzc, long long nvox,
+    int d, int h, int w_dim, float* __restrict__ dw) {
+  const int tid = static_cast<int>(threadIdx.x), lane = tid & 63, wave = tid >> 6;
+  const int col = lane & 31, kg = lane >> 5;
+  f32x16 acc[kTapsPerWave];
+#pragma unroll
+  for (int u = 0; u < kTapsPerWave; ++u)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[u][i] = 0.0f;
+  const long long rows = nvox / w_dim;
+  for (long long r = blockIdx.x; r < rows; r += gridDim.x) {
+    const int y = static_cast<int>(r % h), z = static_cast<int>((r / h) % d);
+    for (int kb = 0; kb < w_dim / 16; ++kb) {
+      const long long v0 = r * w_dim + kb * 16 + kg * 8;
+      const u16x8 av = *reinterpret_cast<const u16x8*>(dzc + col * nvox + v0);
+#pragma unroll
+      for (int u = 0; u < kTapsPerWave; ++u) {
+        const int tap = wave + 4 * u;
+        if (tap >= 27) continue;
+        const int oz = tap / 9 - 1, oy = (tap / 3) % 3 - 1, ox = tap % 3 - 1;
+        u16x8 bv = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (z + oz >= 0 && z + oz < d && y + oy >= 0 && y + oy < h)
+          bv = *reinterpret_cast<const u16x8*>(xc + ((ox + 1) * kC + col) * nvox + v0 +
+                                              (static_cast<long long>(oz) * h + oy) * w_dim);
+        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc[u], 0, 0, 0);
       }
     }
   }
-  // this wave's taps (dz, dy, dx = wave - 1): rows co, columns ci
+  // rows co (acc_row), columns ci (this lane's col)
 #pragma unroll
-  for (int t = 0; t < 9; ++t) {
-    const int tap = t * 3 + wave;
+  for (int u = 0; u < kTapsPerWave; ++u) {
+    const int tap = wave + 4 * u;
+    if (tap >= 27) continue;
 #pragma unroll
-    for (int i = 0; i < 16; ++i) {
-      const int co = acc_row(i, lane), ci = lane & 31;
-      if (acc[t][i] != 0.0f) unsafeAtomicAdd(a.dw + (tap * kC + co) * kC + ci, acc[t][i]);
-    }
+    for (int i = 0; i < 16; ++i)
+      if (acc[u][i] != 0.0f) unsafeAtomicAdd(dw + (tap * kC + acc_row(i, lane)) * kC + col, acc[u][i]);
   }
-  if (tid < kC && db_acc != 0.0f) unsafeAtomicAdd(a.db + tid, db_acc);
 }
 
 // Loss of the surrogate (mean squared error of channel 0 against the target) and its
@@ -312,10 +324,16 @@ hipError_t launch_conv(const ConvArgs& a, bool backward, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_wgrad(const ConvArgs& a, hipStream_t s) {
-  const long long rows = static_cast<long long>(a.n) * a.d * a.h;
-  const int grid = static_cast<int>(rows < 1024 ? (rows < 1 ? 1 : rows) : 1024);
-  hipLaunchKernelGGL(wgrad_kernel, dim3(grid), dim3(kWgradThreads), 0, s, a);
+hipError_t launch_wgrad(const ConvArgs& a, unsigned short* xc, unsigned short* dzc, hipStream_t s) {
+  const long long nvox = static_cast<long long>(a.n) * a.d * a.h * a.w_dim;
+  const int tgrid = grid_for(nvox, kTrVox);
+  hipLaunchKernelGGL(wgrad_transpose_kernel, dim3(tgrid), dim3(kTrThreads), 0, s,
+                     static_cast<const unsigned short*>(a.x), static_cast<const unsigned short*>(a.dz), nvox,
+                     a.w_dim, xc, dzc, a.db);
+  const long long rows = nvox / a.w_dim;
+  const int ggrid = static_cast<int>(rows < 256 ? rows : 256);
+  hipLaunchKernelGGL(wgrad_gemm_kernel, dim3(ggrid), dim3(kGemmThreads), 0, s, xc, dzc, nvox, a.d, a.h,
+                     a.w_dim, a.dw);
   return hipGetLastError();
 }
 

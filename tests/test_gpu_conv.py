@@ -87,7 +87,7 @@ def test_backward_data_matches_oracle(rt, dev, shape):
     assert np.allclose(f64(dzp), want, rtol=2 ** -7, atol=1e-5 * bound.max())
 
 
-@pytest.mark.parametrize("shape", [(1, 4, 5, 32), (2, 3, 3, 16), (1, 2, 2, 64)])
+@pytest.mark.parametrize("shape", [(1, 4, 5, 32), (2, 3, 3, 16), (1, 2, 2, 64), (1, 2, 3, 80), (2, 8, 20, 16)])
 def test_backward_weight_matches_oracle(rt, dev, shape):
     rng = np.random.default_rng(14)
     x, _, _ = case(rng, dev, shape)
