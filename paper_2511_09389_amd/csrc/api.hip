@@ -434,27 +434,67 @@ constexpr int kItemChunks = 2 * rtmi::kTileThreads;
 // Schedule buffers of the tile launches, carved from the workspace.
 struct TileSchedule {
   unsigned long long* cost = nullptr;
+  long long *begin = nullptr, *count = nullptr, *fill = nullptr;
   int2* map = nullptr;
-  int* counters = nullptr;
+  int* counters = nullptr;   // item total, next, done; the record total at byte 16
   static size_t bytes(int tiles) {
-    return align256(size_t(tiles) * sizeof(unsigned long long)) +
-           align256(size_t(tiles) * rtmi::kMaxParts * sizeof(int2)) + 256;
+    return 4 * align256(size_t(tiles) * 8) + align256(size_t(tiles) * rtmi::kMaxParts * sizeof(int2)) + 256;
   }
   void carve(char* base, int tiles) {
+    const size_t per = align256(size_t(tiles) * 8);
     cost = reinterpret_cast<unsigned long long*>(base);
-    base += align256(size_t(tiles) * sizeof(unsigned long long));
-    map = reinterpret_cast<int2*>(base);
-    base += align256(size_t(tiles) * rtmi::kMaxParts * sizeof(int2));
-    counters = reinterpret_cast<int*>(base);
+    begin = reinterpret_cast<long long*>(base + per);
+    count = reinterpret_cast<long long*>(base + 2 * per);
+    fill = reinterpret_cast<long long*>(base + 3 * per);
+    map = reinterpret_cast<int2*>(base + 4 * per);
+    counters = reinterpret_cast<int*>(base + 4 * per + align256(size_t(tiles) * rtmi::kMaxParts * sizeof(int2)));
   }
-  void apply(rtmi::TileArgs& t, int item_chunks) const {
+  long long* rec_total() const { return reinterpret_cast<long long*>(counters + 4); }
+  void apply(rtmi::TileArgs& t, int item_chunks, uint2* recs, int64_t capacity) const {
     t.tile_cost = cost;
+    t.tile_begin = begin;
+    t.tile_count = count;
+    t.tile_fill = fill;
+    t.rec_total = rec_total();
+    t.recs = recs;
+    t.rec_capacity = capacity;
     t.item_map = map;
     t.item_total = counters;
     t.item_next = counters + 1;
     t.item_done = counters + 2;
     t.item_chunks = item_chunks > 0 ? item_chunks : kItemChunks;
   }
+};
+
+// Upper bound on the chunk records that sources [s0, s0 + ns) can produce. A tile lists a
+// chunk (kChunk substeps from 8c) when its substep range [ka, kb] meets the chunk, and
+// that range lies within two substeps (plus division rounding) of the ray's parameter
+// interval inside the tile widened by the stencil and the margin m. So the ray, over
+// t in [(8c - 2) ds, (8c + 9) ds] (widened for rounding to 13 ds), meets that tile's
+// widened box, whose extent along an axis is at most 17 + 4m with a stride of 16 between
+// tiles: at most floor((13 ds + 17 + 4m) / 16) + 1 tiles per axis, which for m <= 1/2 is
+// floor((13 ds + 19) / 16) + 1. (The fill kernel also never writes past the buffer.)
+int64_t record_bound(const Problem& p, const Plan& plan, int32_t s0, int32_t ns, int tiles_x, int tiles_y,
+                     int tiles_z) {
+  int64_t total = 0;
+  for (int32_t s = s0; s < s0 + ns; ++s) {
+    if (plan.nsub[s] <= 0) continue;
+    const double tmax = double(plan.nsub[s] - 1) * p.ds;
+    const double amax = std::max(std::fabs(double(p.src[3 * s])),
+                                 std::max(std::fabs(double(p.src[3 * s + 1])), std::fabs(double(p.src[3 * s + 2]))));
+    const double m = 5.0e-7 * (amax + tmax + 2.0) + 1.0e-6;
+    const int64_t per_axis = m <= 0.5 ? int64_t(std::floor((13.0 * p.ds + 19.0) / 16.0)) + 1 : int64_t(1) << 30;
+    const int64_t f = std::min<int64_t>(per_axis, tiles_x) * std::min<int64_t>(per_axis, tiles_y) *
+                      std::min<int64_t>(per_axis, tiles_z);
+    total += int64_t(p.nrays[s]) * ((plan.nsub[s] + rtmi::kChunk - 1) / rtmi::kChunk) * f;
+  }
+  return total;
+}
+
+// A plan's chunk records: one slice per launch, sized exactly at plan creation.
+struct RecordSlices {
+  uint2* base = nullptr;
+  std::vector<int64_t> off, count;
 };
 
 int64_t row_stride(int32_t nsub) { return (int64_t(nsub) + kRowAlign - 1) / kRowAlign * kRowAlign; }
@@ -468,8 +508,9 @@ struct TiledLayout {
   int tiles_x = 0, tiles_y = 0, tiles_z = 0, tiles = 0;
   int n_launch = 0;
   bool interleaved = false;
-  size_t corner = 0, sched = 0, med = 0, v = 0, p = 0, segtot = 0, total = 0;   // byte offsets / size
+  size_t corner = 0, sched = 0, med = 0, v = 0, p = 0, segtot = 0, recs = 0, total = 0;   // byte offsets / size
   size_t sched_bytes = 0;
+  int64_t rec_capacity = 0;   // chunk records of the shared buffer (0: a plan's own slices)
   std::vector<int> seg_len;   // per source chunk: substeps per record run (0: whole rays)
 };
 
@@ -496,7 +537,7 @@ int record_run_length(int64_t rays, int32_t max_nsub) {
 
 constexpr size_t kCornerBytes = 256;   // [4][8] floats, then (next 256 B) [4][8] u64
 
-TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_launch) {
+TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_launch, bool shared_records) {
   TiledLayout L;
   L.tiles_x = (p.nx + kTile - 1) / kTile;
   L.tiles_y = (p.ny + kTile - 1) / kTile;
@@ -515,6 +556,9 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
       }
     const int len = record_run_length(rays, max_nsub);
     L.seg_len.push_back(len);
+    if (shared_records)
+      L.rec_capacity = std::max(L.rec_capacity, record_bound(p, plan, s0, std::min(kMaxSrcPerLaunch, p.n_src - s0),
+                                                             L.tiles_x, L.tiles_y, L.tiles_z));
     int64_t t = 0;
     if (len > 0)
       for (int32_t s = s0; s < std::min(p.n_src, s0 + kMaxSrcPerLaunch); ++s)
@@ -534,14 +578,16 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
   L.v = L.med + (L.interleaved ? align256(size_t(plan.cells) * 4 * sizeof(float4)) : 0);
   L.p = L.v + align256(size_t(v_elems_max) * nb_max * sizeof(float));
   L.segtot = L.p + align256(size_t(p_elems_max) * nb_max * sizeof(float));
-  L.total = L.segtot + size_t(t_elems_max) * nb_max * sizeof(float2);
+  L.recs = L.segtot + align256(size_t(t_elems_max) * nb_max * sizeof(float2));
+  L.total = L.recs + size_t(L.rec_capacity) * sizeof(uint2);
   return L;
 }
 
-// What the tiled path enqueues: kFull (schedules computed in line, the stateless calls),
-// kSchedule (only the schedules, each into its own buffer: plan creation) and kReplay
-// (everything but the schedules, which a plan keeps).
-enum class TiledMode { kFull, kSchedule, kReplay };
+// What the tiled path enqueues: kFull (schedules and records computed in line, the
+// stateless calls), kSchedule and kFill (only the schedules, each into its own buffer,
+// then only the records: plan creation, which sizes the records in between) and kReplay
+// (everything but the schedules and records, which a plan keeps).
+enum class TiledMode { kFull, kSchedule, kFill, kReplay };
 
 // One (bin chunk, source chunk) launch of the tiled path.
 struct LaunchArgs {
@@ -588,9 +634,12 @@ struct SideStream {
 
 int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
                   const double* det_scale, TiledMode mode = TiledMode::kFull,
-                  char* given_ws = nullptr) {
+                  char* given_ws = nullptr, const RecordSlices* slices = nullptr) {
   const hipStream_t st = p.stream;
-  const TiledLayout L = tiled_layout(p, plan, true);
+  // a stateless call keeps its records in the workspace; a plan, in slices of its own
+  const TiledLayout L = tiled_layout(p, plan, true, mode == TiledMode::kFull);
+  if ((mode == TiledMode::kFill || mode == TiledMode::kReplay) && !slices)
+    return fail(RTMI_ERR_INVALID_ARG, "a plan's chunk records are missing");
   char* ws = given_ws;
   if (!ws) {
     if (mode != TiledMode::kFull) return fail(RTMI_ERR_INVALID_ARG, "a plan's workspace is missing");
@@ -674,22 +723,31 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       t.tiles_z = L.tiles_z;
       TileSchedule sched;
       sched.carve(ws + L.sched + launch * L.sched_bytes, L.tiles);
-      sched.apply(t, plan.item_chunks);
+      if (slices && launch < static_cast<int>(slices->off.size()))
+        sched.apply(t, plan.item_chunks, slices->base + slices->off[launch], slices->count[launch]);
+      else
+        sched.apply(t, plan.item_chunks, reinterpret_cast<uint2*>(ws + L.recs), L.rec_capacity);
       launches.push_back({r, t, nb, blocks, fix_waves});
     }
   }
 
-  // The schedules depend on the geometry only. A stateless call computes them on a side
-  // stream, overlapped with the gather table and the first record pass; the first tile
-  // pass waits for them.
+  // The schedules and records depend on the geometry only. A stateless call computes them
+  // on a side stream, overlapped with the gather table and the first record pass; the
+  // first tile pass waits for them. Launches that share one record buffer fill it each
+  // just before their tile pass instead.
   hipStream_t sched_st = st;
   SideStream side;
   if (mode == TiledMode::kFull && side.open(st) == hipSuccess) sched_st = side.stream;
-  if (mode != TiledMode::kReplay)
+  if (mode == TiledMode::kFull || mode == TiledMode::kSchedule)
     for (const LaunchArgs& l : launches)
       if ((e = rtmi::launch_tile_schedule(l.t, L.tiles, sched_st)) != hipSuccess)
         return hip_fail(e, "tile schedule");
-  if (mode == TiledMode::kSchedule) return RTMI_OK;
+  const bool fill_each = mode == TiledMode::kFull && launches.size() > 1;
+  if (mode == TiledMode::kFill || (mode == TiledMode::kFull && !fill_each))
+    for (const LaunchArgs& l : launches)
+      if ((e = rtmi::launch_tile_fill(l.t, L.tiles, sched_st)) != hipSuccess)
+        return hip_fail(e, "tile records");
+  if (mode == TiledMode::kSchedule || mode == TiledMode::kFill) return RTMI_OK;
   if (sched_st != st && (e = side.join(st)) != hipSuccess) return hip_fail(e, "side stream");
 
   if (L.interleaved && (e = rtmi::launch_cell_table(p.j, p.kap, med, p.nx, p.ny, p.nz, st)) != hipSuccess)
@@ -717,6 +775,8 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       if ((e = hipStreamWaitEvent(st, side.done, 0)) != hipSuccess) return hip_fail(e, "side stream");
       joined = true;
     }
+    if (fill_each && (e = rtmi::launch_tile_fill(l.t, L.tiles, st)) != hipSuccess)
+      return hip_fail(e, "tile records");
     TimedLaunch tl;
     if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl)) != hipSuccess) return hip_fail(e, "timing");
     if ((e = rtmi::launch_tile_run(l.t, l.nb, plan.det, false, st)) != hipSuccess)
@@ -865,12 +925,17 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
             tiles_z = (p.nz + kTile - 1) / kTile;
   const int tiles = tiles_x * tiles_y * tiles_z;
   const size_t sched_bytes = TileSchedule::bytes(tiles);
+  int64_t rec_capacity = 0;
+  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch)
+    rec_capacity = std::max(rec_capacity, record_bound(p, plan, s0, std::min(kMaxSrcPerLaunch, p.n_src - s0),
+                                                       tiles_x, tiles_y, tiles_z));
+  const size_t rec_off = corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes) + sched_bytes;
   char* ws = nullptr;
-  if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&ws),
-                              corner_bytes + med_bytes + 2 * v_bytes + c_bytes + sched_bytes, st))
+  if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&ws), rec_off + size_t(rec_capacity) * sizeof(uint2), st))
     return rc;
   TileSchedule sched;
-  sched.carve(ws + corner_bytes + med_bytes + 2 * v_bytes + c_bytes, tiles);
+  sched.carve(ws + corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes), tiles);
+  uint2* recs = reinterpret_cast<uint2*>(ws + rec_off);
   float* corner = reinterpret_cast<float*>(ws);  // [0..7] for dL/dj, [8..15] for dL/dkappa
   float4* med = reinterpret_cast<float4*>(ws + corner_bytes);
   float* Vj = reinterpret_cast<float*>(ws + corner_bytes + med_bytes);
@@ -931,15 +996,16 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
     t.tiles_x = tiles_x;
     t.tiles_y = tiles_y;
     t.tiles_z = tiles_z;
-    sched.apply(t, 0);
+    sched.apply(t, 0, recs, rec_capacity);
     if ((e = rtmi::launch_fill_zero(corner, 64, st)) != hipSuccess) return hip_fail(e, "fill");
     if (blocks > 0 && (e = rtmi::launch_adjoint_record(r, blocks, st)) != hipSuccess)
       return hip_fail(e, "adjoint launch");
     t.V = Vj;
     t.corner = corner;
     t.out = grad_j;
-    // one schedule serves both deposits (same rays, same tiles)
+    // one schedule and one set of records serve both deposits (same rays, same tiles)
     if ((e = rtmi::launch_tile_schedule(t, tiles, st)) != hipSuccess ||
+        (e = rtmi::launch_tile_fill(t, tiles, st)) != hipSuccess ||
         (e = rtmi::launch_tile_run(t, 1, false, false, st)) != hipSuccess)
       return hip_fail(e, "tile launch");
     t.V = Vk;
@@ -967,6 +1033,7 @@ struct rtmi_plan {
   Plan plan;
   char* ws = nullptr;          // hipMalloc'd
   size_t ws_bytes = 0;
+  RecordSlices recs;          // chunk records of every launch; recs.base hipMalloc'd
   char* table = nullptr;       // explicit direction table, hipMalloc'd
   unsigned long long* out_q = nullptr;
   double* det_scale = nullptr;
@@ -980,6 +1047,7 @@ void plan_release(rtmi_plan* P) {
   const bool switch_dev = hipGetDevice(&cur) == hipSuccess && cur != P->device;
   if (switch_dev) (void)hipSetDevice(P->device);
   if (P->ws) (void)hipFree(P->ws);
+  if (P->recs.base) (void)hipFree(P->recs.base);
   if (P->table) (void)hipFree(P->table);
   if (switch_dev) (void)hipSetDevice(cur);
   delete P;
@@ -1041,8 +1109,9 @@ int32_t plan_create(const Problem& given, rtmi_plan** out) {
       if (int32_t rc = get_dirs(p.nrays[s], st, &P->plan.tables[s])) return rc;
   }
 
-  // workspace: the tiled layout with one schedule per launch, then the fixed-point field
-  const TiledLayout L = tiled_layout(p, P->plan, true);
+  // workspace: the tiled layout with one schedule per launch, then the fixed-point field;
+  // the chunk records get their own allocation once the schedules have counted them
+  const TiledLayout L = tiled_layout(p, P->plan, true, false);
   const int64_t total = P->plan.cells * p.n_bins;
   const size_t det_off = align256(L.total);
   P->ws_bytes = P->plan.det ? det_off + size_t(total) * 8 + 16 : L.total;
@@ -1054,6 +1123,23 @@ int32_t plan_create(const Problem& given, rtmi_plan** out) {
   }
   if (int32_t rc = run_tiled(p, P->plan, P->out_q, P->det_scale, TiledMode::kSchedule, P->ws)) return rc;
   if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "plan schedule");
+  int64_t rec_sum = 0;
+  for (int i = 0; i < L.n_launch; ++i) {
+    TileSchedule sched;
+    sched.carve(P->ws + L.sched + size_t(i) * L.sched_bytes, L.tiles);
+    long long n = 0;
+    if ((e = hipMemcpy(&n, sched.rec_total(), sizeof n, hipMemcpyDeviceToHost)) != hipSuccess)
+      return hip_fail(e, "plan record count");
+    P->recs.off.push_back(rec_sum);
+    P->recs.count.push_back(n);
+    rec_sum += n;
+  }
+  if ((e = hipMalloc(reinterpret_cast<void**>(&P->recs.base), std::max<size_t>(size_t(rec_sum) * sizeof(uint2), 256))) !=
+      hipSuccess)
+    return hip_fail(e, "hipMalloc(plan records)");
+  P->ws_bytes += size_t(rec_sum) * sizeof(uint2);
+  if (int32_t rc = run_tiled(p, P->plan, P->out_q, P->det_scale, TiledMode::kFill, P->ws, &P->recs)) return rc;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return hip_fail(e, "plan records");
   p.stream = nullptr;
   P->p = p;
   *out = P.release();
@@ -1079,7 +1165,7 @@ int32_t plan_execute(const rtmi_plan* P, const float* j, const float* kap, float
     if ((e = rtmi::launch_det_scale(p.j, j_count, P->plan.bound_per_unit_j, P->det_scale, st)) != hipSuccess)
       return hip_fail(e, "det_scale");
   }
-  if (int32_t rc = run_tiled(p, P->plan, P->out_q, P->det_scale, TiledMode::kReplay, P->ws)) return rc;
+  if (int32_t rc = run_tiled(p, P->plan, P->out_q, P->det_scale, TiledMode::kReplay, P->ws, &P->recs)) return rc;
   if (P->plan.det && (e = rtmi::launch_det_convert(P->out_q, P->det_scale, p.out, total, st)) != hipSuccess)
     return hip_fail(e, "det_convert");
   g_error.clear();

@@ -95,14 +95,20 @@ struct TileArgs {
   int tiles_x, tiles_y, tiles_z;
   float ds;
   int n_src;
-  // Schedule, written by the cost and schedule kernels and read by the tile kernel (the
-  // field must be zeroed before the tile kernel adds into it).
-  unsigned long long* tile_cost;  // [tiles] chunks (plus a per-pair charge) per tile
+  // Schedule, written by the cost, schedule and fill kernels and read by the tile kernel
+  // (the field must be zeroed before the tile kernel adds into it).
+  unsigned long long* tile_cost;  // [tiles] chunks per tile
+  long long* tile_begin;          // [tiles] first chunk record of the tile
+  long long* tile_count;          // [tiles] its records (clipped to rec_capacity)
+  long long* tile_fill;           // [tiles] fill cursor: records below it are written
+  long long* rec_total;           // chunk records of all tiles (before clipping)
+  uint2* recs;                    // chunk records, grouped by tile
+  long long rec_capacity;
   int2* item_map;                 // [tiles * kMaxParts] work item -> (tile, part | parts << 16)
   int* item_total;                // number of work items
   int* item_next;                 // next unclaimed work item
   int* item_done;                 // work-groups finished (the last one rewinds the counters)
-  int item_chunks;                // target chunks per work item
+  int item_chunks;                // target chunk records per work item
   int pbegin[kMaxSrcPerLaunch + 1];  // prefix sums of patch counts over sources
   float sx[kMaxSrcPerLaunch], sy[kMaxSrcPerLaunch], sz[kMaxSrcPerLaunch];
   int nrays[kMaxSrcPerLaunch];
@@ -198,7 +204,10 @@ hipError_t launch_adam(float* w, float* m, float* v, const float* g, unsigned sh
 
 // Tile launches: the schedule (per-tile cost, work items; depends on the geometry only)
 // and the persistent tile kernel, which leaves the schedule ready for another run.
+// Per tile: chunk counts, the work items and the record offsets (cost + schedule kernels).
 hipError_t launch_tile_schedule(const TileArgs& a, int tiles, hipStream_t s);
+// Writes the chunk records of every tile (after launch_tile_schedule on the same buffers).
+hipError_t launch_tile_fill(const TileArgs& a, int tiles, hipStream_t s);
 hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool deterministic, bool nearest,
                            hipStream_t s);
 hipError_t launch_adjoint_record(const AdjointArgs& a, int n_blocks, hipStream_t s);

@@ -6,13 +6,14 @@
 // for once. Samples whose stencil has collapsed onto a single corner voxel of the box
 // (outside along all three axes) are summed per lane and reduced per corner instead.
 //
-// Phase 2, tile_kernel: one work-group owns a 16^3 tile of the output. For every
-// (source, 64-ray patch) whose swept bounding box reaches the tile, each lane finds the
-// substep range of its ray that can touch the tile (the tile widened by the stencil and,
-// on the box faces, extended to infinity to catch clamped samples), recomputes the same
-// binary32 sample points and adds v_k times the trilinear weights of the corners inside
-// the tile to a binary64 LDS accumulator. The tile is then stored with plain coalesced
-// writes.
+// Phase 2, tile_kernel: one work-group owns a 16^3 tile of the output. Beforehand, and
+// from the geometry alone, every (source, 64-ray patch) whose swept bounding box reaches
+// the tile has each lane find the substep range of its ray that can touch the tile (the
+// tile widened by the stencil and, on the box faces, extended to infinity to catch
+// clamped samples); that range becomes chunk records of up to 8 substeps, grouped by
+// tile. The tile's lanes then stream through its records, recompute the same binary32
+// sample points and add v_k times the trilinear weights of the corners inside the tile
+// to a binary64 LDS accumulator. The tile is then stored with plain coalesced writes.
 // No global float atomics are used for the field.
 #include <type_traits>
 
@@ -452,14 +453,17 @@ __device__ __forceinline__ int tile_slot(int lx, int ly, int lz) {
 
 // ---- output tiles ----
 //
-// A tile launch runs three kernels. tile_cost_kernel: per tile, the (source, patch) pairs
-// that can reach it and the chunks their rays bring (a chunk is the part of one ray's
-// substep range inside one aligned block of kChunk substeps). tile_schedule_kernel: each
-// tile becomes ceil(chunks / target) work items (at least one, at most kMaxParts); item
-// q of a tile with P items takes the tile's pairs with index = q mod P. tile_kernel: a
-// persistent grid whose work-groups claim items until none are left, so tiles next to
-// sources, several times the mean load, are shared by several compute units while light
-// tiles cost one item each.
+// A tile launch runs four kernels. tile_pairs_kernel<false>: per tile, the (source,
+// patch) pairs that can reach it and the chunks their rays bring (a chunk is the part of
+// one ray's substep range inside one aligned block of kChunk substeps).
+// tile_schedule_kernel: each tile's first record (a prefix sum of the counts) and
+// ceil(chunks / target) work items (at most kMaxParts; none for an empty tile without a
+// box corner); item q of a tile with P items takes the q-th of P equal shares of its
+// records. tile_pairs_kernel<true>: the same pass again, writing one 8-byte record per
+// chunk. tile_kernel: a persistent grid whose work-groups claim items until none are
+// left, so tiles next to sources, several times the mean load, are shared by several
+// compute units while light tiles cost one item each. The first three depend on the
+// geometry only, so a plan runs them once.
 
 // One 16^3 output tile and the positions whose clamped stencil can reach it:
 // [x0 - 1, x0 + ex) per axis, unbounded on the box faces.
@@ -505,6 +509,7 @@ struct SrcTable {
   int nrays[kMaxSrcPerLaunch];
   const float* pbounds[kMaxSrcPerLaunch];
   const float4* dirs[kMaxSrcPerLaunch];
+  long long vbase[kMaxSrcPerLaunch];   // workspace row base of the source's rays
 };
 
 __device__ __forceinline__ void load_sources(const TileArgs& a, SrcTable& S, int tid) {
@@ -517,6 +522,7 @@ __device__ __forceinline__ void load_sources(const TileArgs& a, SrcTable& S, int
     S.nrays[tid] = a.nrays[tid];
     S.pbounds[tid] = a.pbounds[tid];
     S.dirs[tid] = a.dirs[tid];
+    S.vbase[tid] = a.vbase[tid];
   }
   if (tid <= a.n_src) S.pbegin[tid] = a.pbegin[tid];
 }
@@ -612,16 +618,29 @@ __device__ __forceinline__ int range_chunks(int ka, int kb) {
   return kb >= ka ? kb / kChunk - ka / kChunk + 1 : 0;
 }
 
-// Per tile: chunks of all rays that can reach it, plus kPairCost per reaching pair for
-// the pair's own set-up. One wave per pair when counting.
+// Per (tile, block of kCostPairs pairs): the pairs that can reach the tile, then, one
+// wave per pair, the substep range of each of its rays. FILL = false: the chunks are
+// summed into tile_cost[t] (zeroed beforehand). FILL = true: each pair reserves its
+// chunks at the tile's fill cursor and writes one record per chunk,
+//   x = source << kRecRayBits | ray,
+//   y = chunk << 6 | (first substep - chunk start) << 3 | (last substep - chunk start),
+// never past the tile's count or the record buffer. Both passes run the same code on
+// the same inputs, so they agree on every count; the tile kernel also trusts only records
+// below the cursor. Blocks hold few pairs because next to a source every pair of a block
+// reaches the tile and each needs its rays' ranges.
 constexpr int kCostThreads = 256;
 constexpr int kCostPairs = 64;
-constexpr int kPairCost = 16;
+constexpr int kRecRayBits = 24;   // rays per source < 2^24
 
-__global__ void __launch_bounds__(kCostThreads) tile_cost_kernel(const TileArgs a) {
-  // block (t, q): tile t, pairs [q kCostPairs, (q + 1) kCostPairs); the tile's total is
-  // summed into tile_cost[t], zeroed beforehand. Blocks hold few pairs because next to a
-  // source every pair of a block reaches the tile and each needs its rays' ranges.
+__device__ __forceinline__ long long shfl_ll(long long v, int src) {
+  const int lo = __shfl(static_cast<int>(static_cast<unsigned long long>(v) & 0xffffffffull), src, 64);
+  const int hi = __shfl(static_cast<int>(static_cast<unsigned long long>(v) >> 32), src, 64);
+  return static_cast<long long>((static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                static_cast<unsigned>(lo));
+}
+
+template <bool FILL>
+__global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs a) {
   __shared__ SrcTable S;
   __shared__ int list[kCostPairs];
   __shared__ int count;
@@ -636,6 +655,11 @@ __global__ void __launch_bounds__(kCostThreads) tile_cost_kernel(const TileArgs 
   const TileGeom g = tile_geom(a, t);
   const int npairs = a.pbegin[a.n_src];
   const int nblocks = (npairs + kCostPairs - 1) / kCostPairs;
+  long long rec_end = 0;   // records of this tile end here (FILL)
+  if constexpr (FILL) {
+    rec_end = a.tile_begin[t] + a.tile_count[t];
+    rec_end = rec_end < a.rec_capacity ? rec_end : a.rec_capacity;
+  }
   unsigned long long sum = 0;
   // (blocks beyond the grid's y extent, 65535, are taken in turn)
   for (int q0 = static_cast<int>(blockIdx.y); q0 < nblocks; q0 += static_cast<int>(gridDim.y)) {
@@ -648,79 +672,151 @@ __global__ void __launch_bounds__(kCostThreads) tile_cost_kernel(const TileArgs 
       if (pair_reaches(a, S, g, s, p - S.pbegin[s])) list[atomicAdd(&count, 1)] = p;
     }
     __syncthreads();
-    // A tile next to a source keeps every pair of the block: each wave then counts many
+    // A tile next to a source keeps every pair of the block: each wave then takes many
     // pairs, four at a time so that their direction loads overlap.
     constexpr int kWavesC = kCostThreads / 64, kUnroll = 4;
     for (int i0 = wave; i0 < count; i0 += kWavesC * kUnroll) {
-      int c[kUnroll];
+      int ka[kUnroll], kb[kUnroll], src[kUnroll], ray[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int i = i0 + u * kWavesC;
-        c[u] = 0;
+        ka[u] = 0;
+        kb[u] = -1;
+        src[u] = 0;
+        ray[u] = 0;
         if (i < count) {
           const int q = list[i];
-          const int s = pair_source(S, a.n_src, q);
-          int ka, kb;
+          src[u] = pair_source(S, a.n_src, q);
+          ray[u] = (q - S.pbegin[src[u]]) * kPatch + lane;
           float4 d;
-          ray_range(a, S, g, s, (q - S.pbegin[s]) * kPatch + lane, ka, kb, d);
-          c[u] = range_chunks(ka, kb);
+          ray_range(a, S, g, src[u], ray[u], ka[u], kb[u], d);
         }
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
-        int cu = c[u];
+        const int c = range_chunks(ka[u], kb[u]);
+        if constexpr (!FILL) {
+          int cu = c;
 #pragma unroll
-        for (int off = 32; off > 0; off >>= 1) cu += __shfl_xor(cu, off, 64);
-        sum += cu > 0 ? static_cast<unsigned long long>(cu + kPairCost) : 0ull;
+          for (int off = 32; off > 0; off >>= 1) cu += __shfl_xor(cu, off, 64);
+          sum += static_cast<unsigned long long>(cu);
+        } else {
+          int incl = c;
+#pragma unroll
+          for (int off = 1; off < 64; off <<= 1) {
+            const int o = __shfl_up(incl, off, 64);
+            if (lane >= off) incl += o;
+          }
+          const int wtot = __shfl(incl, 63, 64);
+          if (wtot == 0) continue;   // (uniform across the wave)
+          long long base = 0;
+          if (lane == 63)
+            base = static_cast<long long>(atomicAdd(reinterpret_cast<unsigned long long*>(a.tile_fill + t),
+                                                    static_cast<unsigned long long>(wtot)));
+          base = shfl_ll(base, 63);
+          long long idx = base + incl - c;
+          const unsigned rx = (static_cast<unsigned>(src[u]) << kRecRayBits) | static_cast<unsigned>(ray[u]);
+          for (int q = 0; q < c && idx < rec_end; ++q, ++idx) {
+            const int cb = ka[u] / kChunk + q, kblk = cb * kChunk;
+            const int ob = max(ka[u], kblk) - kblk, oe = min(kb[u], kblk + kChunk - 1) - kblk;
+            a.recs[idx] = make_uint2(rx, (static_cast<unsigned>(cb) << 6) | static_cast<unsigned>(ob << 3) |
+                                             static_cast<unsigned>(oe));
+          }
+        }
       }
     }
   }
-  if (lane == 0 && sum) atomicAdd(&total, sum);
-  __syncthreads();
-  if (tid == 0 && total) atomicAdd(a.tile_cost + t, total);
+  if constexpr (!FILL) {
+    if (lane == 0 && sum) atomicAdd(&total, sum);
+    __syncthreads();
+    if (tid == 0 && total) atomicAdd(a.tile_cost + t, total);
+  }
 }
 
-// One work-group: items per tile, their prefix sums and the item -> (tile, part) map;
-// also resets the claim counter of the tile kernel.
+__device__ __forceinline__ long long shfl_up_ll(long long v, int off) {
+  const int lo = __shfl_up(static_cast<int>(static_cast<unsigned long long>(v) & 0xffffffffull), off, 64);
+  const int hi = __shfl_up(static_cast<int>(static_cast<unsigned long long>(v) >> 32), off, 64);
+  return static_cast<long long>((static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                static_cast<unsigned>(lo));
+}
+
+// One work-group: per tile, its first record (prefix sums of the counts), its work items
+// and the item -> (tile, part) map; also resets the fill cursors and the claim counter of
+// the tile kernel. A tile without records keeps one item only if it holds a corner voxel
+// of the box (the record phase's corner sums are added there).
 constexpr int kScheduleThreads = 1024;
 
 __global__ void __launch_bounds__(kScheduleThreads) tile_schedule_kernel(const TileArgs a, int n_tiles) {
   __shared__ int w_sum[kScheduleThreads / 64];
+  __shared__ long long w_rec[kScheduleThreads / 64];
   __shared__ int carry;
+  __shared__ long long rec_carry;
   const int tid = static_cast<int>(threadIdx.x), wave = tid >> 6, lane = tid & 63;
-  if (tid == 0) carry = 0;
+  if (tid == 0) {
+    carry = 0;
+    rec_carry = 0;
+  }
   __syncthreads();
   for (int t0 = 0; t0 < n_tiles; t0 += kScheduleThreads) {
     const int t = t0 + tid;
     int items = 0;
+    long long recs = 0;
     if (t < n_tiles) {
-      const unsigned long long c = a.tile_cost[t];
-      const unsigned long long want = (c + a.item_chunks - 1) / a.item_chunks;
-      items = static_cast<int>(want < 1 ? 1 : (want > kMaxParts ? kMaxParts : want));
+      recs = static_cast<long long>(a.tile_cost[t]);
+      if (recs > 0) {
+        const long long want = (recs + a.item_chunks - 1) / a.item_chunks;
+        items = static_cast<int>(want > kMaxParts ? kMaxParts : want);
+      } else {
+        const int tz = t % a.tiles_z, ty = (t / a.tiles_z) % a.tiles_y, tx = t / (a.tiles_z * a.tiles_y);
+        const bool corner = (tx == 0 || tx == a.tiles_x - 1) && (ty == 0 || ty == a.tiles_y - 1) &&
+                            (tz == 0 || tz == a.tiles_z - 1);
+        items = corner ? 1 : 0;
+      }
     }
     int incl = items;
+    long long rincl = recs;
 #pragma unroll
     for (int off = 1; off < 64; off <<= 1) {
       const int o = __shfl_up(incl, off, 64);
-      if (lane >= off) incl += o;
+      const long long ro = shfl_up_ll(rincl, off);
+      if (lane >= off) {
+        incl += o;
+        rincl += ro;
+      }
     }
-    if (lane == 63) w_sum[wave] = incl;
+    if (lane == 63) {
+      w_sum[wave] = incl;
+      w_rec[wave] = rincl;
+    }
     __syncthreads();
     int base = carry;
-    for (int w = 0; w < wave; ++w) base += w_sum[w];
+    long long rbase = rec_carry;
+    for (int w = 0; w < wave; ++w) {
+      base += w_sum[w];
+      rbase += w_rec[w];
+    }
     const int begin = base + incl - items;
+    if (t < n_tiles) {
+      const long long rbegin = rbase + rincl - recs;
+      a.tile_begin[t] = rbegin;
+      a.tile_count[t] = recs;
+      a.tile_fill[t] = rbegin;
+    }
     for (int q = 0; q < items; ++q) a.item_map[begin + q] = make_int2(t, q | (items << 16));
     __syncthreads();
-    if (tid == kScheduleThreads - 1) carry = begin + items;
+    if (tid == kScheduleThreads - 1) {
+      carry = begin + items;
+      rec_carry = rbase + rincl;
+    }
     __syncthreads();
   }
   if (tid == 0) {
     *a.item_total = carry;
     *a.item_next = 0;
     *a.item_done = 0;
+    *a.rec_total = rec_carry;
   }
 }
-
 
 // Lanes per tile work-group. 512 lets two work-groups share a compute unit (one bin), so
 // one can compute while the other waits at a barrier or on memory.
@@ -736,31 +832,15 @@ template <int NB, bool DET, bool NEAREST>
 __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs a) {
   using T = typename std::conditional<DET, unsigned long long, double>::type;
   constexpr int kThreads = tile_threads<NB>();
-  constexpr int kWaves = kThreads / 64;
   __shared__ T acc[NB][kTileVox];
   __shared__ SrcTable S;
-  // Records of one batch: record r holds ray (r mod 64) of the pair taken by wave r / 64,
-  // with its substep range, direction and the exclusive prefix of the chunk counts.
-  __shared__ int r_excl[kThreads + 1];
-  __shared__ int r_k0[kThreads];
-  __shared__ int r_k1[kThreads];
-  __shared__ float4 r_dir[kThreads];
-  __shared__ int w_tot[kWaves];
-  __shared__ float4 b_src[kWaves];        // source position of each wave's pair
-  __shared__ long long b_row[kWaves];     // workspace base of the pair's source
-  __shared__ int b_nrays[kWaves];         // its ray count (the rows' chunk stride)
-  __shared__ int b_ray0[kWaves];          // the pair's first ray
-  __shared__ int pair_list[kThreads];
-  __shared__ int pair_count;
   __shared__ int2 claimed;
   const int tid = static_cast<int>(threadIdx.x);
-  const int wave = tid >> 6, lane = tid & 63;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const float ds = a.ds;
   double det_scale = 0.0;
   if constexpr (DET) det_scale = *a.det_scale;
   load_sources(a, S, tid);
-  const int npairs = a.pbegin[a.n_src];
   const int n_items = *a.item_total;
 
   for (;;) {
@@ -784,137 +864,78 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
     const TileGeom g = tile_geom(a, t);
     const int x0 = g.x0, y0 = g.y0, z0 = g.z0, ex = g.ex, ey = g.ey, ez = g.ez;
 
-    // The item's pairs (index = part mod parts) that can reach the tile are listed a
-    // block at a time, then expanded kWaves at a time: each wave turns one pair's 64 rays
-    // into records, a work-group-wide prefix sum over their chunk counts follows, and
-    // every lane then takes chunks of any record, so a heavy pair is shared by the whole
-    // work-group instead of one wavefront.
-    for (int blk0 = 0; blk0 < npairs; blk0 += kThreads * parts) {
-      if (tid == 0) pair_count = 0;
-      __syncthreads();
-      {
-        const int p = blk0 + tid * parts + part;
-        if (p < npairs) {
-          const int s = pair_source(S, a.n_src, p);
-          if (pair_reaches(a, S, g, s, p - S.pbegin[s])) pair_list[atomicAdd(&pair_count, 1)] = p;
+    // The item's share of the tile's chunk records; only records below the fill cursor
+    // and inside the buffer were written.
+    const long long rbegin = a.tile_begin[t], rcount = a.tile_count[t];
+    long long rend = rbegin + rcount * (part + 1) / parts;
+    rend = min(rend, min(a.tile_fill[t], a.rec_capacity));
+    for (long long i = rbegin + rcount * part / parts + tid; i < rend; i += kThreads) {
+      const uint2 rec = a.recs[i];
+      const int s = static_cast<int>(rec.x >> kRecRayBits);
+      const int ray = static_cast<int>(rec.x & ((1u << kRecRayBits) - 1u));
+      if (s >= a.n_src || ray >= S.nrays[s]) continue;   // (not produced by the fill pass)
+      const int kblk = static_cast<int>(rec.y >> 6) * kChunk;
+      const int kbeg = kblk + static_cast<int>((rec.y >> 3) & 7u), kend = kblk + static_cast<int>(rec.y & 7u);
+      const float4 dd = S.dirs[s][ray];
+      const float4 src = S.pos[s];
+      const float* vrow = a.V + row_slot(S.vbase[s], S.nrays[s], ray, kblk);
+      // the chunk's recorded values, fetched before any of them is needed
+      float vv[NB][kChunk];
+#pragma unroll
+      for (int b = 0; b < NB; ++b) {
+        const float4* src4 = reinterpret_cast<const float4*>(vrow + b * a.v_bin_stride);
+#pragma unroll
+        for (int q = 0; q < kChunk / 4; ++q) {
+          const float4 f = src4[q];
+          vv[b][4 * q] = f.x;
+          vv[b][4 * q + 1] = f.y;
+          vv[b][4 * q + 2] = f.z;
+          vv[b][4 * q + 3] = f.w;
         }
       }
-      __syncthreads();
-      const int n_listed = pair_count;
-      for (int b0 = 0; b0 < n_listed; b0 += kWaves) {
-        const int it = b0 + wave;
-        int ka = 0, kb = -1;
-        float4 d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-        if (it < n_listed) {
-          const int p = pair_list[it];
-          const int s = pair_source(S, a.n_src, p);
-          const int patch = p - S.pbegin[s];
-          if (lane == 0) {
-            b_src[wave] = S.pos[s];
-            b_row[wave] = a.vbase[s];
-            b_nrays[wave] = a.nrays[s];
-            b_ray0[wave] = patch * kPatch;
-          }
-          ray_range(a, S, g, s, patch * kPatch + lane, ka, kb, d);
-        }
-        const int chunks = range_chunks(ka, kb);
-        // inclusive prefix sum of the chunk counts across the wavefront
-        int incl = chunks;
+      // Each sample adds its eight weighted corners straight to the tile: no per-lane
+      // state to flush, and no branch that diverges with where each ray stands.
 #pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-          const int o = __shfl_up(incl, off, 64);
-          if (lane >= off) incl += o;
-        }
-        if (lane == 63) w_tot[wave] = incl;
-        r_k0[tid] = ka;
-        r_k1[tid] = kb;
-        r_dir[tid] = d;
-        __syncthreads();
-        int off = 0, total = 0;
+      for (int u = 0; u < kChunk; ++u) {
+        const int k = kblk + u;
+        const float dist = sample_distance(k, ds);
+        const float x = sample_axis(src.x, dist, dd.x);
+        const float y = sample_axis(src.y, dist, dd.y);
+        const float z = sample_axis(src.z, dist, dd.z);
+        // outside this ray's range for the tile, or collapsed onto one corner voxel of
+        // the box (summed by the record phase)
+        // (bitwise tests: one branch per sample, not a chain of short-circuit branches)
+        const int clamped = static_cast<int>(axis_clamped(x, nx)) + static_cast<int>(axis_clamped(y, ny)) +
+                            static_cast<int>(axis_clamped(z, nz));
+        if ((k < kbeg) | (k > kend) | (clamped == 3)) continue;
+        const Axis X = axis_stencil(x, nx);
+        const Axis Y = axis_stencil(y, ny);
+        const Axis Z = axis_stencil(z, nz);
+        if constexpr (NEAREST) {
+          const int lx = X.nearest - x0, ly = Y.nearest - y0, lz = Z.nearest - z0;
+          if ((static_cast<unsigned>(lx) >= static_cast<unsigned>(ex)) |
+              (static_cast<unsigned>(ly) >= static_cast<unsigned>(ey)) |
+              (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
+            continue;
+          const int li = tile_slot(lx, ly, lz);
 #pragma unroll
-        for (int w = 0; w < kWaves; ++w) {
-          const int v = w_tot[w];
-          off += w < wave ? v : 0;
-          total += v;
-        }
-        r_excl[tid + 1] = off + incl;
-        if (tid == 0) r_excl[0] = 0;
-        __syncthreads();
-
-        for (int i = tid; i < total; i += kThreads) {
-          // owner record o: r_excl[o] <= i < r_excl[o + 1]
-          int lo = 0, hi = kThreads;
-          while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (r_excl[mid] <= i) lo = mid;
-            else hi = mid;
-          }
-          const int o = lo, ow = o >> 6;
-          const int ka_o = r_k0[o], kb_o = r_k1[o];
-          const int kblk = (ka_o / kChunk + (i - r_excl[o])) * kChunk;
-          const int kbeg = max(ka_o, kblk), kend = min(kb_o, kblk + kChunk - 1);
-          const float4 dd = r_dir[o];
-          const float4 src = b_src[ow];
-          const float* vrow = a.V + row_slot(b_row[ow], b_nrays[ow], b_ray0[ow] + (o & 63), kblk);
-          // the chunk's recorded values, fetched before any of them is needed
-          float vv[NB][kChunk];
+          for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][u], det_scale));
+        } else {
+          const TileAxis tx = tile_axis(X, x0, ex);
+          const TileAxis ty = tile_axis(Y, y0, ey);
+          const TileAxis tz = tile_axis(Z, z0, ez);
+          if (!(tx.any & ty.any & tz.any)) continue;
 #pragma unroll
-          for (int b = 0; b < NB; ++b) {
-            const float4* src4 = reinterpret_cast<const float4*>(vrow + b * a.v_bin_stride);
+          for (int c = 0; c < 8; ++c) {
+            const float w = (tx.w[c >> 2] * ty.w[(c >> 1) & 1]) * tz.w[c & 1];
+            const int li = tile_slot(tx.off[c >> 2], ty.off[(c >> 1) & 1], tz.off[c & 1]);
 #pragma unroll
-            for (int q = 0; q < kChunk / 4; ++q) {
-              const float4 f = src4[q];
-              vv[b][4 * q] = f.x;
-              vv[b][4 * q + 1] = f.y;
-              vv[b][4 * q + 2] = f.z;
-              vv[b][4 * q + 3] = f.w;
-            }
-          }
-          // Each sample adds its eight weighted corners straight to the tile: no per-lane
-          // state to flush, and no branch that diverges with where each ray stands.
-#pragma unroll
-          for (int t = 0; t < kChunk; ++t) {
-            const int k = kblk + t;
-            const float dist = sample_distance(k, ds);
-            const float x = sample_axis(src.x, dist, dd.x);
-            const float y = sample_axis(src.y, dist, dd.y);
-            const float z = sample_axis(src.z, dist, dd.z);
-            // outside this ray's range for the tile, or collapsed onto one corner voxel of
-            // the box (summed by the record phase)
-            // (bitwise tests: one branch per sample, not a chain of short-circuit branches)
-            const int clamped = static_cast<int>(axis_clamped(x, nx)) + static_cast<int>(axis_clamped(y, ny)) +
-                                static_cast<int>(axis_clamped(z, nz));
-            if ((k < kbeg) | (k > kend) | (clamped == 3)) continue;
-            const Axis X = axis_stencil(x, nx);
-            const Axis Y = axis_stencil(y, ny);
-            const Axis Z = axis_stencil(z, nz);
-            if constexpr (NEAREST) {
-              const int lx = X.nearest - x0, ly = Y.nearest - y0, lz = Z.nearest - z0;
-              if ((static_cast<unsigned>(lx) >= static_cast<unsigned>(ex)) |
-                  (static_cast<unsigned>(ly) >= static_cast<unsigned>(ey)) |
-                  (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
-                continue;
-              const int li = tile_slot(lx, ly, lz);
-#pragma unroll
-              for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][t], det_scale));
-            } else {
-              const TileAxis tx = tile_axis(X, x0, ex);
-              const TileAxis ty = tile_axis(Y, y0, ey);
-              const TileAxis tz = tile_axis(Z, z0, ez);
-              if (!(tx.any & ty.any & tz.any)) continue;
-#pragma unroll
-              for (int c = 0; c < 8; ++c) {
-                const float w = (tx.w[c >> 2] * ty.w[(c >> 1) & 1]) * tz.w[c & 1];
-                const int li = tile_slot(tx.off[c >> 2], ty.off[(c >> 1) & 1], tz.off[c & 1]);
-#pragma unroll
-                for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][t] * w, det_scale));
-              }
-            }
+            for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][u] * w, det_scale));
           }
         }
-        __syncthreads();   // the records are rewritten by the next batch
       }
     }
+    __syncthreads();
 
     // the corner voxels of the box also receive the record phase's per-corner sums
     for (int i = tid; i < kTileVox; i += kThreads) {
@@ -1007,6 +1028,11 @@ hipError_t launch_tile_nb(const TileArgs& a, bool det, bool nearest, hipStream_t
   return det ? launch_tile_variant<NB, true, false>(a, s) : launch_tile_variant<NB, false, false>(a, s);
 }
 
+dim3 pairs_grid(const TileArgs& a, int tiles) {
+  const int nblocks = (a.pbegin[a.n_src] + kCostPairs - 1) / kCostPairs;
+  return dim3(tiles, nblocks < 65535 ? nblocks : 65535);
+}
+
 }  // namespace
 
 template <int NB>
@@ -1051,13 +1077,15 @@ hipError_t launch_cell_table(const float* j, const float* kap, float4* table, in
 hipError_t launch_tile_schedule(const TileArgs& a, int tiles, hipStream_t s) {
   hipError_t e = launch_fill_zero_u64(a.tile_cost, tiles, s);
   if (e != hipSuccess) return e;
-  const int npairs = a.pbegin[a.n_src];
-  if (npairs > 0) {   // (without rays every tile keeps a zero cost: one empty item)
-    const int nblocks = (npairs + kCostPairs - 1) / kCostPairs;
-    const dim3 grid(tiles, nblocks < 65535 ? nblocks : 65535);
-    hipLaunchKernelGGL(tile_cost_kernel, grid, dim3(kCostThreads), 0, s, a);
-  }
+  if (a.pbegin[a.n_src] > 0)   // (without rays every tile keeps a zero count)
+    hipLaunchKernelGGL(tile_pairs_kernel<false>, pairs_grid(a, tiles), dim3(kCostThreads), 0, s, a);
   hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kScheduleThreads), 0, s, a, tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_fill(const TileArgs& a, int tiles, hipStream_t s) {
+  if (a.pbegin[a.n_src] > 0 && a.rec_capacity > 0)
+    hipLaunchKernelGGL(tile_pairs_kernel<true>, pairs_grid(a, tiles), dim3(kCostThreads), 0, s, a);
   return hipGetLastError();
 }
 
