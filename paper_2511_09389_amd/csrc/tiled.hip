@@ -618,18 +618,131 @@ __device__ __forceinline__ int range_chunks(int ka, int kb) {
   return kb >= ka ? kb / kChunk - ka / kChunk + 1 : 0;
 }
 
+__device__ __forceinline__ long long shfl_up_ll(long long v, int off) {
+  const int lo = __shfl_up(static_cast<int>(static_cast<unsigned long long>(v) & 0xffffffffull), off, 64);
+  const int hi = __shfl_up(static_cast<int>(static_cast<unsigned long long>(v) >> 32), off, 64);
+  return static_cast<long long>((static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
+                                static_cast<unsigned>(lo));
+}
+
+// LDS scratch of the schedule pass.
+template <int THREADS>
+struct ScheduleShared {
+  int w_items[THREADS / 64];
+  long long w_recs[THREADS / 64];
+  int carry;
+  long long rec_carry;
+};
+
+// One work-group of THREADS lanes, four consecutive tiles per lane: per tile, its first
+// record (prefix sums of the counts), its work items and the item -> (tile, part) map;
+// also resets the fill cursors and the claim counters of the tile kernel. A tile without
+// records keeps one item only if it holds a corner voxel of the box (the record phase's
+// corner sums are added there).
+template <int THREADS>
+__device__ void schedule_tiles(const TileArgs& a, int n_tiles, ScheduleShared<THREADS>& sh) {
+  constexpr int kPer = 4;
+  const int tid = static_cast<int>(threadIdx.x), wave = tid >> 6, lane = tid & 63;
+  if (tid == 0) {
+    sh.carry = 0;
+    sh.rec_carry = 0;
+  }
+  __syncthreads();
+  for (int t0 = 0; t0 < n_tiles; t0 += THREADS * kPer) {
+    int items[kPer];
+    long long recs[kPer];
+    int isum = 0;
+    long long rsum = 0;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = t0 + tid * kPer + q;
+      items[q] = 0;
+      recs[q] = 0;
+      if (t < n_tiles) {
+        recs[q] = static_cast<long long>(a.tile_cost[t]);
+        if (recs[q] > 0) {
+          const long long want = (recs[q] + a.item_chunks - 1) / a.item_chunks;
+          items[q] = static_cast<int>(want > kMaxParts ? kMaxParts : want);
+        } else {
+          const int tz = t % a.tiles_z, ty = (t / a.tiles_z) % a.tiles_y, tx = t / (a.tiles_z * a.tiles_y);
+          const bool corner = (tx == 0 || tx == a.tiles_x - 1) && (ty == 0 || ty == a.tiles_y - 1) &&
+                              (tz == 0 || tz == a.tiles_z - 1);
+          items[q] = corner ? 1 : 0;
+        }
+      }
+      isum += items[q];
+      rsum += recs[q];
+    }
+    int incl = isum;
+    long long rincl = rsum;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const int o = __shfl_up(incl, off, 64);
+      const long long ro = shfl_up_ll(rincl, off);
+      if (lane >= off) {
+        incl += o;
+        rincl += ro;
+      }
+    }
+    if (lane == 63) {
+      sh.w_items[wave] = incl;
+      sh.w_recs[wave] = rincl;
+    }
+    __syncthreads();
+    int ib = sh.carry + incl - isum;
+    long long rb = sh.rec_carry + rincl - rsum;
+    for (int w = 0; w < wave; ++w) {
+      ib += sh.w_items[w];
+      rb += sh.w_recs[w];
+    }
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int t = t0 + tid * kPer + q;
+      if (t < n_tiles) {
+        a.tile_begin[t] = rb;
+        a.tile_count[t] = recs[q];
+        a.tile_fill[t] = rb;
+      }
+      for (int i = 0; i < items[q]; ++i) a.item_map[ib + i] = make_int2(t, i | (items[q] << 16));
+      ib += items[q];
+      rb += recs[q];
+    }
+    __syncthreads();
+    if (tid == THREADS - 1) {
+      sh.carry = ib;
+      sh.rec_carry = rb;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    *a.item_total = sh.carry;
+    *a.item_next = 0;
+    *a.item_done = 0;
+    *a.rec_total = sh.rec_carry;
+  }
+}
+
+constexpr int kScheduleThreads = 256;
+
+// (a small work-group, so that it finds room beside a record pass running concurrently)
+__global__ void __launch_bounds__(kScheduleThreads) tile_schedule_kernel(const TileArgs a, int n_tiles) {
+  __shared__ ScheduleShared<kScheduleThreads> sh;
+  schedule_tiles<kScheduleThreads>(a, n_tiles, sh);
+}
+
 // Per (tile, block of kCostPairs pairs): the pairs that can reach the tile, then, one
 // wave per pair, the substep range of each of its rays. FILL = false: the chunks are
-// summed into tile_cost[t] (zeroed beforehand). FILL = true: each pair reserves its
-// chunks at the tile's fill cursor and writes one record per chunk,
+// summed into tile_cost[t] (zeroed beforehand). FILL = true: a wave reserves the chunks
+// of the four pairs it holds with one atomic add at the tile's fill cursor and writes one
+// record per chunk,
 //   x = source << kRecRayBits | ray,
 //   y = chunk << 6 | (first substep - chunk start) << 3 | (last substep - chunk start),
 // never past the tile's count or the record buffer. Both passes run the same code on
 // the same inputs, so they agree on every count; the tile kernel also trusts only records
-// below the cursor. Blocks hold few pairs because next to a source every pair of a block
-// reaches the tile and each needs its rays' ranges.
+// below the cursor. Blocks hold a modest number of pairs because next to a source every
+// pair of a block reaches the tile and each needs its rays' ranges.
 constexpr int kCostThreads = 256;
-constexpr int kCostPairs = 64;
+constexpr int kCostPairs = 128;
 constexpr int kRecRayBits = 24;   // rays per source < 2^24
 
 __device__ __forceinline__ long long shfl_ll(long long v, int src) {
@@ -692,31 +805,42 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
           ray_range(a, S, g, src[u], ray[u], ka[u], kb[u], d);
         }
       }
+      if constexpr (!FILL) {
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int c = range_chunks(ka[u], kb[u]);
-        if constexpr (!FILL) {
-          int cu = c;
+        for (int u = 0; u < kUnroll; ++u) {
+          int cu = range_chunks(ka[u], kb[u]);
 #pragma unroll
           for (int off = 32; off > 0; off >>= 1) cu += __shfl_xor(cu, off, 64);
           sum += static_cast<unsigned long long>(cu);
-        } else {
-          int incl = c;
+        }
+      } else {
+        // offsets of each lane's chunks within the wave's kUnroll pairs, then one
+        // reservation at the tile's cursor for all of them
+        int incl[kUnroll], c[kUnroll];
+        int run = 0;
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          c[u] = range_chunks(ka[u], kb[u]);
+          incl[u] = c[u];
 #pragma unroll
           for (int off = 1; off < 64; off <<= 1) {
-            const int o = __shfl_up(incl, off, 64);
-            if (lane >= off) incl += o;
+            const int o = __shfl_up(incl[u], off, 64);
+            if (lane >= off) incl[u] += o;
           }
-          const int wtot = __shfl(incl, 63, 64);
-          if (wtot == 0) continue;   // (uniform across the wave)
-          long long base = 0;
-          if (lane == 63)
-            base = static_cast<long long>(atomicAdd(reinterpret_cast<unsigned long long*>(a.tile_fill + t),
-                                                    static_cast<unsigned long long>(wtot)));
-          base = shfl_ll(base, 63);
-          long long idx = base + incl - c;
+          incl[u] += run;
+          run = __shfl(incl[u], 63, 64);
+        }
+        if (run == 0) continue;   // (uniform across the wave)
+        long long base = 0;
+        if (lane == 63)
+          base = static_cast<long long>(atomicAdd(reinterpret_cast<unsigned long long*>(a.tile_fill + t),
+                                                  static_cast<unsigned long long>(run)));
+        base = shfl_ll(base, 63);
+#pragma unroll
+        for (int u = 0; u < kUnroll; ++u) {
+          long long idx = base + incl[u] - c[u];
           const unsigned rx = (static_cast<unsigned>(src[u]) << kRecRayBits) | static_cast<unsigned>(ray[u]);
-          for (int q = 0; q < c && idx < rec_end; ++q, ++idx) {
+          for (int q = 0; q < c[u] && idx < rec_end; ++q, ++idx) {
             const int cb = ka[u] / kChunk + q, kblk = cb * kChunk;
             const int ob = max(ka[u], kblk) - kblk, oe = min(kb[u], kblk + kChunk - 1) - kblk;
             a.recs[idx] = make_uint2(rx, (static_cast<unsigned>(cb) << 6) | static_cast<unsigned>(ob << 3) |
@@ -730,91 +854,6 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
     if (lane == 0 && sum) atomicAdd(&total, sum);
     __syncthreads();
     if (tid == 0 && total) atomicAdd(a.tile_cost + t, total);
-  }
-}
-
-__device__ __forceinline__ long long shfl_up_ll(long long v, int off) {
-  const int lo = __shfl_up(static_cast<int>(static_cast<unsigned long long>(v) & 0xffffffffull), off, 64);
-  const int hi = __shfl_up(static_cast<int>(static_cast<unsigned long long>(v) >> 32), off, 64);
-  return static_cast<long long>((static_cast<unsigned long long>(static_cast<unsigned>(hi)) << 32) |
-                                static_cast<unsigned>(lo));
-}
-
-// One work-group: per tile, its first record (prefix sums of the counts), its work items
-// and the item -> (tile, part) map; also resets the fill cursors and the claim counter of
-// the tile kernel. A tile without records keeps one item only if it holds a corner voxel
-// of the box (the record phase's corner sums are added there).
-constexpr int kScheduleThreads = 1024;
-
-__global__ void __launch_bounds__(kScheduleThreads) tile_schedule_kernel(const TileArgs a, int n_tiles) {
-  __shared__ int w_sum[kScheduleThreads / 64];
-  __shared__ long long w_rec[kScheduleThreads / 64];
-  __shared__ int carry;
-  __shared__ long long rec_carry;
-  const int tid = static_cast<int>(threadIdx.x), wave = tid >> 6, lane = tid & 63;
-  if (tid == 0) {
-    carry = 0;
-    rec_carry = 0;
-  }
-  __syncthreads();
-  for (int t0 = 0; t0 < n_tiles; t0 += kScheduleThreads) {
-    const int t = t0 + tid;
-    int items = 0;
-    long long recs = 0;
-    if (t < n_tiles) {
-      recs = static_cast<long long>(a.tile_cost[t]);
-      if (recs > 0) {
-        const long long want = (recs + a.item_chunks - 1) / a.item_chunks;
-        items = static_cast<int>(want > kMaxParts ? kMaxParts : want);
-      } else {
-        const int tz = t % a.tiles_z, ty = (t / a.tiles_z) % a.tiles_y, tx = t / (a.tiles_z * a.tiles_y);
-        const bool corner = (tx == 0 || tx == a.tiles_x - 1) && (ty == 0 || ty == a.tiles_y - 1) &&
-                            (tz == 0 || tz == a.tiles_z - 1);
-        items = corner ? 1 : 0;
-      }
-    }
-    int incl = items;
-    long long rincl = recs;
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-      const int o = __shfl_up(incl, off, 64);
-      const long long ro = shfl_up_ll(rincl, off);
-      if (lane >= off) {
-        incl += o;
-        rincl += ro;
-      }
-    }
-    if (lane == 63) {
-      w_sum[wave] = incl;
-      w_rec[wave] = rincl;
-    }
-    __syncthreads();
-    int base = carry;
-    long long rbase = rec_carry;
-    for (int w = 0; w < wave; ++w) {
-      base += w_sum[w];
-      rbase += w_rec[w];
-    }
-    const int begin = base + incl - items;
-    if (t < n_tiles) {
-      const long long rbegin = rbase + rincl - recs;
-      a.tile_begin[t] = rbegin;
-      a.tile_count[t] = recs;
-      a.tile_fill[t] = rbegin;
-    }
-    for (int q = 0; q < items; ++q) a.item_map[begin + q] = make_int2(t, q | (items << 16));
-    __syncthreads();
-    if (tid == kScheduleThreads - 1) {
-      carry = begin + items;
-      rec_carry = rbase + rincl;
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
-    *a.item_total = carry;
-    *a.item_next = 0;
-    *a.item_done = 0;
-    *a.rec_total = rec_carry;
   }
 }
 
