@@ -419,37 +419,19 @@ __device__ __forceinline__ T tile_value(float v, double scale) {
     return static_cast<T>(v);
 }
 
-// One axis of a sample's stencil as seen from a tile: both corners' tile coordinates,
-// clamped into the tile, and their weights, zero for a corner outside the tile
-// (another tile owns it). An axis whose two corners coincide carries its whole weight
-// on the lower one.
-struct TileAxis {
-  int off[2];
-  float w[2];
-  bool any;   // some corner of this axis lies in the tile
-};
+// The LDS tile carries a one-voxel halo: padded coordinates p = l + 1 run over
+// [0, kTile + 1], so both corners of every sample that touches the tile have a slot and
+// a sample's eight corners sit at fixed offsets from its lower corner (immediate offsets
+// of the LDS atomics; no per-corner clamping or index arithmetic). The halo is dropped at
+// write-out: its voxels belong to the neighbouring tiles, which collect them from their
+// own records. Rows carry one slot of padding: in units of 8 bytes, x then moves the bank
+// by 6 (of 16 eight-byte bank pairs), y by 3 and z by 1, which measured faster than
+// unpadded rows.
+constexpr int kPadRow = kTile + 3;                 // stride of y
+constexpr int kPadPlane = kPadRow * (kTile + 2);   // stride of x
+constexpr int kPadVox = (kTile + 2) * kPadPlane;
 
-__device__ __forceinline__ TileAxis tile_axis(const Axis& A, int origin, int extent) {
-  TileAxis r;
-  const bool same = A.lo == A.hi;
-  const int l0 = A.lo - origin, l1 = A.hi - origin;
-  const bool in0 = static_cast<unsigned>(l0) < static_cast<unsigned>(extent);
-  const bool in1 = static_cast<unsigned>(l1) < static_cast<unsigned>(extent) && !same;
-  r.w[0] = in0 ? (same ? 1.0f : A.w0) : 0.0f;
-  r.w[1] = in1 ? A.w1 : 0.0f;
-  r.off[0] = min(max(l0, 0), extent - 1);
-  r.off[1] = min(max(l1, 0), extent - 1);
-  r.any = in0 | in1;
-  return r;
-}
-
-// Slot of tile voxel (lx, ly, lz) in the LDS accumulator. Row-major order would put
-// lx in no bank bit (a 256-element stride) and ly in one, so lanes whose samples differ
-// mainly in x would queue on one bank; XOR-ing lz with a hash of (lx, ly) spreads them
-// over the banks and stays a permutation within each z-row.
-__device__ __forceinline__ int tile_slot(int lx, int ly, int lz) {
-  return (lx * kTile + ly) * kTile + (lz ^ ((lx + 3 * ly) & (kTile - 1)));
-}
+__device__ __forceinline__ int pad_slot(int px, int py, int pz) { return px * kPadPlane + py * kPadRow + pz; }
 
 // ---- output tiles ----
 //
@@ -871,7 +853,8 @@ template <int NB, bool DET, bool NEAREST>
 __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs a) {
   using T = typename std::conditional<DET, unsigned long long, double>::type;
   constexpr int kThreads = tile_threads<NB>();
-  __shared__ T acc[NB][kTileVox];
+  static_assert(NB * kPadVox * sizeof(T) + sizeof(SrcTable) + 64 <= 160 * 1024, "LDS tile too large");
+  __shared__ T acc[NB][kPadVox];
   __shared__ SrcTable S;
   __shared__ int2 claimed;
   const int tid = static_cast<int>(threadIdx.x);
@@ -887,7 +870,7 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
       const int item = atomicAdd(a.item_next, 1);
       claimed = item < n_items ? a.item_map[item] : make_int2(-1, 0);
     }
-    for (int i = tid; i < NB * kTileVox; i += kThreads) (&acc[0][0])[i] = T(0);
+    for (int i = tid; i < NB * kPadVox; i += kThreads) (&acc[0][0])[i] = T(0);
     __syncthreads();
     const int t = claimed.x;
     if (t < 0) {
@@ -932,8 +915,30 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
           vv[b][4 * q + 3] = f.w;
         }
       }
-      // Each sample adds its eight weighted corners straight to the tile: no per-lane
-      // state to flush, and no branch that diverges with where each ray stands.
+      // A lane sums the weighted corners of consecutive samples that share a lower corner
+      // (the nearest voxel, for NEAREST) in registers: samples less than a voxel apart
+      // often do. The sums reach the tile when the ray moves on to another cell and at the
+      // end of the chunk, which takes a third or more of the LDS atomics away.
+      constexpr int kCorners = NEAREST ? 1 : 8;
+      int cell = -1;   // padded slot of the current lower corner (nearest voxel)
+      T run[NB][kCorners];
+      auto flush = [&]() {
+        if (cell < 0) return;
+#pragma unroll
+        for (int c = 0; c < kCorners; ++c)
+#pragma unroll
+          for (int b = 0; b < NB; ++b)
+            atomicAdd(&acc[b][cell + (c >> 2) * kPadPlane + ((c >> 1) & 1) * kPadRow + (c & 1)], run[b][c]);
+      };
+      auto move_to = [&](int slot) {
+        if (slot == cell) return;
+        flush();
+        cell = slot;
+#pragma unroll
+        for (int c = 0; c < kCorners; ++c)
+#pragma unroll
+          for (int b = 0; b < NB; ++b) run[b][c] = T(0);
+      };
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) {
         const int k = kblk + u;
@@ -956,23 +961,32 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
               (static_cast<unsigned>(ly) >= static_cast<unsigned>(ey)) |
               (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
             continue;
-          const int li = tile_slot(lx, ly, lz);
+          move_to(pad_slot(lx + 1, ly + 1, lz + 1));
 #pragma unroll
-          for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][u], det_scale));
+          for (int b = 0; b < NB; ++b) run[b][0] += tile_value<T>(vv[b][u], det_scale);
         } else {
-          const TileAxis tx = tile_axis(X, x0, ex);
-          const TileAxis ty = tile_axis(Y, y0, ey);
-          const TileAxis tz = tile_axis(Z, z0, ez);
-          if (!(tx.any & ty.any & tz.any)) continue;
+          // some corner lies in the tile iff the lower corner is in [origin - 1, origin +
+          // extent - 1] on every axis (a collapsed axis, lower = upper corner, only occurs on
+          // the box faces, where the lower corner is never origin - 1)
+          const int px = X.lo - x0 + 1, py = Y.lo - y0 + 1, pz = Z.lo - z0 + 1;
+          if ((static_cast<unsigned>(px) > static_cast<unsigned>(ex)) |
+              (static_cast<unsigned>(py) > static_cast<unsigned>(ey)) |
+              (static_cast<unsigned>(pz) > static_cast<unsigned>(ez)))
+            continue;
+          // a collapsed axis carries its whole weight on the lower corner
+          const float wx[2] = {X.lo == X.hi ? 1.0f : X.w0, X.lo == X.hi ? 0.0f : X.w1};
+          const float wy[2] = {Y.lo == Y.hi ? 1.0f : Y.w0, Y.lo == Y.hi ? 0.0f : Y.w1};
+          const float wz[2] = {Z.lo == Z.hi ? 1.0f : Z.w0, Z.lo == Z.hi ? 0.0f : Z.w1};
+          move_to(pad_slot(px, py, pz));
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
-            const float w = (tx.w[c >> 2] * ty.w[(c >> 1) & 1]) * tz.w[c & 1];
-            const int li = tile_slot(tx.off[c >> 2], ty.off[(c >> 1) & 1], tz.off[c & 1]);
+            const float w = (wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1];
 #pragma unroll
-            for (int b = 0; b < NB; ++b) atomicAdd(&acc[b][li], tile_value<T>(vv[b][u] * w, det_scale));
+            for (int b = 0; b < NB; ++b) run[b][c] += tile_value<T>(vv[b][u] * w, det_scale);
           }
         }
       }
+      flush();
     }
     __syncthreads();
 
@@ -986,7 +1000,7 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
                  cz_any = (gz == 0 || gz == nz - 1);
 #pragma unroll
       for (int b = 0; b < NB; ++b) {
-        T val = acc[b][tile_slot(lx, ly, lz)];
+        T val = acc[b][pad_slot(lx + 1, ly + 1, lz + 1)];
         if (cx_any && cy_any && cz_any && part == 0) {
           for (int c = 0; c < 8; ++c) {
             const int vx = (c & 4) ? nx - 1 : 0, vy = (c & 2) ? ny - 1 : 0, vz = (c & 1) ? nz - 1 : 0;
@@ -1133,7 +1147,19 @@ hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool det, bool nearest
     case 1: return launch_tile_nb<1>(a, det, nearest, s);
     case 2: return launch_tile_nb<2>(a, det, nearest, s);
     case 3: return launch_tile_nb<3>(a, det, nearest, s);
-    case 4: return launch_tile_nb<4>(a, det, nearest, s);
+    case 4: {
+      // four LDS tiles with halos exceed a compute unit's LDS: two passes of two bins over
+      // the same schedule (each pass leaves it rewound for the next)
+      hipError_t e = launch_tile_nb<2>(a, det, nearest, s);
+      if (e != hipSuccess) return e;
+      TileArgs b = a;
+      b.V = a.V + 2 * a.v_bin_stride;
+      if (a.out) b.out = a.out + 2 * a.out_stride;
+      if (a.out_q) b.out_q = a.out_q + 2 * a.out_stride;
+      b.corner = a.corner + 2 * 8;
+      b.corner_q = a.corner_q + 2 * 8;
+      return launch_tile_nb<2>(b, det, nearest, s);
+    }
     default: return hipErrorInvalidValue;
   }
 }
