@@ -510,7 +510,8 @@ struct TiledLayout {
   bool interleaved = false;
   size_t corner = 0, sched = 0, med = 0, v = 0, p = 0, segtot = 0, recs = 0, total = 0;   // byte offsets / size
   size_t sched_bytes = 0;
-  int64_t rec_capacity = 0;   // chunk records of the shared buffer (0: a plan's own slices)
+  int64_t rec_capacity = 0;   // chunk records of each shared buffer (0: a plan's own slices)
+  int rec_buffers = 1;        // shared buffers: two when several launches alternate
   std::vector<int> seg_len;   // per source chunk: substeps per record run (0: whole rays)
 };
 
@@ -579,7 +580,8 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
   L.p = L.v + align256(size_t(v_elems_max) * nb_max * sizeof(float));
   L.segtot = L.p + align256(size_t(p_elems_max) * nb_max * sizeof(float));
   L.recs = L.segtot + align256(size_t(t_elems_max) * nb_max * sizeof(float2));
-  L.total = L.recs + size_t(L.rec_capacity) * sizeof(uint2);
+  L.rec_buffers = L.n_launch > 1 ? 2 : 1;
+  L.total = L.recs + size_t(L.rec_buffers) * align256(size_t(L.rec_capacity) * sizeof(uint2));
   return L;
 }
 
@@ -629,6 +631,25 @@ struct SideStream {
   ~SideStream() {
     if (fork) (void)hipEventDestroy(fork);
     if (done) (void)hipEventDestroy(done);
+  }
+};
+
+// Events that order the two streams launch by launch (destroyed with the list; HIP
+// releases an event whose recorded work is still pending once that work completes).
+struct EventList {
+  std::vector<hipEvent_t> ev;
+  hipError_t create(size_t n) {
+    for (size_t i = 0; i < n; ++i) {
+      hipEvent_t x = nullptr;
+      const hipError_t e = hipEventCreateWithFlags(&x, hipEventDisableTiming);
+      if (e != hipSuccess) return e;
+      ev.push_back(x);
+    }
+    return hipSuccess;
+  }
+  hipEvent_t operator[](size_t i) const { return ev[i]; }
+  ~EventList() {
+    for (hipEvent_t x : ev) (void)hipEventDestroy(x);
   }
 };
 
@@ -725,16 +746,21 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       sched.carve(ws + L.sched + launch * L.sched_bytes, L.tiles);
       if (slices && launch < static_cast<int>(slices->off.size()))
         sched.apply(t, plan.item_chunks, slices->base + slices->off[launch], slices->count[launch]);
-      else
-        sched.apply(t, plan.item_chunks, reinterpret_cast<uint2*>(ws + L.recs), L.rec_capacity);
+      else   // launches alternate between the shared buffers
+        sched.apply(t, plan.item_chunks,
+                    reinterpret_cast<uint2*>(ws + L.recs + (launch % L.rec_buffers) *
+                                                               align256(size_t(L.rec_capacity) * sizeof(uint2))),
+                    L.rec_capacity);
       launches.push_back({r, t, nb, blocks, fix_waves});
     }
   }
 
   // The schedules and records depend on the geometry only. A stateless call computes them
-  // on a side stream, overlapped with the gather table and the first record pass; the
-  // first tile pass waits for them. Launches that share one record buffer fill it each
-  // just before their tile pass instead.
+  // on a side stream, overlapped with the gather table and the record passes. With one
+  // launch, the first tile pass waits for all of it. Several launches alternate between
+  // two record buffers: the side stream fills launch i + 2 once the tile pass of launch i
+  // has read its buffer, while launches i + 1 and i + 2 record (per-launch events order
+  // the two streams). Without a side stream, each fill runs just before its tile pass.
   hipStream_t sched_st = st;
   SideStream side;
   if (mode == TiledMode::kFull && side.open(st) == hipSuccess) sched_st = side.stream;
@@ -743,12 +769,23 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       if ((e = rtmi::launch_tile_schedule(l.t, L.tiles, sched_st)) != hipSuccess)
         return hip_fail(e, "tile schedule");
   const bool fill_each = mode == TiledMode::kFull && launches.size() > 1;
+  const bool fill_ahead = fill_each && sched_st != st;
   if (mode == TiledMode::kFill || (mode == TiledMode::kFull && !fill_each))
     for (const LaunchArgs& l : launches)
       if ((e = rtmi::launch_tile_fill(l.t, L.tiles, sched_st)) != hipSuccess)
         return hip_fail(e, "tile records");
   if (mode == TiledMode::kSchedule || mode == TiledMode::kFill) return RTMI_OK;
-  if (sched_st != st && (e = side.join(st)) != hipSuccess) return hip_fail(e, "side stream");
+  EventList filled, read;   // per launch: its records written / its tile pass done
+  if (fill_ahead) {
+    if ((e = filled.create(launches.size())) != hipSuccess || (e = read.create(launches.size())) != hipSuccess)
+      return hip_fail(e, "hipEventCreate");
+    for (size_t i = 0; i < std::min<size_t>(2, launches.size()); ++i)
+      if ((e = rtmi::launch_tile_fill(launches[i].t, L.tiles, sched_st)) != hipSuccess ||
+          (e = hipEventRecord(filled[i], sched_st)) != hipSuccess)
+        return hip_fail(e, "tile records");
+  } else if (sched_st != st && (e = side.join(st)) != hipSuccess) {
+    return hip_fail(e, "side stream");
+  }
 
   if (L.interleaved && (e = rtmi::launch_cell_table(p.j, p.kap, med, p.nx, p.ny, p.nz, st)) != hipSuccess)
     return hip_fail(e, "gather table");
@@ -758,8 +795,9 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
     else e = rtmi::launch_fill_zero(p.out, total, st);
     if (e != hipSuccess) return hip_fail(e, "fill");
   }
-  bool joined = sched_st == st;
-  for (const LaunchArgs& l : launches) {
+  bool joined = sched_st == st || fill_ahead;
+  for (size_t li = 0; li < launches.size(); ++li) {
+    const LaunchArgs& l = launches[li];
     if ((e = rtmi::launch_fill_zero(corner, 2 * kCornerBytes / sizeof(float), st)) != hipSuccess)
       return hip_fail(e, "fill");
     if (l.blocks > 0) {
@@ -775,13 +813,23 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       if ((e = hipStreamWaitEvent(st, side.done, 0)) != hipSuccess) return hip_fail(e, "side stream");
       joined = true;
     }
-    if (fill_each && (e = rtmi::launch_tile_fill(l.t, L.tiles, st)) != hipSuccess)
+    if (fill_ahead) {
+      if ((e = hipStreamWaitEvent(st, filled[li], 0)) != hipSuccess) return hip_fail(e, "side stream");
+    } else if (fill_each && (e = rtmi::launch_tile_fill(l.t, L.tiles, st)) != hipSuccess) {
       return hip_fail(e, "tile records");
+    }
     TimedLaunch tl;
     if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl)) != hipSuccess) return hip_fail(e, "timing");
     if ((e = rtmi::launch_tile_run(l.t, l.nb, plan.det, false, st)) != hipSuccess)
       return hip_fail(e, "tile launch");
     if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
+    if (fill_ahead && li + 2 < launches.size()) {   // launch li + 2 reuses this launch's buffer
+      if ((e = hipEventRecord(read[li], st)) != hipSuccess ||
+          (e = hipStreamWaitEvent(sched_st, read[li], 0)) != hipSuccess ||
+          (e = rtmi::launch_tile_fill(launches[li + 2].t, L.tiles, sched_st)) != hipSuccess ||
+          (e = hipEventRecord(filled[li + 2], sched_st)) != hipSuccess)
+        return hip_fail(e, "tile records");
+    }
   }
   if (!given_ws && (e = hipFreeAsync(ws, st)) != hipSuccess) return hip_fail(e, "workspace release");
   return RTMI_OK;
