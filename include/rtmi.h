@@ -88,11 +88,15 @@ typedef struct rtmi_options {
  *    work-group own a 16^3 block of the output, accumulate the deposits landing in it
  *    in LDS and add it to the field. Workspace: 4 bytes per (ray, substep, bin), plus
  *    64 bytes per voxel (a gather table of j and kappa) when j and kappa are shared by
- *    the bins, taken from a stream-ordered pool the library owns per device (allocated
- *    on first use, then reused; see rtmi_reserve). The tile schedules, which depend on
- *    the geometry only, run on a library-owned stream of the same device, ordered by
- *    events after the caller's earlier work on `stream` and before the tile pass; the
- *    call's results are still ordered on `stream` like any other enqueued work.
+ *    the bins, plus the chunk records that list each tile's work (8 bytes per chunk of
+ *    up to 8 substeps and tile it reaches; sized by an upper bound, 8 tiles per chunk
+ *    for step_size <= 0.9, two such buffers when the sources or bins need several
+ *    launches), taken from a stream-ordered pool the library owns per device (allocated
+ *    on first use, then reused; see rtmi_reserve). The tile schedules and records, which
+ *    depend on the geometry only, are computed on a library-owned stream of the same
+ *    device, ordered by events after the caller's earlier work on `stream` and before
+ *    the tile passes that read them; the call's results are still ordered on `stream`
+ *    like any other enqueued work.
  *  RTMI_PATH_DIRECT: one kernel; each lane sums its ray's consecutive deposits into a
  *    2x2x2 register window and flushes it with global atomics. No workspace. */
 enum { RTMI_PATH_TILED = 0, RTMI_PATH_DIRECT = 1 };
@@ -170,8 +174,8 @@ int32_t rtmi_trace_bins(const float* j_maps, int64_t j_bin_stride,
  * and substep caps, times bins, exactly as rtmi_trace_bins computes them (same field, and
  * in the deterministic mode the same bits). Creation validates the geometry, uploads the
  * direction tables, allocates the whole workspace (rtmi_plan_workspace_bytes) and
- * computes the tile schedules, which depend on the geometry only; it synchronises and
- * may allocate. Execution takes new maps and only enqueues kernels: it allocates nothing,
+ * computes the tile schedules and chunk records, which depend on the geometry only (the
+ * records are counted first and allocated exactly); it synchronises and may allocate. Execution takes new maps and only enqueues kernels: it allocates nothing,
  * does not synchronise and reads no device data on the host, so it may be captured into
  * a HIP graph and replayed. Executions of one plan share its workspace: they must be
  * ordered on one stream (or otherwise serialised), never run concurrently. A plan
