@@ -1143,25 +1143,21 @@ hipError_t launch_tile_fill(const TileArgs& a, int tiles, hipStream_t s) {
 }
 
 hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool det, bool nearest, hipStream_t s) {
-  switch (n_bins) {
-    case 1: return launch_tile_nb<1>(a, det, nearest, s);
-    case 2: return launch_tile_nb<2>(a, det, nearest, s);
-    case 3: return launch_tile_nb<3>(a, det, nearest, s);
-    case 4: {
-      // four LDS tiles with halos exceed a compute unit's LDS: two passes of two bins over
-      // the same schedule (each pass leaves it rewound for the next)
-      hipError_t e = launch_tile_nb<2>(a, det, nearest, s);
-      if (e != hipSuccess) return e;
-      TileArgs b = a;
-      b.V = a.V + 2 * a.v_bin_stride;
-      if (a.out) b.out = a.out + 2 * a.out_stride;
-      if (a.out_q) b.out_q = a.out_q + 2 * a.out_stride;
-      b.corner = a.corner + 2 * 8;
-      b.corner_q = a.corner_q + 2 * 8;
-      return launch_tile_nb<2>(b, det, nearest, s);
-    }
-    default: return hipErrorInvalidValue;
+  // One pass per bin over the same schedule (each pass leaves it rewound for the next).
+  // A one-bin LDS tile with its halo lets three work-groups share a compute unit; tiles
+  // of several bins would hold one, and measured slower than repeating the geometry.
+  if (n_bins < 1 || n_bins > kMaxBinsPerLaunch) return hipErrorInvalidValue;
+  for (int b0 = 0; b0 < n_bins; ++b0) {
+    TileArgs b = a;
+    b.V = a.V + b0 * a.v_bin_stride;
+    if (a.out) b.out = a.out + b0 * a.out_stride;
+    if (a.out_q) b.out_q = a.out_q + b0 * a.out_stride;
+    b.corner = a.corner + b0 * 8;
+    b.corner_q = a.corner_q + b0 * 8;
+    const hipError_t e = launch_tile_nb<1>(b, det, nearest, s);
+    if (e != hipSuccess) return e;
   }
+  return hipSuccess;
 }
 
 }  // namespace rtmi
