@@ -74,6 +74,32 @@ def test_plan_deterministic_is_bitwise_trace_bins(rt, dev, batch):
         assert torch.equal(got.view(torch.int32), want.view(torch.int32))
 
 
+@pytest.mark.parametrize("ds,c,outside", [(0.9, 20.0, False), (1.7, 40.0, True), (4.5, 60.0, True)])
+def test_stateless_record_bound_drops_nothing(rt, dev, ds, c, outside):
+    """A stateless call sizes its chunk-record buffer by an upper bound on the tiles that
+    can list one chunk (it grows with the step size); a plan counts its records and
+    allocates exactly. A record dropped for want of space would change the deterministic
+    field, so the two must agree bit for bit, here with large steps and with sources
+    outside the box whose rays run along its faces; and both must match the oracle."""
+    rng = np.random.default_rng(int(ds * 10))
+    shape = (40, 36, 44)
+    j = rng.random(shape).astype(np.float32)
+    kap = (0.05 * rng.random(shape)).astype(np.float32)
+    src = rng.uniform(0, 35, size=(6, 3)).astype(np.float32)
+    if outside:
+        src[:3] = np.array([[-7.5, 10.0, 20.0], [45.0, -3.0, 50.0], [20.0, 18.0, -12.0]], np.float32)
+    rays = [512, 300, 1000, 64, 777, 2048]
+    note(f"record bound: ds {ds}, c dt {c}, sources outside the box: {outside}")
+    jd, kd = torch.from_numpy(j).to(dev), torch.from_numpy(kap).to(dev)
+    want = rt.trace_bins(jd, kd, src, rays, ds, c, 1.0, deterministic=True)
+    plan = rt.Plan(shape, src, rays, ds, c, 1.0, deterministic=True)
+    got = plan.execute(jd, kd)
+    assert torch.equal(got.view(torch.int32), want.view(torch.int32))
+    ref = oracle.trace_multi(j, kap, src, rays, ds, c, 1.0)
+    err = np.linalg.norm(want[0].cpu().numpy() - ref) / np.linalg.norm(ref)
+    assert err <= 1e-5, err
+
+
 def test_plan_matches_oracle_small(rt, dev):
     """Parity of a plan with the FP64 oracle on a small two-source, two-bin case."""
     w = inputs.uniform_blob()
