@@ -91,8 +91,11 @@ typedef struct rtmi_options {
  *    the bins, plus the chunk records that list each tile's work (8 bytes per chunk of
  *    up to 8 substeps and tile it reaches; sized by an upper bound, 8 tiles per chunk
  *    for step_size <= 0.9, two such buffers when the sources or bins need several
- *    launches), taken from a stream-ordered pool the library owns per device (allocated
- *    on first use, then reused; see rtmi_reserve). The tile schedules and records, which
+ *    launches), taken from a stream-ordered pool the library owns per device. The
+ *    library keeps one such workspace per (device, stream) and reuses it for the next
+ *    call on that stream, growing it when a call needs more; it is held until the process
+ *    ends (one per stream the caller uses). During graph capture a call takes its own
+ *    stream-ordered allocation instead, which the graph owns. The tile schedules and records, which
  *    depend on the geometry only, are computed on a library-owned stream of the same
  *    device, ordered by events after the caller's earlier work on `stream` and before
  *    the tile passes that read them; the call's results are still ordered on `stream`
@@ -124,8 +127,9 @@ int32_t rtmi_fibonacci_directions(int32_t n, float* host_xyz);
 int32_t rtmi_prepare(int32_t num_rays);
 
 /* Grow the current device's workspace pool so that tiled calls needing up to `bytes`
- * of workspace allocate nothing from the system (their pool allocations are then
- * served from memory the pool already holds). */
+ * of workspace allocate nothing from the system (their pool allocations, the first on
+ * each stream and those made during graph capture, are then served from memory the pool
+ * already holds). */
 int32_t rtmi_reserve(int64_t bytes);
 
 /* The single-source kernel of Sec. 2: advance the field over one dt for one source.

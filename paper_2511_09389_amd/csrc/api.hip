@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -294,6 +295,49 @@ int32_t pool_alloc(void** ptr, size_t bytes, hipStream_t s) {
   if (int32_t st = get_pool(&pool)) return st;
   const hipError_t e = hipMallocFromPoolAsync(ptr, std::max<size_t>(bytes, 256), pool, s);
   if (e != hipSuccess) return hip_fail(e, "workspace allocation");
+  return RTMI_OK;
+}
+
+// Scratch of the stateless calls, kept per (device, stream, purpose) and reused by the
+// next call on the same stream: stream order makes the reuse safe (the call before has
+// finished with it by the time the next one's kernels run), and it spares a stream-ordered
+// free per call, which costs a few hundred microseconds of host time on this runtime,
+// more than a whole 128^3 march. A call that needs more grows it (the old block is freed
+// in stream order). Under graph capture a call takes its own stream-ordered allocation,
+// which the graph owns. The cached blocks are held until the process ends.
+enum WorkspaceSlot { kSlotTiled = 0, kSlotFixedPoint = 1, kSlotAdjoint = 2, kSlotConv = 3 };
+
+struct Scratch {
+  char* ptr = nullptr;
+  bool owned = false;   // freed by the caller (captured allocation)
+  hipError_t release(hipStream_t s) { return owned ? hipFreeAsync(ptr, s) : hipSuccess; }
+};
+
+std::mutex g_scratch_mu;   // (not g_mu: the pool lookup below takes that one)
+std::map<std::tuple<int, hipStream_t, int>, std::pair<char*, size_t>> g_scratch;
+
+int32_t acquire_scratch(size_t bytes, hipStream_t s, WorkspaceSlot slot, Scratch* out) {
+  bytes = std::max<size_t>(bytes, 256);
+  if (capturing(s)) {
+    out->owned = true;
+    return pool_alloc(reinterpret_cast<void**>(&out->ptr), bytes, s);
+  }
+  int dev = 0;
+  if (int32_t st = current_device(&dev)) return st;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  auto& held = g_scratch[std::make_tuple(dev, s, static_cast<int>(slot))];
+  if (held.second < bytes) {
+    if (held.first) {
+      const hipError_t e = hipFreeAsync(held.first, s);
+      held = {nullptr, 0};
+      if (e != hipSuccess) return hip_fail(e, "workspace release");
+    }
+    void* p = nullptr;
+    if (int32_t rc = pool_alloc(&p, bytes, s)) return rc;
+    held = {static_cast<char*>(p), bytes};
+  }
+  out->ptr = held.first;
+  out->owned = false;
   return RTMI_OK;
 }
 
@@ -662,9 +706,11 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
   if ((mode == TiledMode::kFill || mode == TiledMode::kReplay) && !slices)
     return fail(RTMI_ERR_INVALID_ARG, "a plan's chunk records are missing");
   char* ws = given_ws;
+  Scratch scratch;
   if (!ws) {
     if (mode != TiledMode::kFull) return fail(RTMI_ERR_INVALID_ARG, "a plan's workspace is missing");
-    if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&ws), L.total, st)) return rc;
+    if (int32_t rc = acquire_scratch(L.total, st, kSlotTiled, &scratch)) return rc;
+    ws = scratch.ptr;
   }
   float* corner = reinterpret_cast<float*>(ws + L.corner);
   unsigned long long* corner_q = reinterpret_cast<unsigned long long*>(ws + L.corner + kCornerBytes);
@@ -831,7 +877,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
         return hip_fail(e, "tile records");
     }
   }
-  if (!given_ws && (e = hipFreeAsync(ws, st)) != hipSuccess) return hip_fail(e, "workspace release");
+  if ((e = scratch.release(st)) != hipSuccess) return hip_fail(e, "workspace release");
   return RTMI_OK;
 }
 
@@ -920,8 +966,10 @@ int32_t run(const Problem& p) {
   const int64_t total = plan.cells * p.n_bins;
   unsigned long long* out_q = nullptr;
   double* det_scale = nullptr;
+  Scratch fixed;
   if (plan.det) {
-    if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&out_q), size_t(total) * 8 + 16, st)) return rc;
+    if (int32_t rc = acquire_scratch(size_t(total) * 8 + 16, st, kSlotFixedPoint, &fixed)) return rc;
+    out_q = reinterpret_cast<unsigned long long*>(fixed.ptr);
     det_scale = reinterpret_cast<double*>(out_q + total);
     if (!plan.tiled && (e = rtmi::launch_fill_zero_u64(out_q, total, st)) != hipSuccess)
       return hip_fail(e, "fill");
@@ -936,7 +984,7 @@ int32_t run(const Problem& p) {
   if (plan.det) {
     if ((e = rtmi::launch_det_convert(out_q, det_scale, p.out, total, st)) != hipSuccess)
       return hip_fail(e, "det_convert");
-    if ((e = hipFreeAsync(out_q, st)) != hipSuccess) return hip_fail(e, "workspace release");
+    if ((e = fixed.release(st)) != hipSuccess) return hip_fail(e, "workspace release");
   }
   if (explicit_table && (e = hipFreeAsync(explicit_table, st)) != hipSuccess)
     return hip_fail(e, "workspace release");
@@ -978,9 +1026,10 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
     rec_capacity = std::max(rec_capacity, record_bound(p, plan, s0, std::min(kMaxSrcPerLaunch, p.n_src - s0),
                                                        tiles_x, tiles_y, tiles_z));
   const size_t rec_off = corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes) + sched_bytes;
-  char* ws = nullptr;
-  if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&ws), rec_off + size_t(rec_capacity) * sizeof(uint2), st))
+  Scratch scratch;
+  if (int32_t rc = acquire_scratch(rec_off + size_t(rec_capacity) * sizeof(uint2), st, kSlotAdjoint, &scratch))
     return rc;
+  char* ws = scratch.ptr;
   TileSchedule sched;
   sched.carve(ws + corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes), tiles);
   uint2* recs = reinterpret_cast<uint2*>(ws + rec_off);
@@ -1061,7 +1110,7 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
     t.out = grad_k;
     if ((e = rtmi::launch_tile_run(t, 1, false, true, st)) != hipSuccess) return hip_fail(e, "tile launch");
   }
-  if ((e = hipFreeAsync(ws, st)) != hipSuccess) return hip_fail(e, "workspace release");
+  if ((e = scratch.release(st)) != hipSuccess) return hip_fail(e, "workspace release");
   g_error.clear();
   return RTMI_OK;
 }
@@ -1443,11 +1492,12 @@ int32_t rtmi_conv3d_backward_weight(const void* x, const void* dz, int32_t n, in
   a.w_dim = w_dim;
   const hipStream_t st = static_cast<hipStream_t>(stream);
   const size_t nvox = size_t(n) * d * h * w_dim;
-  unsigned short* scratch = nullptr;   // channel-major copies: x three times, dz once
-  if (int32_t rc = pool_alloc(reinterpret_cast<void**>(&scratch), nvox * rtmi::kConvChannels * 4 * 2, st)) return rc;
+  Scratch held;   // channel-major copies: x three times, dz once
+  if (int32_t rc = acquire_scratch(nvox * rtmi::kConvChannels * 4 * 2, st, kSlotConv, &held)) return rc;
+  unsigned short* scratch = reinterpret_cast<unsigned short*>(held.ptr);
   hipError_t e = rtmi::launch_wgrad(a, scratch, scratch + nvox * rtmi::kConvChannels * 3, st);
   if (e != hipSuccess) return hip_fail(e, "conv backward-weight launch");
-  if ((e = hipFreeAsync(scratch, st)) != hipSuccess) return hip_fail(e, "workspace release");
+  if ((e = held.release(st)) != hipSuccess) return hip_fail(e, "workspace release");
   g_error.clear();
   return RTMI_OK;
 }
