@@ -188,7 +188,7 @@ def main():
     plan_graph = {"ms_per_step": 1e3 * (g1 - g0) / args.steps, "value": units * args.steps / (g1 - g0),
                   "tile_item_chunks": best_chunks,
                   "autotune_ms": {str(c): round(t, 4) for c, t in tune_ms.items()},
-                  "note": "plan made once (tables, workspace, tile schedule), step replayed as one graph"}
+                  "note": "plan made once (tables, workspace, tile schedules and chunk records), step replayed as one graph"}
     del graph
     plan.close()
 

@@ -1275,7 +1275,7 @@ extern "C" {
 
 const char* rtmi_last_error(void) { return g_error.c_str(); }
 
-int32_t rtmi_version(void) { return 300; }
+int32_t rtmi_version(void) { return 310; }
 
 int64_t rtmi_num_substeps(float step_size, float radiation_velocity, float time_step,
                           int32_t cap) {
