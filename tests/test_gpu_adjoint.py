@@ -50,6 +50,26 @@ def test_vjp_matches_oracle(rt, dev, shape, src, rays, caps):
     assert ek <= 1e-5
 
 
+def test_vjp_many_sources_span_launches(rt, dev):
+    """70 sources (three launches of up to 32) with caps, some outside the box: each
+    launch recomputes its tile schedule and chunk records into the one record buffer,
+    and both deposits of every launch add into the gradients."""
+    rng = np.random.default_rng(5)
+    shape = (20, 18, 22)
+    src = rng.uniform(-2, 20, size=(70, 3)).astype(np.float32)
+    rays = rng.integers(8, 120, size=70)
+    caps = rng.integers(0, 30, size=70)
+    kap = (0.15 * rng.random(shape)).astype(np.float32)
+    j = rng.random(shape).astype(np.float32)
+    G = rng.normal(size=shape).astype(np.float32)
+    note(f"vjp {shape}, 70 sources (3 launches)")
+    gj, gk = rt.trace_vjp(to_dev(j, dev), to_dev(kap, dev), src, rays, 0.5, 18.0, 1.0, to_dev(G, dev),
+                          substep_cap=caps)
+    wj, wk = oracle.trace_multi_vjp(j, kap, src, rays, 0.5, 18.0, 1.0, G, caps=caps)
+    assert rel_l2(gj.cpu().numpy(), wj) <= 1e-5
+    assert rel_l2(gk.cpu().numpy(), wk) <= 1e-5
+
+
 def test_vjp_matches_central_differences(rt, dev):
     """16^3, 64 rays: dL/dkappa and dL/dj against central differences (h = 1e-3) of the
     FP64 oracle, for L = <G, J>."""
