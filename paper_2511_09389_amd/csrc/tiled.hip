@@ -839,22 +839,17 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
   }
 }
 
-// Lanes per tile work-group. 512 lets two work-groups share a compute unit (one bin), so
-// one can compute while the other waits at a barrier or on memory.
-template <int NB>
-constexpr int tile_threads() { return kTileThreads; }
-
+// One bin per launch, 512 lanes per work-group, three work-groups per compute unit.
 // The tile is accumulated in binary64 (or 64-bit fixed point in the deterministic mode):
 // a voxel next to a source collects thousands of deposits, and binary32 running sums of
 // that length drift by more than the binary32 field is allowed to differ from the exact one.
 // NEAREST: each sample adds its value to its nearest voxel only (the adjoint's kappa
 // deposit) instead of the trilinear stencil.
-template <int NB, bool DET, bool NEAREST>
-__global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs a) {
+template <bool DET, bool NEAREST>
+__global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
   using T = typename std::conditional<DET, unsigned long long, double>::type;
-  constexpr int kThreads = tile_threads<NB>();
-  static_assert(NB * kPadVox * sizeof(T) + sizeof(SrcTable) + 64 <= 160 * 1024, "LDS tile too large");
-  __shared__ T acc[NB][kPadVox];
+  constexpr int kThreads = kTileThreads;
+  __shared__ T acc[kPadVox];
   __shared__ SrcTable S;
   __shared__ int2 claimed;
   const int tid = static_cast<int>(threadIdx.x);
@@ -870,7 +865,7 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
       const int item = atomicAdd(a.item_next, 1);
       claimed = item < n_items ? a.item_map[item] : make_int2(-1, 0);
     }
-    for (int i = tid; i < NB * kPadVox; i += kThreads) (&acc[0][0])[i] = T(0);
+    for (int i = tid; i < kPadVox; i += kThreads) acc[i] = T(0);
     __syncthreads();
     const int t = claimed.x;
     if (t < 0) {
@@ -902,18 +897,14 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
       const float4 src = S.pos[s];
       const float* vrow = a.V + row_slot(S.vbase[s], S.nrays[s], ray, kblk);
       // the chunk's recorded values, fetched before any of them is needed
-      float vv[NB][kChunk];
+      float vv[kChunk];
 #pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        const float4* src4 = reinterpret_cast<const float4*>(vrow + b * a.v_bin_stride);
-#pragma unroll
-        for (int q = 0; q < kChunk / 4; ++q) {
-          const float4 f = src4[q];
-          vv[b][4 * q] = f.x;
-          vv[b][4 * q + 1] = f.y;
-          vv[b][4 * q + 2] = f.z;
-          vv[b][4 * q + 3] = f.w;
-        }
+      for (int q = 0; q < kChunk / 4; ++q) {
+        const float4 f = reinterpret_cast<const float4*>(vrow)[q];
+        vv[4 * q] = f.x;
+        vv[4 * q + 1] = f.y;
+        vv[4 * q + 2] = f.z;
+        vv[4 * q + 3] = f.w;
       }
       // A lane sums the weighted corners of consecutive samples that share a lower corner
       // (the nearest voxel, for NEAREST) in registers: samples less than a voxel apart
@@ -921,23 +912,19 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
       // end of the chunk, which takes a third or more of the LDS atomics away.
       constexpr int kCorners = NEAREST ? 1 : 8;
       int cell = -1;   // padded slot of the current lower corner (nearest voxel)
-      T run[NB][kCorners];
+      T run[kCorners];
       auto flush = [&]() {
         if (cell < 0) return;
 #pragma unroll
         for (int c = 0; c < kCorners; ++c)
-#pragma unroll
-          for (int b = 0; b < NB; ++b)
-            atomicAdd(&acc[b][cell + (c >> 2) * kPadPlane + ((c >> 1) & 1) * kPadRow + (c & 1)], run[b][c]);
+          atomicAdd(&acc[cell + (c >> 2) * kPadPlane + ((c >> 1) & 1) * kPadRow + (c & 1)], run[c]);
       };
       auto move_to = [&](int slot) {
         if (slot == cell) return;
         flush();
         cell = slot;
 #pragma unroll
-        for (int c = 0; c < kCorners; ++c)
-#pragma unroll
-          for (int b = 0; b < NB; ++b) run[b][c] = T(0);
+        for (int c = 0; c < kCorners; ++c) run[c] = T(0);
       };
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) {
@@ -962,8 +949,7 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
               (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
             continue;
           move_to(pad_slot(lx + 1, ly + 1, lz + 1));
-#pragma unroll
-          for (int b = 0; b < NB; ++b) run[b][0] += tile_value<T>(vv[b][u], det_scale);
+          run[0] += tile_value<T>(vv[u], det_scale);
         } else {
           // some corner lies in the tile iff the lower corner is in [origin - 1, origin +
           // extent - 1] on every axis (a collapsed axis, lower = upper corner, only occurs on
@@ -981,8 +967,7 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
             const float w = (wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1];
-#pragma unroll
-            for (int b = 0; b < NB; ++b) run[b][c] += tile_value<T>(vv[b][u] * w, det_scale);
+            run[c] += tile_value<T>(vv[u] * w, det_scale);
           }
         }
       }
@@ -998,33 +983,30 @@ __global__ void __launch_bounds__(tile_threads<NB>()) tile_kernel(const TileArgs
       const long long voxel = (static_cast<long long>(gx) * ny + gy) * nz + gz;
       const bool cx_any = (gx == 0 || gx == nx - 1), cy_any = (gy == 0 || gy == ny - 1),
                  cz_any = (gz == 0 || gz == nz - 1);
-#pragma unroll
-      for (int b = 0; b < NB; ++b) {
-        T val = acc[b][pad_slot(lx + 1, ly + 1, lz + 1)];
-        if (cx_any && cy_any && cz_any && part == 0) {
-          for (int c = 0; c < 8; ++c) {
-            const int vx = (c & 4) ? nx - 1 : 0, vy = (c & 2) ? ny - 1 : 0, vz = (c & 1) ? nz - 1 : 0;
-            if (vx == gx && vy == gy && vz == gz) {
-              if constexpr (DET) val += a.corner_q[b * 8 + c];
-              else val += a.corner[b * 8 + c];
-            }
+      T val = acc[pad_slot(lx + 1, ly + 1, lz + 1)];
+      if (cx_any && cy_any && cz_any && part == 0) {
+        for (int c = 0; c < 8; ++c) {
+          const int vx = (c & 4) ? nx - 1 : 0, vy = (c & 2) ? ny - 1 : 0, vz = (c & 1) ? nz - 1 : 0;
+          if (vx == gx && vy == gy && vz == gz) {
+            if constexpr (DET) val += a.corner_q[c];
+            else val += a.corner[c];
           }
         }
-        // The field was zeroed before the launch. A tile served by one item adds its sum
-        // with a plain read-modify-write; items sharing a tile add atomically (consecutive
-        // lanes hold consecutive z, so the adds of a wave coalesce).
-        if constexpr (DET) {
-          unsigned long long* o = a.out_q + b * a.out_stride + voxel;
-          if (val != 0ull) {
-            if (parts > 1) atomicAdd(o, val);
-            else *o += val;
-          }
-        } else {
-          float* o = a.out + b * a.out_stride + voxel;
-          if (val != 0.0) {
-            if (parts > 1) unsafeAtomicAdd(o, static_cast<float>(val));
-            else *o = static_cast<float>(static_cast<double>(*o) + val);
-          }
+      }
+      // The field was zeroed before the launch. A tile served by one item adds its sum
+      // with a plain read-modify-write; items sharing a tile add atomically (consecutive
+      // lanes hold consecutive z, so the adds of a wave coalesce).
+      if constexpr (DET) {
+        unsigned long long* o = a.out_q + voxel;
+        if (val != 0ull) {
+          if (parts > 1) atomicAdd(o, val);
+          else *o += val;
+        }
+      } else {
+        float* o = a.out + voxel;
+        if (val != 0.0) {
+          if (parts > 1) unsafeAtomicAdd(o, static_cast<float>(val));
+          else *o = static_cast<float>(static_cast<double>(*o) + val);
         }
       }
     }
@@ -1066,19 +1048,18 @@ int resident_groups(K kernel, int threads, int* cache) {
   return cache[dev];
 }
 
-template <int NB, bool DET, bool NEAREST>
+template <bool DET, bool NEAREST>
 hipError_t launch_tile_variant(const TileArgs& a, hipStream_t s) {
   static int cache[kCacheDevices] = {0};   // one per kernel variant and device
-  const auto kernel = tile_kernel<NB, DET, NEAREST>;
-  const int groups = resident_groups(kernel, tile_threads<NB>(), cache);
-  hipLaunchKernelGGL(kernel, dim3(groups), dim3(tile_threads<NB>()), 0, s, a);
+  const auto kernel = tile_kernel<DET, NEAREST>;
+  const int groups = resident_groups(kernel, kTileThreads, cache);
+  hipLaunchKernelGGL(kernel, dim3(groups), dim3(kTileThreads), 0, s, a);
   return hipGetLastError();
 }
 
-template <int NB>
-hipError_t launch_tile_nb(const TileArgs& a, bool det, bool nearest, hipStream_t s) {
-  if (nearest) return det ? launch_tile_variant<NB, true, true>(a, s) : launch_tile_variant<NB, false, true>(a, s);
-  return det ? launch_tile_variant<NB, true, false>(a, s) : launch_tile_variant<NB, false, false>(a, s);
+hipError_t launch_tile_one_bin(const TileArgs& a, bool det, bool nearest, hipStream_t s) {
+  if (nearest) return det ? launch_tile_variant<true, true>(a, s) : launch_tile_variant<false, true>(a, s);
+  return det ? launch_tile_variant<true, false>(a, s) : launch_tile_variant<false, false>(a, s);
 }
 
 dim3 pairs_grid(const TileArgs& a, int tiles) {
@@ -1144,8 +1125,8 @@ hipError_t launch_tile_fill(const TileArgs& a, int tiles, hipStream_t s) {
 
 hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool det, bool nearest, hipStream_t s) {
   // One pass per bin over the same schedule (each pass leaves it rewound for the next).
-  // A one-bin LDS tile with its halo lets three work-groups share a compute unit; tiles
-  // of several bins would hold one, and measured slower than repeating the geometry.
+  // A one-bin LDS tile with its halo (49 KB) lets three work-groups share a compute unit;
+  // tiles of several bins would hold one, and measured slower than repeating the geometry.
   if (n_bins < 1 || n_bins > kMaxBinsPerLaunch) return hipErrorInvalidValue;
   for (int b0 = 0; b0 < n_bins; ++b0) {
     TileArgs b = a;
@@ -1154,7 +1135,7 @@ hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool det, bool nearest
     if (a.out_q) b.out_q = a.out_q + b0 * a.out_stride;
     b.corner = a.corner + b0 * 8;
     b.corner_q = a.corner_q + b0 * 8;
-    const hipError_t e = launch_tile_nb<1>(b, det, nearest, s);
+    const hipError_t e = launch_tile_one_bin(b, det, nearest, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
