@@ -479,19 +479,26 @@ constexpr int kItemChunks = 2 * rtmi::kTileThreads;
 struct TileSchedule {
   unsigned long long* cost = nullptr;
   long long *begin = nullptr, *count = nullptr, *fill = nullptr;
+  unsigned* mask = nullptr;   // per (tile, block of kPairBlock pairs): pairs with chunks
   int2* map = nullptr;
   int* counters = nullptr;   // item total, next, done; the record total at byte 16
-  static size_t bytes(int tiles) {
-    return 4 * align256(size_t(tiles) * 8) + align256(size_t(tiles) * rtmi::kMaxParts * sizeof(int2)) + 256;
+  static size_t mask_bytes(int tiles, int pair_blocks) {
+    return align256(size_t(tiles) * std::max(pair_blocks, 1) * (rtmi::kPairBlock / 32) * sizeof(unsigned));
   }
-  void carve(char* base, int tiles) {
+  static size_t bytes(int tiles, int pair_blocks) {
+    return 4 * align256(size_t(tiles) * 8) + mask_bytes(tiles, pair_blocks) +
+           align256(size_t(tiles) * rtmi::kMaxParts * sizeof(int2)) + 256;
+  }
+  void carve(char* base, int tiles, int pair_blocks) {
     const size_t per = align256(size_t(tiles) * 8);
     cost = reinterpret_cast<unsigned long long*>(base);
     begin = reinterpret_cast<long long*>(base + per);
     count = reinterpret_cast<long long*>(base + 2 * per);
     fill = reinterpret_cast<long long*>(base + 3 * per);
-    map = reinterpret_cast<int2*>(base + 4 * per);
-    counters = reinterpret_cast<int*>(base + 4 * per + align256(size_t(tiles) * rtmi::kMaxParts * sizeof(int2)));
+    mask = reinterpret_cast<unsigned*>(base + 4 * per);
+    base += 4 * per + mask_bytes(tiles, pair_blocks);
+    map = reinterpret_cast<int2*>(base);
+    counters = reinterpret_cast<int*>(base + align256(size_t(tiles) * rtmi::kMaxParts * sizeof(int2)));
   }
   long long* rec_total() const { return reinterpret_cast<long long*>(counters + 4); }
   void apply(rtmi::TileArgs& t, int item_chunks, uint2* recs, int64_t capacity) const {
@@ -499,6 +506,7 @@ struct TileSchedule {
     t.tile_begin = begin;
     t.tile_count = count;
     t.tile_fill = fill;
+    t.pair_mask = mask;
     t.rec_total = rec_total();
     t.recs = recs;
     t.rec_capacity = capacity;
@@ -509,6 +517,14 @@ struct TileSchedule {
     t.item_chunks = item_chunks > 0 ? item_chunks : kItemChunks;
   }
 };
+
+// Blocks of kPairBlock (source, patch) pairs in a launch of sources [s0, s0 + ns).
+int pair_blocks(const Problem& p, const Plan& plan, int32_t s0, int32_t ns) {
+  int64_t patches = 0;
+  for (int32_t s = s0; s < s0 + ns; ++s)
+    if (plan.nsub[s] > 0) patches += (p.nrays[s] + kPatch - 1) / kPatch;
+  return static_cast<int>((patches + rtmi::kPairBlock - 1) / rtmi::kPairBlock);
+}
 
 // Upper bound on the chunk records that sources [s0, s0 + ns) can produce. A tile lists a
 // chunk (kChunk substeps from 8c) when its substep range [ka, kb] meets the chunk, and
@@ -554,6 +570,7 @@ struct TiledLayout {
   bool interleaved = false;
   size_t corner = 0, sched = 0, med = 0, v = 0, p = 0, segtot = 0, recs = 0, total = 0;   // byte offsets / size
   size_t sched_bytes = 0;
+  int pair_blocks = 0;        // most pair blocks of any launch
   int64_t rec_capacity = 0;   // chunk records of each shared buffer (0: a plan's own slices)
   int rec_buffers = 1;        // shared buffers: two when several launches alternate
   std::vector<int> seg_len;   // per source chunk: substeps per record run (0: whole rays)
@@ -604,6 +621,7 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
     if (shared_records)
       L.rec_capacity = std::max(L.rec_capacity, record_bound(p, plan, s0, std::min(kMaxSrcPerLaunch, p.n_src - s0),
                                                              L.tiles_x, L.tiles_y, L.tiles_z));
+    L.pair_blocks = std::max(L.pair_blocks, pair_blocks(p, plan, s0, std::min(kMaxSrcPerLaunch, p.n_src - s0)));
     int64_t t = 0;
     if (len > 0)
       for (int32_t s = s0; s < std::min(p.n_src, s0 + kMaxSrcPerLaunch); ++s)
@@ -616,7 +634,7 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
   const int32_t nb_max = std::min(kMaxBinsPerLaunch, p.n_bins);
   // a shared j and a shared (scaled) kappa are gathered from one interleaved copy
   L.interleaved = p.j_stride == 0 && p.k_stride == 0;
-  L.sched_bytes = TileSchedule::bytes(L.tiles);
+  L.sched_bytes = TileSchedule::bytes(L.tiles, L.pair_blocks);
   L.corner = 0;
   L.sched = 2 * kCornerBytes;
   L.med = L.sched + L.sched_bytes * (sched_per_launch ? L.n_launch : 1);
@@ -789,7 +807,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       t.tiles_y = L.tiles_y;
       t.tiles_z = L.tiles_z;
       TileSchedule sched;
-      sched.carve(ws + L.sched + launch * L.sched_bytes, L.tiles);
+      sched.carve(ws + L.sched + launch * L.sched_bytes, L.tiles, L.pair_blocks);
       if (slices && launch < static_cast<int>(slices->off.size()))
         sched.apply(t, plan.item_chunks, slices->base + slices->off[launch], slices->count[launch]);
       else   // launches alternate between the shared buffers
@@ -1020,18 +1038,21 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
   const int tiles_x = (p.nx + kTile - 1) / kTile, tiles_y = (p.ny + kTile - 1) / kTile,
             tiles_z = (p.nz + kTile - 1) / kTile;
   const int tiles = tiles_x * tiles_y * tiles_z;
-  const size_t sched_bytes = TileSchedule::bytes(tiles);
   int64_t rec_capacity = 0;
-  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch)
+  int max_blocks = 0;
+  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
     rec_capacity = std::max(rec_capacity, record_bound(p, plan, s0, std::min(kMaxSrcPerLaunch, p.n_src - s0),
                                                        tiles_x, tiles_y, tiles_z));
+    max_blocks = std::max(max_blocks, pair_blocks(p, plan, s0, std::min(kMaxSrcPerLaunch, p.n_src - s0)));
+  }
+  const size_t sched_bytes = TileSchedule::bytes(tiles, max_blocks);
   const size_t rec_off = corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes) + sched_bytes;
   Scratch scratch;
   if (int32_t rc = acquire_scratch(rec_off + size_t(rec_capacity) * sizeof(uint2), st, kSlotAdjoint, &scratch))
     return rc;
   char* ws = scratch.ptr;
   TileSchedule sched;
-  sched.carve(ws + corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes), tiles);
+  sched.carve(ws + corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes), tiles, max_blocks);
   uint2* recs = reinterpret_cast<uint2*>(ws + rec_off);
   float* corner = reinterpret_cast<float*>(ws);  // [0..7] for dL/dj, [8..15] for dL/dkappa
   float4* med = reinterpret_cast<float4*>(ws + corner_bytes);
@@ -1223,7 +1244,7 @@ int32_t plan_create(const Problem& given, rtmi_plan** out) {
   int64_t rec_sum = 0;
   for (int i = 0; i < L.n_launch; ++i) {
     TileSchedule sched;
-    sched.carve(P->ws + L.sched + size_t(i) * L.sched_bytes, L.tiles);
+    sched.carve(P->ws + L.sched + size_t(i) * L.sched_bytes, L.tiles, L.pair_blocks);
     long long n = 0;
     if ((e = hipMemcpy(&n, sched.rec_total(), sizeof n, hipMemcpyDeviceToHost)) != hipSuccess)
       return hip_fail(e, "plan record count");

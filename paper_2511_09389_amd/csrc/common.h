@@ -13,6 +13,7 @@ constexpr int kPatch = 64;           // rays per coherent patch (one wavefront)
 constexpr int kTile = 16;            // output tile edge, voxels
 constexpr int kTileVox = kTile * kTile * kTile;
 constexpr int kTileThreads = 512;    // lanes per tile work-group
+constexpr int kPairBlock = 128;      // (source, patch) pairs per work-group of the tile geometry passes
 constexpr int kChunk = 8;            // consecutive substeps one tile lane sums in registers
 constexpr int kSeg = 4;              // substeps per recomputed segment of the adjoint sweep
 // Per-patch record of the direction table: min x, y, z, max x, y, z, -, -, cone axis
@@ -101,6 +102,7 @@ struct TileArgs {
   long long* tile_begin;          // [tiles] first chunk record of the tile
   long long* tile_count;          // [tiles] its records (clipped to rec_capacity)
   long long* tile_fill;           // [tiles] fill cursor: records below it are written
+  unsigned* pair_mask;            // [tiles][pair blocks][kPairBlock / 32]: pairs with chunks in the tile
   long long* rec_total;           // chunk records of all tiles (before clipping)
   uint2* recs;                    // chunk records, grouped by tile
   long long rec_capacity;

@@ -712,9 +712,10 @@ __global__ void __launch_bounds__(kScheduleThreads) tile_schedule_kernel(const T
   schedule_tiles<kScheduleThreads>(a, n_tiles, sh);
 }
 
-// Per (tile, block of kCostPairs pairs): the pairs that can reach the tile, then, one
+// Per (tile, block of kPairBlock pairs): the pairs that can reach the tile, then, one
 // wave per pair, the substep range of each of its rays. FILL = false: the chunks are
-// summed into tile_cost[t] (zeroed beforehand). FILL = true: a wave reserves the chunks
+// summed into tile_cost[t] (zeroed beforehand), and the pairs with chunks are marked in
+// pair_mask. FILL = true takes only the marked pairs (no cull, no pair without chunks). FILL = true: a wave reserves the chunks
 // of the four pairs it holds with one atomic add at the tile's fill cursor and writes one
 // record per chunk,
 //   x = source << kRecRayBits | ray,
@@ -724,7 +725,6 @@ __global__ void __launch_bounds__(kScheduleThreads) tile_schedule_kernel(const T
 // below the cursor. Blocks hold a modest number of pairs because next to a source every
 // pair of a block reaches the tile and each needs its rays' ranges.
 constexpr int kCostThreads = 256;
-constexpr int kCostPairs = 128;
 constexpr int kRecRayBits = 24;   // rays per source < 2^24
 
 __device__ __forceinline__ long long shfl_ll(long long v, int src) {
@@ -737,9 +737,11 @@ __device__ __forceinline__ long long shfl_ll(long long v, int src) {
 template <bool FILL>
 __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs a) {
   __shared__ SrcTable S;
-  __shared__ int list[kCostPairs];
+  __shared__ int list[kPairBlock];
   __shared__ int count;
   __shared__ unsigned long long total;
+  constexpr int kMaskWords = kPairBlock / 32;
+  __shared__ unsigned mask[kMaskWords];   // pairs of the block with chunks in the tile
   const int tid = static_cast<int>(threadIdx.x), wave = tid >> 6, lane = tid & 63;
   load_sources(a, S, tid);
   if (tid == 0) {
@@ -749,7 +751,7 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
   const int t = static_cast<int>(blockIdx.x);
   const TileGeom g = tile_geom(a, t);
   const int npairs = a.pbegin[a.n_src];
-  const int nblocks = (npairs + kCostPairs - 1) / kCostPairs;
+  const int nblocks = (npairs + kPairBlock - 1) / kPairBlock;
   long long rec_end = 0;   // records of this tile end here (FILL)
   if constexpr (FILL) {
     rec_end = a.tile_begin[t] + a.tile_count[t];
@@ -760,11 +762,17 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
   for (int q0 = static_cast<int>(blockIdx.y); q0 < nblocks; q0 += static_cast<int>(gridDim.y)) {
     __syncthreads();
     if (tid == 0) count = 0;
+    if (tid < kMaskWords) mask[tid] = 0u;
     __syncthreads();
-    const int p = q0 * kCostPairs + tid;
-    if (tid < kCostPairs && p < npairs) {
-      const int s = pair_source(S, a.n_src, p);
-      if (pair_reaches(a, S, g, s, p - S.pbegin[s])) list[atomicAdd(&count, 1)] = p;
+    unsigned* const block_mask = a.pair_mask + (static_cast<long long>(t) * nblocks + q0) * kMaskWords;
+    const int p = q0 * kPairBlock + tid;
+    if (tid < kPairBlock && p < npairs) {
+      if constexpr (FILL) {   // only the pairs the count pass found chunks for
+        if ((block_mask[tid >> 5] >> (tid & 31)) & 1u) list[atomicAdd(&count, 1)] = p;
+      } else {
+        const int s = pair_source(S, a.n_src, p);
+        if (pair_reaches(a, S, g, s, p - S.pbegin[s])) list[atomicAdd(&count, 1)] = p;
+      }
     }
     __syncthreads();
     // A tile next to a source keeps every pair of the block: each wave then takes many
@@ -794,6 +802,11 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
 #pragma unroll
           for (int off = 32; off > 0; off >>= 1) cu += __shfl_xor(cu, off, 64);
           sum += static_cast<unsigned long long>(cu);
+          const int i = i0 + u * kWavesC;
+          if (lane == 0 && cu > 0) {
+            const int bit = list[i] - q0 * kPairBlock;
+            atomicOr(&mask[bit >> 5], 1u << (bit & 31));
+          }
         }
       } else {
         // offsets of each lane's chunks within the wave's kUnroll pairs, then one
@@ -830,6 +843,10 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
           }
         }
       }
+    }
+    if constexpr (!FILL) {
+      __syncthreads();
+      if (tid < kMaskWords) block_mask[tid] = mask[tid];
     }
   }
   if constexpr (!FILL) {
@@ -1063,7 +1080,7 @@ hipError_t launch_tile_one_bin(const TileArgs& a, bool det, bool nearest, hipStr
 }
 
 dim3 pairs_grid(const TileArgs& a, int tiles) {
-  const int nblocks = (a.pbegin[a.n_src] + kCostPairs - 1) / kCostPairs;
+  const int nblocks = (a.pbegin[a.n_src] + kPairBlock - 1) / kPairBlock;
   return dim3(tiles, nblocks < 65535 ? nblocks : 65535);
 }
 
