@@ -93,8 +93,8 @@ typedef struct rtmi_options {
  *    for step_size <= 0.9, two such buffers when the sources or bins need several
  *    launches), taken from a stream-ordered pool the library owns per device. The
  *    library keeps one such workspace per (device, stream) and reuses it for the next
- *    call on that stream, growing it when a call needs more; it is held until the process
- *    ends (one per stream the caller uses). During graph capture a call takes its own
+ *    call on that stream, growing it when a call needs more; it is held until
+ *    rtmi_release_workspaces or the process ends. During graph capture a call takes its own
  *    stream-ordered allocation instead, which the graph owns. The tile schedules and records, which
  *    depend on the geometry only, are computed on a library-owned stream of the same
  *    device, ordered by events after the caller's earlier work on `stream` and before
@@ -131,6 +131,14 @@ int32_t rtmi_prepare(int32_t num_rays);
  * each stream and those made during graph capture, are then served from memory the pool
  * already holds). */
 int32_t rtmi_reserve(int64_t bytes);
+
+/* Free the workspaces that stateless calls keep per stream on the current device (see
+ * RTMI_PATH_TILED), after waiting for all work on the device. Call it to return that
+ * memory, and before a stream that still had calls pending is destroyed if a stream
+ * created later might receive the same handle (a cached workspace is keyed by the
+ * handle; reusing it from a new stream while the old stream's work still runs would
+ * race). Returns RTMI_OK or RTMI_ERR_HIP. */
+int32_t rtmi_release_workspaces(void);
 
 /* The single-source kernel of Sec. 2: advance the field over one dt for one source.
  * Arguments mirror the paper's (j_map, kappa_map, source_pos, num_rays, step_size,

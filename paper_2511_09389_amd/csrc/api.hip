@@ -1331,6 +1331,29 @@ int32_t rtmi_reserve(int64_t bytes) {
   return RTMI_OK;
 }
 
+int32_t rtmi_release_workspaces(void) {
+  int dev = 0;
+  if (int32_t st = current_device(&dev)) return st;
+  hipError_t e = hipDeviceSynchronize();   // every call that used the blocks has finished
+  if (e != hipSuccess) return hip_fail(e, "rtmi_release_workspaces");
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    for (auto it = g_scratch.begin(); it != g_scratch.end();) {
+      if (std::get<0>(it->first) != dev) {
+        ++it;
+        continue;
+      }
+      // (the caller's stream may no longer exist: free on the null stream, now idle)
+      if (it->second.first && (e = hipFreeAsync(it->second.first, nullptr)) != hipSuccess)
+        return hip_fail(e, "rtmi_release_workspaces");
+      it = g_scratch.erase(it);
+    }
+  }
+  if ((e = hipStreamSynchronize(nullptr)) != hipSuccess) return hip_fail(e, "rtmi_release_workspaces");
+  g_error.clear();
+  return RTMI_OK;
+}
+
 int32_t rtmi_trace_single(const float* j_map, const float* kappa_map, int32_t nx, int32_t ny,
                           int32_t nz, const float* source_pos, int32_t num_rays,
                           float step_size, float radiation_velocity, float time_step,

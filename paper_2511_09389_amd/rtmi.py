@@ -56,6 +56,7 @@ def _load():
         "rtmi_fibonacci_directions": (I32, [I32, P]),
         "rtmi_prepare": (I32, [I32]),
         "rtmi_reserve": (I32, [I64]),
+        "rtmi_release_workspaces": (I32, []),
         "rtmi_trace_single": (I32, [P, P, I32, I32, I32, P, I32, F32, F32, F32, P, P]),
         "rtmi_trace_multi": (I32, [P, P, I32, I32, I32, I32, P, P, P, F32, F32, F32, P, P]),
         "rtmi_trace_bins": (I32, [P, I64, P, I64, P, I32, I32, I32, I32, I32, P, P, P, F32, F32,
@@ -141,6 +142,12 @@ def reserve(nbytes, device=None):
     """Grow the device's workspace pool to at least nbytes (tiled path)."""
     with torch.cuda.device(device if device is not None else torch.cuda.current_device()):
         _check(lib.rtmi_reserve(int(nbytes)))
+
+
+def release_workspaces(device=None):
+    """Wait for the device, then free the workspaces stateless calls keep per stream."""
+    with torch.cuda.device(device if device is not None else torch.cuda.current_device()):
+        _check(lib.rtmi_release_workspaces())
 
 
 def _new_field(shape, like):
