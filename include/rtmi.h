@@ -94,7 +94,9 @@ typedef struct rtmi_options {
  *    launches), taken from a stream-ordered pool the library owns per device. The
  *    library keeps one such workspace per (device, stream) and reuses it for the next
  *    call on that stream, growing it when a call needs more; it is held until
- *    rtmi_release_workspaces or the process ends. During graph capture a call takes its own
+ *    rtmi_release_workspaces or the process ends. Host threads that call on one stream
+ *    must take turns (one call at a time per stream), as they must for any stream-ordered
+ *    work that shares memory. During graph capture a call takes its own
  *    stream-ordered allocation instead, which the graph owns. The tile schedules and records, which
  *    depend on the geometry only, are computed on a library-owned stream of the same
  *    device, ordered by events after the caller's earlier work on `stream` and before
