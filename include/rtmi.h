@@ -61,7 +61,10 @@ enum {
    * device from max|j| and the worst-case sum) and added with integer atomics, so the
    * field is bitwise reproducible from run to run and does not depend on the order of
    * the sources or on scheduling. (Short per-lane partial sums are formed in a fixed
-   * order set by the build before rounding.) Assumes kappa >= 0. */
+   * order set by the build before rounding.) The worst-case sum uses each source's ray
+   * weight times its N_Omega; negative kappa values in the maps widen it by
+   * exp(N_s ds max(-kappa)), so the integers cannot wrap. A negative kappa_scale is
+   * refused in this mode (RTMI_ERR_INVALID_ARG). */
   RTMI_ACCUM_DETERMINISTIC = 1
 };
 
@@ -300,6 +303,15 @@ int32_t rtmi_trace_vjp(const float* j_map, const float* kappa_map,
                        const int32_t* substep_cap, float step_size,
                        float radiation_velocity, float time_step, const float* grad_field,
                        float* grad_j, float* grad_kappa, void* stream);
+
+/* Squared field error of the inverse problem (Sec. 4, "Gradient-based inversion": a
+ * loss on the traced field, minimised through the tracer's gradient): *loss =
+ * scale * sum_i (field[i] - target[i])^2 (DEVICE float[1], overwritten) and grad[i] =
+ * 2 scale (field[i] - target[i]) = dL/dfield (DEVICE float[count], overwritten; it may
+ * be passed as grad_field to rtmi_trace_vjp). field, target: DEVICE float[count]. With
+ * scale = 1 / count this is the mean squared error. */
+int32_t rtmi_field_mse(const float* field, const float* target, int64_t count, float scale,
+                       float* grad, float* loss, void* stream);
 
 /* Per-ray intensities of one source (a check of Eq. (2) on the device): writes
  * I_{k+1} for ray i (lattice order) and substep k to out_rays[i * n_s + k] (DEVICE

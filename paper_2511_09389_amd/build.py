@@ -11,6 +11,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "librtmi.so")
 SOURCES = ["api.hip", "march.hip", "tiled.hip", "adjoint.hip", "conv.hip"]
+HOST_FEATURE_NOTE = "'-packed-fp32-ops' is not a recognized feature for this target"
 
 
 def hipcc():
@@ -32,7 +33,16 @@ def build(verbose=False):
            "-I", INCLUDE, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
     if verbose:
         print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True, cwd=PKG)
+    res = subprocess.run(cmd, cwd=PKG, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    # The feature flag above must reach the device pass, and hipcc forwards it to the host
+    # pass too (-Xarch_device does not take options with arguments), whose x86 backend
+    # prints one harmless "not a recognized feature" line per source file. Those lines are
+    # dropped; everything else the compiler prints is passed on.
+    lines = [ln for ln in res.stdout.splitlines() if HOST_FEATURE_NOTE not in ln]
+    if lines:
+        print("\n".join(lines), file=sys.stderr, flush=True)
+    if res.returncode != 0:
+        raise subprocess.CalledProcessError(res.returncode, cmd, output=res.stdout)
     os.replace(tmp, LIB)
     return LIB
 

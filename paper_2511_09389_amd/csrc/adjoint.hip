@@ -175,7 +175,37 @@ __global__ void __launch_bounds__(kBlock) adjoint_record_kernel(const AdjointArg
   }
 }
 
+// Mean-squared field error of the inverse problem and its gradient: loss[0] +=
+// scale * sum (J - T)^2 (the caller's loss word is zeroed first), grad = 2 scale (J - T).
+__global__ void field_mse_kernel(const float* __restrict__ field, const float* __restrict__ target,
+                                 long long n, float scale, float* __restrict__ grad, float* __restrict__ loss) {
+  float part = 0.0f;
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x) {
+    const float d = field[i] - target[i];
+    part += d * d;
+    grad[i] = 2.0f * scale * d;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off, 64);
+  if ((threadIdx.x & 63) == 0 && part != 0.0f) unsafeAtomicAdd(loss, part * scale);
+}
+
+__global__ void zero_word_kernel(float* p) {
+  if (threadIdx.x == 0) *p = 0.0f;
+}
+
 }  // namespace
+
+hipError_t launch_field_mse(const float* field, const float* target, long long n, float scale, float* grad,
+                            float* loss, hipStream_t s) {
+  long long blocks = (n + 1023) / 1024;
+  blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
+  hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(64), 0, s, loss);
+  hipLaunchKernelGGL(field_mse_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, field, target, n,
+                     scale, grad, loss);
+  return hipGetLastError();
+}
 
 hipError_t launch_adjoint_record(const AdjointArgs& a, int blocks, hipStream_t s) {
   const dim3 grid((blocks + kXcds - 1) / kXcds * kXcds), block(kBlock);

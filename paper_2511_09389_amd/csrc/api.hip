@@ -406,6 +406,8 @@ struct Plan {
   std::vector<int32_t> nsub;
   std::vector<DevTable> tables;
   double bound_per_unit_j = 0.0;
+  double det_growth = 0.0;   // N_s ds, largest over sources
+  double kscale_max = 1.0;   // largest |kappa_scale| (1 without scales)
   int64_t cells = 0;
 };
 
@@ -424,14 +426,21 @@ int32_t validate(const Problem& p, Plan* plan, bool maps_given = true) {
                        (p.k_stride != 0 && p.k_stride < plan->cells)))
     return fail(RTMI_ERR_INVALID_ARG, "a non-zero bin stride must be >= nx*ny*nz");
   if (p.kscale)
-    for (int32_t b = 0; b < p.n_bins; ++b)
+    for (int32_t b = 0; b < p.n_bins; ++b) {
       if (!std::isfinite(p.kscale[b])) return fail(RTMI_ERR_NONFINITE, "kappa_scale[%d] is not finite", b);
+      plan->kscale_max = std::max(plan->kscale_max, std::fabs(double(p.kscale[b])));
+    }
   if (p.opts) {
     if (p.opts->accum_mode != RTMI_ACCUM_ATOMIC && p.opts->accum_mode != RTMI_ACCUM_DETERMINISTIC)
       return fail(RTMI_ERR_INVALID_ARG, "unknown accum_mode %d", p.opts->accum_mode);
     if (p.opts->path != RTMI_PATH_TILED && p.opts->path != RTMI_PATH_DIRECT)
       return fail(RTMI_ERR_INVALID_ARG, "unknown path %d", p.opts->path);
     plan->det = p.opts->accum_mode == RTMI_ACCUM_DETERMINISTIC;
+    if (plan->det && p.kscale)
+      for (int32_t b = 0; b < p.n_bins; ++b)
+        if (p.kscale[b] < 0.0f)
+          return fail(RTMI_ERR_INVALID_ARG, "the deterministic mode needs kappa_scale >= 0 (bin %d: %g)", b,
+                      double(p.kscale[b]));
     plan->tiled = p.opts->path == RTMI_PATH_TILED;
     plan->explicit_dirs = p.opts->directions != nullptr;
     if (p.opts->tile_item_chunks < 0 || p.opts->tile_item_chunks > (1 << 20))
@@ -454,8 +463,12 @@ int32_t validate(const Problem& p, Plan* plan, bool maps_given = true) {
     if (n < 0) return fail(RTMI_ERR_RANGE, "N_s = ceil(c dt / ds) exceeds 2^24");
     plan->nsub[s] = static_cast<int32_t>(n);
     // I <= N_s ds max|j| (exp factors <= 1 for kappa >= 0); each ray deposits at most
-    // N_s times into one voxel with weight <= 1, times 4 pi / N_Omega, over N_Omega rays.
-    plan->bound_per_unit_j += kFourPi * double(n) * double(n) * double(p.ds);
+    // N_s times into one voxel with weight <= 1, times its ray weight, over N_Omega rays.
+    // (A negative kappa multiplies this by at most exp(N_s ds max(-kappa)): det_growth.)
+    const double wray = (plan->explicit_dirs && p.opts->ray_weight > 0.0f) ? double(p.opts->ray_weight)
+                                                                           : kFourPi / p.nrays[s];
+    plan->bound_per_unit_j += wray * double(p.nrays[s]) * double(n) * double(n) * double(p.ds);
+    plan->det_growth = std::max(plan->det_growth, double(n) * double(p.ds));
   }
   if (plan->explicit_dirs)
     for (int64_t i = 0; i < int64_t(p.nrays[0]) * 3; ++i)
@@ -467,6 +480,15 @@ float ray_weight(const Problem& p, const Plan& plan, int32_t s) {
   const double w = (plan.explicit_dirs && p.opts->ray_weight > 0.0f) ? double(p.opts->ray_weight)
                                                                      : kFourPi / p.nrays[s];
   return static_cast<float>(w);
+}
+
+// Fixed-point scale of the deterministic mode, on the device: from max|j| over the bins'
+// j and max(0, -kappa) over their kappa (which widens the bound by exp(N_s ds |kappa|)).
+hipError_t det_scale_launch(const Problem& p, const Plan& plan, double* det_scale) {
+  const int64_t j_count = p.j_stride ? p.j_stride * (p.n_bins - 1) + plan.cells : plan.cells;
+  const int64_t k_count = p.k_stride ? p.k_stride * (p.n_bins - 1) + plan.cells : plan.cells;
+  return rtmi::launch_det_scale(p.j, j_count, p.kap, k_count, plan.kscale_max * plan.det_growth,
+                                plan.bound_per_unit_j, det_scale, p.stream);
 }
 
 size_t align256(size_t n) { return (n + 255) / 256 * 256; }
@@ -991,9 +1013,7 @@ int32_t run(const Problem& p) {
     det_scale = reinterpret_cast<double*>(out_q + total);
     if (!plan.tiled && (e = rtmi::launch_fill_zero_u64(out_q, total, st)) != hipSuccess)
       return hip_fail(e, "fill");
-    const int64_t j_count = p.j_stride ? p.j_stride * (p.n_bins - 1) + plan.cells : plan.cells;
-    if ((e = rtmi::launch_det_scale(p.j, j_count, plan.bound_per_unit_j, det_scale, st)) != hipSuccess)
-      return hip_fail(e, "det_scale");
+    if ((e = det_scale_launch(p, plan, det_scale)) != hipSuccess) return hip_fail(e, "det_scale");
   }
 
   const int32_t rc = plan.tiled ? run_tiled(p, plan, out_q, det_scale) : run_direct(p, plan, out_q, det_scale);
@@ -1279,9 +1299,7 @@ int32_t plan_execute(const rtmi_plan* P, const float* j, const float* kap, float
   hipError_t e;
   const int64_t total = P->plan.cells * p.n_bins;
   if (P->plan.det) {
-    const int64_t j_count = p.j_stride ? p.j_stride * (p.n_bins - 1) + P->plan.cells : P->plan.cells;
-    if ((e = rtmi::launch_det_scale(p.j, j_count, P->plan.bound_per_unit_j, P->det_scale, st)) != hipSuccess)
-      return hip_fail(e, "det_scale");
+    if ((e = det_scale_launch(p, P->plan, P->det_scale)) != hipSuccess) return hip_fail(e, "det_scale");
   }
   if (int32_t rc = run_tiled(p, P->plan, P->out_q, P->det_scale, TiledMode::kReplay, P->ws, &P->recs)) return rc;
   if (P->plan.det && (e = rtmi::launch_det_convert(P->out_q, P->det_scale, p.out, total, st)) != hipSuccess)
@@ -1398,6 +1416,18 @@ int32_t rtmi_trace_vjp(const float* j_map, const float* kappa_map, int32_t nx, i
                   substep_cap, step_size, radiation_velocity, time_step, grad_j, nullptr,
                   static_cast<hipStream_t>(stream)};
   return run_vjp(p, grad_field, grad_j, grad_kappa);
+}
+
+int32_t rtmi_field_mse(const float* field, const float* target, int64_t count, float scale,
+                       float* grad, float* loss, void* stream) {
+  if (!field || !target || !grad || !loss) return fail(RTMI_ERR_INVALID_ARG, "null pointer");
+  if (count < 1) return fail(RTMI_ERR_INVALID_ARG, "count must be >= 1");
+  if (!std::isfinite(scale)) return fail(RTMI_ERR_NONFINITE, "scale is not finite");
+  const hipError_t e = rtmi::launch_field_mse(field, target, count, scale, grad, loss,
+                                              static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "field_mse launch");
+  g_error.clear();
+  return RTMI_OK;
 }
 
 int32_t rtmi_debug_rays(const float* j_map, const float* kappa_map, int32_t nx, int32_t ny,

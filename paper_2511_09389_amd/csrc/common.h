@@ -213,13 +213,20 @@ hipError_t launch_tile_fill(const TileArgs& a, int tiles, hipStream_t s);
 hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool deterministic, bool nearest,
                            hipStream_t s);
 hipError_t launch_adjoint_record(const AdjointArgs& a, int n_blocks, hipStream_t s);
+// loss[0] = scale * sum (field - target)^2 (overwritten), grad = 2 scale (field - target).
+hipError_t launch_field_mse(const float* field, const float* target, long long n, float scale, float* grad,
+                            float* loss, hipStream_t s);
 // Gather table of j and kappa (64 bytes per voxel) for the record and adjoint kernels.
 hipError_t launch_cell_table(const float* j, const float* kap, float4* table, int nx, int ny, int nz,
                              hipStream_t s);
 hipError_t launch_fill_zero(float* p, long long n, hipStream_t s);
 hipError_t launch_fill_zero_u64(unsigned long long* p, long long n, hipStream_t s);
-hipError_t launch_det_scale(const float* j, long long j_count, double bound_per_unit_j,
-                            double* scale_out, hipStream_t s);
+// scale_out[0] = the fixed-point scale, a power of two with bound * scale <= 2^62, where
+// bound = max|j| * bound_per_unit_j * exp(growth_per_neg_kappa * max(0, -min kappa));
+// scale_out[1] is scratch.
+hipError_t launch_det_scale(const float* j, long long j_count, const float* kap, long long k_count,
+                            double growth_per_neg_kappa, double bound_per_unit_j, double* scale_out,
+                            hipStream_t s);
 hipError_t launch_det_convert(const unsigned long long* acc, const double* scale, float* out,
                               long long n, hipStream_t s);
 

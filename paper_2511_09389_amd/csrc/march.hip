@@ -270,10 +270,30 @@ __global__ void absmax_kernel(const float* j, long long n, unsigned int* out_bit
   if (threadIdx.x == 0) atomicMax(out_bits, red[0]);
 }
 
+// max(0, -kappa) as the bit pattern of a non-negative float.
+__global__ void negmax_kernel(const float* k, long long n, unsigned int* out_bits) {
+  __shared__ unsigned int red[kBlock];
+  unsigned int m = 0u;
+  const long long stride = static_cast<long long>(gridDim.x) * blockDim.x;
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
+       i += stride)
+    m = max(m, __float_as_uint(fmaxf(0.0f, -k[i])));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = kBlock / 2; w > 0; w >>= 1) {
+    if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] = max(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out_bits, red[0]);
+}
+
 // scale = largest power of two with bound * scale <= 2^62 (1 when the bound is 0 or not finite).
-__global__ void det_scale_kernel(const unsigned int* max_bits, double bound_per_unit_j,
-                                 double* scale) {
-  const double bound = static_cast<double>(__uint_as_float(*max_bits)) * bound_per_unit_j;
+// bits[0]: max |j|; bits[1]: max(0, -kappa).
+__global__ void det_scale_kernel(const unsigned int* bits, double growth_per_neg_kappa,
+                                 double bound_per_unit_j, double* scale) {
+  const double neg = static_cast<double>(__uint_as_float(bits[1]));
+  const double growth = neg > 0.0 ? exp(fmin(700.0, neg * growth_per_neg_kappa)) : 1.0;
+  const double bound = static_cast<double>(__uint_as_float(bits[0])) * bound_per_unit_j * growth;
   double sc = 1.0;
   if (bound > 0.0 && isfinite(bound)) sc = exp2(floor(62.0 - log2(bound)));
   *scale = sc;
@@ -337,16 +357,19 @@ hipError_t launch_fill_zero_u64(unsigned long long* p, long long n, hipStream_t 
   return hipGetLastError();
 }
 
-hipError_t launch_det_scale(const float* j, long long j_count, double bound_per_unit_j,
-                            double* scale_out, hipStream_t s) {
-  // scale_out[0] receives the scale; the word after it holds the max-|j| bits.
+hipError_t launch_det_scale(const float* j, long long j_count, const float* kap, long long k_count,
+                            double growth_per_neg_kappa, double bound_per_unit_j, double* scale_out,
+                            hipStream_t s) {
+  // scale_out[0] receives the scale; the word after it holds the max-|j| and max(0, -kappa) bits.
   unsigned int* bits = reinterpret_cast<unsigned int*>(scale_out + 1);
   hipLaunchKernelGGL(fill_zero_u64_kernel, dim3(1), dim3(kBlock), 0, s,
                      reinterpret_cast<unsigned long long*>(bits), 1ll);
   hipLaunchKernelGGL(absmax_kernel, dim3(fill_blocks(j_count)), dim3(kBlock), 0, s, j, j_count,
                      bits);
-  hipLaunchKernelGGL(det_scale_kernel, dim3(1), dim3(1), 0, s, bits, bound_per_unit_j,
-                     scale_out);
+  hipLaunchKernelGGL(negmax_kernel, dim3(fill_blocks(k_count)), dim3(kBlock), 0, s, kap, k_count,
+                     bits + 1);
+  hipLaunchKernelGGL(det_scale_kernel, dim3(1), dim3(1), 0, s, bits, growth_per_neg_kappa,
+                     bound_per_unit_j, scale_out);
   return hipGetLastError();
 }
 

@@ -61,6 +61,7 @@ def _load():
         "rtmi_trace_multi": (I32, [P, P, I32, I32, I32, I32, P, P, P, F32, F32, F32, P, P]),
         "rtmi_trace_bins": (I32, [P, I64, P, I64, P, I32, I32, I32, I32, I32, P, P, P, F32, F32,
                                   F32, P, ctypes.POINTER(Options), P]),
+        "rtmi_field_mse": (I32, [P, P, I64, F32, P, P, P]),
         "rtmi_debug_rays": (I32, [P, P, I32, I32, I32, P, I32, F32, F32, F32, I32, P, P, P]),
         "rtmi_trace_vjp": (I32, [P, P, I32, I32, I32, I32, P, P, P, F32, F32, F32, P, P, P, P]),
         "rtmi_plan_create": (I32, [I32, I32, I32, I32, P, P, P, I32, I64, I64, P, F32, F32, F32,
@@ -103,6 +104,16 @@ def _dev(t, name, ndim=None):
     if ndim is not None and t.dim() not in ((ndim,) if isinstance(ndim, int) else ndim):
         raise ValueError(f"{name} has {t.dim()} dims, expected {ndim}")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _same(t, name, shape, device):
+    """A caller-supplied buffer must have exactly the shape the call reads or writes, on
+    the call's device: the library trusts its sizes, so a short buffer would be overrun."""
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    return t
 
 
 def _stream(device):
@@ -160,7 +171,8 @@ def trace_single(j_map, kappa_map, source_pos, num_rays, step_size, radiation_ve
     if tuple(kappa_map.shape) != tuple(j_map.shape):
         raise ValueError("j_map and kappa_map must have the same shape")
     nx, ny, nz = j_map.shape
-    out = _new_field(j_map.shape, j_map) if out is None else out
+    _same(kappa_map, "kappa_map", j_map.shape, j_map.device)
+    out = _new_field(j_map.shape, j_map) if out is None else _same(out, "out", j_map.shape, j_map.device)
     src = _host_f32(source_pos).reshape(3)
     with torch.cuda.device(j_map.device):
         _check(lib.rtmi_trace_single(_dev(j_map, "j_map", 3), _dev(kappa_map, "kappa_map", 3),
@@ -187,7 +199,8 @@ def trace_multi(j_map, kappa_map, source_pos, num_rays, step_size, radiation_vel
         raise ValueError("j_map and kappa_map must have the same shape")
     nx, ny, nz = j_map.shape
     src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
-    out = _new_field(j_map.shape, j_map) if out is None else out
+    _same(kappa_map, "kappa_map", j_map.shape, j_map.device)
+    out = _new_field(j_map.shape, j_map) if out is None else _same(out, "out", j_map.shape, j_map.device)
     with torch.cuda.device(j_map.device):
         _check(lib.rtmi_trace_multi(_dev(j_map, "j_map", 3), _dev(kappa_map, "kappa_map", 3),
                                     nx, ny, nz, src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
@@ -223,7 +236,10 @@ def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_ve
     if scale is not None and scale.size != n_bins:
         raise ValueError("kappa_scale must have one entry per bin")
     src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
-    out = _new_field((n_bins,) + grid, j_maps) if out is None else out
+    if kappa_maps.device != j_maps.device:
+        raise ValueError("j_maps and kappa_maps must be on one device")
+    out = _new_field((n_bins,) + grid, j_maps) if out is None else \
+        _same(out, "out", (n_bins,) + grid, j_maps.device)
     opts = Options(ACCUM_DETERMINISTIC if deterministic else ACCUM_ATOMIC, None, float(ray_weight),
                    int(path), int(tile_item_chunks))
     dirs = None
@@ -323,8 +339,11 @@ def trace_vjp(j_map, kappa_map, source_pos, num_rays, step_size, radiation_veloc
         raise ValueError("j_map, kappa_map and grad_field must have the same shape")
     nx, ny, nz = j_map.shape
     src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
-    grad_j = _new_field(j_map.shape, j_map) if grad_j is None else grad_j
-    grad_kappa = _new_field(j_map.shape, j_map) if grad_kappa is None else grad_kappa
+    for t, name in ((kappa_map, "kappa_map"), (grad_field, "grad_field")):
+        _same(t, name, j_map.shape, j_map.device)
+    grad_j = _new_field(j_map.shape, j_map) if grad_j is None else _same(grad_j, "grad_j", j_map.shape, j_map.device)
+    grad_kappa = _new_field(j_map.shape, j_map) if grad_kappa is None else \
+        _same(grad_kappa, "grad_kappa", j_map.shape, j_map.device)
     with torch.cuda.device(j_map.device):
         _check(lib.rtmi_trace_vjp(_dev(j_map, "j_map", 3), _dev(kappa_map, "kappa_map", 3),
                                   nx, ny, nz, src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
@@ -336,10 +355,25 @@ def trace_vjp(j_map, kappa_map, source_pos, num_rays, step_size, radiation_veloc
     return grad_j, grad_kappa
 
 
+def field_mse(field, target, scale=None, grad=None, loss=None):
+    """(loss, grad): loss = scale * sum (field - target)^2 written to a one-element device
+    tensor, grad = dL/dfield. scale defaults to 1 / numel (the mean squared error)."""
+    dev = field.device
+    _same(target, "target", field.shape, dev)
+    grad = torch.empty_like(field) if grad is None else _same(grad, "grad", field.shape, dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev) if loss is None else _same(loss, "loss", (1,), dev)
+    scale = 1.0 / field.numel() if scale is None else float(scale)
+    with torch.cuda.device(dev):
+        _check(lib.rtmi_field_mse(_dev(field, "field"), _dev(target, "target"), field.numel(), scale,
+                                  _dev(grad, "grad"), _dev(loss, "loss"), _stream(dev)))
+    return loss, grad
+
+
 def debug_rays(j_map, kappa_map, source_pos, num_rays, step_size, radiation_velocity,
                time_step, cap=0):
     """Per-ray I_{k+1} and tau_{k+1} of one source, lattice order: two [N][N_s] tensors."""
     nx, ny, nz = j_map.shape
+    _same(kappa_map, "kappa_map", j_map.shape, j_map.device)
     n_s = num_substeps(step_size, radiation_velocity, time_step, cap)
     rays = torch.zeros((int(num_rays), n_s), dtype=torch.float32, device=j_map.device)
     tau = torch.zeros_like(rays)
@@ -374,80 +408,120 @@ def _opt(t, name, dtype, ndim=5):
     return None if t is None else _act(t, name, dtype, ndim)
 
 
+WEIGHT_SHAPE = (27, CONV_CHANNELS, CONV_CHANNELS)
+
+
+def _optsame(t, name, shape, device):
+    return None if t is None else _same(t, name, shape, device)
+
+
 def conv3d_forward(x, w, bias=None, residual=None, gelu=False, z=None, y=None):
     """y = act(conv(x, w) + bias) + residual, bf16 channels-last; z (fp32) if given."""
     n, d, h, wd, _ = x.shape
-    y = torch.empty_like(x) if y is None else y
-    with torch.cuda.device(x.device):
+    dev = x.device
+    _same(w, "w", WEIGHT_SHAPE, dev)
+    _optsame(bias, "bias", (CONV_CHANNELS,), dev)
+    _optsame(residual, "residual", x.shape, dev)
+    _optsame(z, "z", x.shape, dev)
+    y = torch.empty_like(x) if y is None else _same(y, "y", x.shape, dev)
+    with torch.cuda.device(dev):
         _check(lib.rtmi_conv3d_forward(_act(x, "x", torch.bfloat16), _act(w, "w", torch.bfloat16, None),
                                        _opt(bias, "bias", torch.float32, None),
                                        _opt(residual, "residual", torch.bfloat16), int(bool(gelu)),
                                        n, d, h, wd, _act(y, "y", torch.bfloat16),
-                                       _opt(z, "z", torch.float32), _stream(x.device)))
+                                       _opt(z, "z", torch.float32), _stream(dev)))
     return y
 
 
 def conv3d_backward_data(dz, w, residual=None, zprev=None, dh=None, dz_prev=None):
     n, d, h, wd, _ = dz.shape
-    with torch.cuda.device(dz.device):
+    dev = dz.device
+    _same(w, "w", WEIGHT_SHAPE, dev)
+    for t, name in ((residual, "residual"), (zprev, "zprev"), (dh, "dh"), (dz_prev, "dz_prev")):
+        _optsame(t, name, dz.shape, dev)
+    with torch.cuda.device(dev):
         _check(lib.rtmi_conv3d_backward_data(_act(dz, "dz", torch.bfloat16), _act(w, "w", torch.bfloat16, None),
                                              _opt(residual, "residual", torch.float32),
                                              _opt(zprev, "zprev", torch.float32), n, d, h, wd,
                                              _opt(dh, "dh", torch.float32),
-                                             _opt(dz_prev, "dz_prev", torch.bfloat16), _stream(dz.device)))
+                                             _opt(dz_prev, "dz_prev", torch.bfloat16), _stream(dev)))
     return dh, dz_prev
 
 
 def conv3d_backward_weight(x, dz, dw, db):
     n, d, h, wd, _ = x.shape
-    with torch.cuda.device(x.device):
+    dev = x.device
+    _same(dz, "dz", x.shape, dev)
+    _same(dw, "dw", WEIGHT_SHAPE, dev)
+    _same(db, "db", (CONV_CHANNELS,), dev)
+    with torch.cuda.device(dev):
         _check(lib.rtmi_conv3d_backward_weight(_act(x, "x", torch.bfloat16), _act(dz, "dz", torch.bfloat16),
                                                n, d, h, wd, _act(dw, "dw", torch.float32, None),
-                                               _act(db, "db", torch.float32, None), _stream(x.device)))
+                                               _act(db, "db", torch.float32, None), _stream(dev)))
     return dw, db
 
 
 def mse_loss(y, target, scale, dz, loss):
     nvox = target.numel()
-    with torch.cuda.device(y.device):
+    dev = y.device
+    if y.dim() != 5 or y.numel() != nvox * CONV_CHANNELS:
+        raise ValueError(f"y must hold {CONV_CHANNELS} channels per target voxel (got {tuple(y.shape)})")
+    _same(target, "target", target.shape, dev)
+    _same(dz, "dz", y.shape, dev)
+    if loss.numel() < 1:
+        raise ValueError("loss must hold one element")
+    _same(loss, "loss", loss.shape, dev)
+    with torch.cuda.device(dev):
         _check(lib.rtmi_mse_loss(_act(y, "y", torch.bfloat16), _act(target, "target", torch.float32, None),
                                  nvox, float(scale), _act(dz, "dz", torch.bfloat16),
-                                 _act(loss, "loss", torch.float32, None), _stream(y.device)))
+                                 _act(loss, "loss", torch.float32, None), _stream(dev)))
     return loss
 
 
 def adam_step(w, m, v, g, w_bf16, lr, step, beta1=0.9, beta2=0.999, eps=1e-8):
-    with torch.cuda.device(w.device):
+    dev = w.device
+    for t, name in ((m, "m"), (v, "v"), (g, "g")):
+        _same(t, name, w.shape, dev)
+    _optsame(w_bf16, "w_bf16", w.shape, dev)
+    with torch.cuda.device(dev):
         _check(lib.rtmi_adam_step(_act(w, "w", torch.float32, None), _act(m, "m", torch.float32, None),
                                   _act(v, "v", torch.float32, None), _act(g, "g", torch.float32, None),
                                   _opt(w_bf16, "w_bf16", torch.bfloat16, None), w.numel(), float(lr),
-                                  float(beta1), float(beta2), float(eps), int(step), _stream(w.device)))
+                                  float(beta1), float(beta2), float(eps), int(step), _stream(dev)))
 
 
 def surrogate_features(j, kappa, cheap, stats, x=None, scale_sums=None):
     """(x, scale_sums): bf16 [1][d][h][w][32] network input from fp32 j, kappa and the
     cheap field (3-D), and the device sums that fix the sample's scale."""
     d, h, w = j.shape
-    x = torch.empty((1, d, h, w, CONV_CHANNELS), dtype=torch.bfloat16, device=j.device) if x is None else x
-    scale_sums = torch.empty(2, dtype=torch.float32, device=j.device) if scale_sums is None else scale_sums
+    dev = j.device
+    _same(kappa, "kappa", j.shape, dev)
+    _same(cheap, "cheap", j.shape, dev)
+    xs = (1, d, h, w, CONV_CHANNELS)
+    x = torch.empty(xs, dtype=torch.bfloat16, device=dev) if x is None else _same(x, "x", xs, dev)
+    scale_sums = torch.empty(2, dtype=torch.float32, device=dev) if scale_sums is None else \
+        _same(scale_sums, "scale_sums", (2,), dev)
     st = np.ascontiguousarray(np.asarray(stats, np.float32).reshape(6))
-    with torch.cuda.device(j.device):
+    with torch.cuda.device(dev):
         _check(lib.rtmi_surrogate_features(_dev(j, "j", 3), _dev(kappa, "kappa", 3), _dev(cheap, "cheap", 3),
                                            j.numel(), st.ctypes.data_as(ctypes.c_void_p),
                                            _act(scale_sums, "scale_sums", torch.float32, None),
-                                           _act(x, "x", torch.bfloat16), _stream(j.device)))
+                                           _act(x, "x", torch.bfloat16), _stream(dev)))
     return x, scale_sums
 
 
 def surrogate_output(y, cheap, scale_sums, field=None, check=None):
     """(field, check sums): prediction from the network output and the error-check sums."""
-    field = torch.empty_like(cheap) if field is None else field
-    check = torch.zeros(2, dtype=torch.float32, device=cheap.device) if check is None else check
-    with torch.cuda.device(cheap.device):
+    dev = cheap.device
+    _same(y, "y", (1,) + tuple(cheap.shape) + (CONV_CHANNELS,), dev)
+    _same(scale_sums, "scale_sums", (2,), dev)
+    field = torch.empty_like(cheap) if field is None else _same(field, "field", cheap.shape, dev)
+    check = torch.zeros(2, dtype=torch.float32, device=dev) if check is None else _same(check, "check", (2,), dev)
+    with torch.cuda.device(dev):
         _check(lib.rtmi_surrogate_output(_act(y, "y", torch.bfloat16), _dev(cheap, "cheap", 3), cheap.numel(),
                                          _act(scale_sums, "scale_sums", torch.float32, None),
                                          _dev(field, "field", 3), _act(check, "check", torch.float32, None),
-                                         _stream(cheap.device)))
+                                         _stream(dev)))
     return field, check
 
 

@@ -95,6 +95,29 @@ class SurrogateNet:
     def state(self):
         return {"w": [w.cpu() for w in self.w], "b": [b.cpu() for b in self.b]}
 
+    def state_dict(self):
+        """Weights, biases, both Adam moments and the step count (host tensors), enough to
+        resume training exactly where it stopped."""
+        return {"w": [w.detach().cpu() for w in self.w], "b": [b.detach().cpu() for b in self.b],
+                "m": [t.detach().cpu() for t in self.m], "v": [t.detach().cpu() for t in self.v],
+                "step": torch.tensor(self.step, dtype=torch.int64)}
+
+    def load_state_dict(self, sd):
+        def put(dst, src, name):
+            if len(dst) != len(src):
+                raise ValueError(f"checkpoint has {len(src)} {name} tensors, expected {len(dst)}")
+            for d, t in zip(dst, src):
+                if tuple(d.shape) != tuple(t.shape):
+                    raise ValueError(f"checkpoint {name} shape {tuple(t.shape)} != {tuple(d.shape)}")
+                d.copy_(t)
+        put(self.w, sd["w"], "w")
+        put(self.b, sd["b"], "b")
+        put(self.m, sd["m"], "m")
+        put(self.v, sd["v"], "v")
+        self.step = int(sd["step"])
+        for l in range(LAYERS):
+            self.wb[l].copy_(self.w[l].to(torch.bfloat16))
+
 
 def make_sample(seed, device, n=64, n_src=16, num_rays=4096, ds=0.5, c=64.0, dt=1.0):
     """(j, kappa, cheap field, full field) of one seeded turbulent sample, on the device."""
@@ -116,6 +139,18 @@ class Surrogate:
     @property
     def floor(self):
         return float(self.stats[5])
+
+    def save(self, path):
+        """Checkpoint: the network's state_dict, the input statistics and the threshold."""
+        torch.save({"net": self.net.state_dict(), "stats": torch.from_numpy(self.stats.copy()),
+                    "threshold": torch.tensor(self.threshold, dtype=torch.float64)}, path)
+
+    @classmethod
+    def load(cls, path, device):
+        sd = torch.load(path, map_location="cpu", weights_only=True)
+        net = SurrogateNet(device)
+        net.load_state_dict(sd["net"])
+        return cls(net, sd["stats"].numpy(), float(sd["threshold"]))
 
     def features(self, j, k, cheap):
         """(x, scale_sums) of one sample."""

@@ -65,8 +65,8 @@ def test_num_substeps_errors(lib):
     assert lib.rtmi_num_substeps(float("nan"), 1.0, 1.0, 0) == -3
     assert lib.rtmi_num_substeps(0.5, float("inf"), 1.0, 0) == -3
     assert lib.rtmi_num_substeps(1e-6, 1e3, 1e3, 0) == -6          # N_s > 2^24
+    assert "2^24" in lib.rtmi_last_error().decode()
     assert lib.rtmi_num_substeps(1e-6, 1e3, 1e3, 10) == 10         # the cap keeps it in range
-    assert "2^24" in lib.rtmi_last_error().decode() or True
 
 
 def _call_single(lib, j=1, k=1, n=(4, 4, 4), src=(1.0, 1.0, 1.0), rays=8, ds=0.5, c=2.0, dt=1.0, out=1):
@@ -126,3 +126,17 @@ def test_debug_rays_validation(lib):
 
 def test_version(lib):
     assert lib.rtmi_version() >= 100
+
+
+def test_deterministic_mode_refuses_negative_kappa_scale(lib):
+    """The fixed-point bound assumes non-negative bin scales; the call is refused on the
+    host (the bogus device pointers are never touched)."""
+    from paper_2511_09389_amd.rtmi import Options
+    src = (ctypes.c_float * 3)(1, 1, 1)
+    nr = (ctypes.c_int32 * 1)(8)
+    scale = (ctypes.c_float * 2)(1.0, -0.5)
+    opts = Options(1, None, 0.0, 0, 0)
+    assert lib.rtmi_trace_bins(ctypes.c_void_p(1), 0, ctypes.c_void_p(1), 0, scale, 2, 4, 4, 4, 1,
+                               src, nr, None, 0.5, 2.0, 1.0, ctypes.c_void_p(1), ctypes.byref(opts),
+                               None) == -1
+    assert "kappa_scale" in lib.rtmi_last_error().decode()
