@@ -31,5 +31,6 @@ from .march import (  # noqa: F401
     trace_single,
     trace_multi,
     trace_bins,
+    trace_voxels,
 )
 from .adjoint import trace_single_vjp, trace_multi_vjp  # noqa: F401

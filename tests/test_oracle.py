@@ -150,3 +150,28 @@ def test_paper_numbers_fixture():
     assert int(w.num_rays[0]) == t["rays_per_source"]
     # the ray-substep count the stand-in workload implies at 256 substeps
     assert t["sources"] * t["rays_per_source"] * 256 == 2_198_863_872
+
+
+def test_voxel_sampled_oracle_equals_full_oracle():
+    """oracle.trace_voxels (the march restricted to the rays that can reach a few voxels)
+    gives the full oracle's value at every interior voxel: several sources, one outside
+    the box, a substep cap, and a bin scale on kappa."""
+    rng = np.random.default_rng(1)
+    shape = (20, 17, 23)
+    j = rng.random(shape).astype(np.float32)
+    k = (0.2 * rng.random(shape)).astype(np.float32)
+    src = np.array([[5.5, 8.2, 11.0], [-3.0, 4.0, 25.0], [19.2, 0.1, 3.3]], np.float32)
+    rays, caps = [200, 64, 129], [0, 17, 0]
+    vox = np.stack(np.meshgrid(*[np.arange(1, n - 1) for n in shape], indexing="ij"), -1).reshape(-1, 3)
+    full = oracle.trace_multi(j, k, src, rays, 0.5, 20.0, 1.0, caps=caps)
+    got = oracle.march.trace_voxels(j, k, src, rays, 0.5, 20.0, 1.0, vox, caps=caps)
+    want = full[vox[:, 0], vox[:, 1], vox[:, 2]]
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.abs(want).max()
+    scale = np.float32(0.296296)
+    binned = oracle.trace_bins(j, k, [1.0, scale], src, rays, 0.5, 20.0, 1.0, caps=caps)[1]
+    sub = vox[::7]
+    got = oracle.march.trace_voxels(j, k, src, rays, 0.5, 20.0, 1.0, sub, caps=caps, kappa_scale=scale)
+    want = binned[sub[:, 0], sub[:, 1], sub[:, 2]]
+    assert np.max(np.abs(got - want)) <= 1e-13 * np.abs(want).max()
+    with pytest.raises(ValueError):
+        oracle.march.trace_voxels(j, k, src, rays, 0.5, 20.0, 1.0, [[0, 3, 3]])
