@@ -118,3 +118,36 @@ def backward(params, cache, dy):
         dx = conv3_grad_input(dz, W)
         dh = dx + dh if 0 < l < L - 1 else dx
     return grads
+
+
+def features(j, kappa, cheap, stats):
+    """Network input of one sample, FP64, as (cells, 4) plus the sample scale s.
+
+    c = max(cheap, 0) is the few-ray march; s = sqrt(mean c^2) its root-mean-square. The
+    four input channels are the standardised log opacity, the scaled emissivity, the cheap
+    field in units of s and the standardised log of the cheap field:
+        ((log max(kappa, 1e-30) - m_k) i_k,  j i_j,  c / s,  (log(c + f) - m_c) i_c)
+    with stats = (m_k, i_k, i_j, m_c, i_c, f) fixed from training data.
+    """
+    st = [float(v) for v in np.asarray(stats, np.float32)]
+    c = np.maximum(np.asarray(cheap, np.float64).ravel(), 0.0)
+    s = max(math.sqrt(np.sum(c * c) / c.size), 1e-30)
+    k = np.asarray(kappa, np.float64).ravel()
+    jj = np.asarray(j, np.float64).ravel()
+    x = np.stack([(np.log(np.maximum(k, 1e-30)) - st[0]) * st[1], jj * st[2], c / s,
+                  (np.log(c + st[5]) - st[3]) * st[4]], axis=1)
+    return x, s
+
+
+def output(y0, cheap):
+    """Prediction from the network's channel 0 and the error-check sums, FP64.
+
+    The network predicts a correction to the cheap field in units of its scale s:
+    J = max(0, c + s y0), with c = max(cheap, 0). The check sums are sum (J - c)^2 and
+    sum c^2; their square-root ratio is the prediction's relative L2 distance from c.
+    Returns (J, (sum (J - c)^2, sum c^2)).
+    """
+    c = np.maximum(np.asarray(cheap, np.float64).ravel(), 0.0)
+    s = max(math.sqrt(np.sum(c * c) / c.size), 1e-30)
+    J = np.maximum(0.0, c + s * np.asarray(y0, np.float64).ravel())
+    return J, (float(np.sum((J - c) ** 2)), float(np.sum(c * c)))

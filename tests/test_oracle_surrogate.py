@@ -124,3 +124,39 @@ def test_zero_residual_blocks_are_identity():
     _, cache = S.forward(params, x)
     h1 = S.gelu(cache[0][1])
     np.testing.assert_array_equal(cache[5][0], h1)
+
+
+def test_feature_transform_invariants():
+    """With the statistics taken from the sample itself, the standardised channels have
+    mean 0 and standard deviation 1, the scaled j peaks at 1, and the linear cheap channel
+    has root-mean-square 1 (it is the field over its own root-mean-square)."""
+    rng = np.random.default_rng(8)
+    shape = (6, 7, 8)
+    kap = np.exp(rng.normal(-3.0, 1.0, size=shape))
+    j = rng.random(shape) * 3.0
+    cheap = rng.random(shape) ** 3
+    floor = 1e-4
+    lk, lc = np.log(kap), np.log(cheap + floor)
+    stats = [lk.mean(), 1.0 / lk.std(), 1.0 / j.max(), lc.mean(), 1.0 / lc.std(), floor]
+    x, s = S.features(j, kap, cheap, np.asarray(stats, np.float64))
+    assert abs(s - np.sqrt(np.mean(cheap ** 2))) <= 1e-12 * s
+    assert abs(np.sqrt(np.mean(x[:, 2] ** 2)) - 1.0) < 1e-12
+    for ch in (0, 3):   # float32 statistics: standardised to about 1e-6
+        assert abs(x[:, ch].mean()) < 1e-5 and abs(x[:, ch].std() - 1.0) < 1e-5
+    assert abs(x[:, 1].max() - 1.0) < 1e-6
+
+
+def test_output_transform_special_cases():
+    """y = 0 returns the cheap field (distance 0); y = 1 adds exactly s to every voxel
+    (distance 1, since s is the root-mean-square); a very negative y clips to zero
+    (distance 1); negative cheap values count as zero."""
+    rng = np.random.default_rng(9)
+    cheap = rng.random(500) - 0.1
+    c = np.maximum(cheap, 0.0)
+    J, (a, b) = S.output(np.zeros(500), cheap)
+    assert np.array_equal(J, c) and a == 0.0 and abs(b - np.sum(c * c)) <= 1e-12 * b
+    J, (a, b) = S.output(np.ones(500), cheap)
+    s = np.sqrt(np.mean(c * c))
+    assert np.allclose(J, c + s, rtol=1e-15, atol=0) and abs(np.sqrt(a / b) - 1.0) < 1e-12
+    J, (a, b) = S.output(np.full(500, -1e9), cheap)
+    assert not J.any() and abs(np.sqrt(a / b) - 1.0) < 1e-12
