@@ -83,6 +83,11 @@ typedef struct rtmi_options {
    * and add atomically. 0 picks 1024. Changes the speed, not the field (in the
    * deterministic mode, not a bit of it). Ignored by the direct path. */
   int32_t tile_item_chunks;
+  /* Test hook of the tiled path's stateless calls: > 0 caps each chunk-record buffer at
+   * this many records instead of the library's upper bound, so that the overflow report
+   * (rtmi_dropped_records) can be exercised. 0: the bound. Plans ignore it (they count
+   * their records exactly). */
+  int64_t record_capacity;
 } rtmi_options;
 
 /* Execution paths (rtmi_options.path). Both compute the same field.
@@ -136,6 +141,14 @@ int32_t rtmi_prepare(int32_t num_rays);
  * each stream and those made during graph capture, are then served from memory the pool
  * already holds). */
 int32_t rtmi_reserve(int64_t bytes);
+
+/* Chunk records that the tiled path's stateless calls on the current device could not
+ * store since the last query (their buffers are sized by an upper bound on the records,
+ * see RTMI_PATH_TILED; the tile passes of those calls then missed those deposits). Waits
+ * for all work on the device, writes the count to *count and resets it. Returns RTMI_OK
+ * when the count is 0, RTMI_ERR_RANGE (with a message) when deposits were dropped, or
+ * RTMI_ERR_HIP. Plans never drop records. */
+int32_t rtmi_dropped_records(int64_t* count);
 
 /* Free the workspaces that stateless calls keep per stream on the current device (see
  * RTMI_PATH_TILED), after waiting for all work on the device. Call it to return that
@@ -325,7 +338,9 @@ int32_t rtmi_debug_rays(const float* j_map, const float* kappa_map,
 
 /* Measurement hooks. While enabled (on != 0), every launch of a march kernel is bracketed
  * by a pair of HIP events recorded on its launch stream, tallied per kernel kind:
- * RTMI_KERNEL_RECORD and RTMI_KERNEL_TILE (tiled path), RTMI_KERNEL_DIRECT. Reading
+ * RTMI_KERNEL_RECORD (a record dispatch with its segment fix-up, if any),
+ * RTMI_KERNEL_TILE (one tile-pass dispatch: one bin of one source launch),
+ * RTMI_KERNEL_DIRECT. Reading
  * waits for that kind's recorded events, returns the summed elapsed milliseconds and the
  * number of launches since the last enable or read of that kind, and resets them. Do
  * not enable timing while a stream is being captured. */

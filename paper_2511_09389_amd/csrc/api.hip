@@ -229,7 +229,7 @@ bool capturing(hipStream_t s) {
   return s != nullptr && hipStreamIsCapturing(s, &cap) == hipSuccess && cap != hipStreamCaptureStatusNone;
 }
 
-int32_t get_dirs(int32_t n, hipStream_t stream, DevTable* out) {
+int32_t get_dirs(int32_t n, hipStream_t stream, DevTable* out, bool may_alloc = true) {
   int dev = 0;
   if (int32_t st = current_device(&dev)) return st;
   std::lock_guard<std::mutex> lock(g_mu);
@@ -238,6 +238,9 @@ int32_t get_dirs(int32_t n, hipStream_t stream, DevTable* out) {
     *out = it->second;
     return RTMI_OK;
   }
+  if (!may_alloc)
+    return fail(RTMI_ERR_UNSUPPORTED,
+                "direction table for %d rays not prepared on this device; call rtmi_prepare(%d) first", n, n);
   if (capturing(stream))
     return fail(RTMI_ERR_UNSUPPORTED,
                 "direction table for %d rays not prepared; call rtmi_prepare before capture", n);
@@ -341,6 +344,29 @@ int32_t acquire_scratch(size_t bytes, hipStream_t s, WorkspaceSlot slot, Scratch
   return RTMI_OK;
 }
 
+// ---- chunk records the stateless calls could not store (reported by rtmi_dropped_records) ----
+// One counter per device: this file-scope device variable, whose per-device address is
+// looked up once per device and passed to the schedule kernels.
+__device__ unsigned long long g_dropped_records;
+
+std::mutex g_dropped_mu;
+std::map<int, unsigned long long*> g_dropped_ptr;
+
+int32_t dropped_counter(unsigned long long** out) {
+  int dev = 0;
+  if (int32_t st = current_device(&dev)) return st;
+  std::lock_guard<std::mutex> lock(g_dropped_mu);
+  auto it = g_dropped_ptr.find(dev);
+  if (it == g_dropped_ptr.end()) {
+    unsigned long long* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&ptr), HIP_SYMBOL(g_dropped_records));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(dropped-record counter)");
+    it = g_dropped_ptr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return RTMI_OK;
+}
+
 // ---- measurement hooks: event pairs around kernel launches, per kernel kind ----
 std::mutex g_tmu;
 bool g_timing = false;
@@ -403,6 +429,7 @@ struct Plan {
   bool tiled = true;
   bool explicit_dirs = false;
   int32_t item_chunks = 0;  // tile work-item size; 0: kItemChunks
+  int64_t record_capacity = 0;  // > 0: stateless chunk-record buffers capped (test hook)
   std::vector<int32_t> nsub;
   std::vector<DevTable> tables;
   double bound_per_unit_j = 0.0;
@@ -447,6 +474,9 @@ int32_t validate(const Problem& p, Plan* plan, bool maps_given = true) {
       return fail(RTMI_ERR_INVALID_ARG, "tile_item_chunks must be in [0, 2^20] (got %d)",
                   p.opts->tile_item_chunks);
     plan->item_chunks = p.opts->tile_item_chunks;
+    if (p.opts->record_capacity < 0)
+      return fail(RTMI_ERR_INVALID_ARG, "record_capacity must be >= 0");
+    plan->record_capacity = p.opts->record_capacity;
     if (plan->explicit_dirs && p.opts->ray_weight > 0.0f && !std::isfinite(p.opts->ray_weight))
       return fail(RTMI_ERR_NONFINITE, "ray_weight is not finite");
   }
@@ -523,7 +553,9 @@ struct TileSchedule {
     counters = reinterpret_cast<int*>(base + align256(size_t(tiles) * rtmi::kMaxParts * sizeof(int2)));
   }
   long long* rec_total() const { return reinterpret_cast<long long*>(counters + 4); }
-  void apply(rtmi::TileArgs& t, int item_chunks, uint2* recs, int64_t capacity) const {
+  void apply(rtmi::TileArgs& t, int item_chunks, uint2* recs, int64_t capacity,
+             unsigned long long* dropped = nullptr) const {
+    t.dropped = dropped;
     t.tile_cost = cost;
     t.tile_begin = begin;
     t.tile_count = count;
@@ -652,6 +684,7 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
     p_elems_max = std::max(p_elems_max, len > 0 ? e : int64_t(0));
     t_elems_max = std::max(t_elems_max, t);
   }
+  if (shared_records && plan.record_capacity > 0) L.rec_capacity = std::min(L.rec_capacity, plan.record_capacity);
   L.n_launch = src_chunks * ((p.n_bins + kMaxBinsPerLaunch - 1) / kMaxBinsPerLaunch);
   const int32_t nb_max = std::min(kMaxBinsPerLaunch, p.n_bins);
   // a shared j and a shared (scaled) kappa are gathered from one interleaved copy
@@ -739,12 +772,15 @@ struct EventList {
 
 int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
                   const double* det_scale, TiledMode mode = TiledMode::kFull,
-                  char* given_ws = nullptr, const RecordSlices* slices = nullptr) {
+                  char* given_ws = nullptr, const RecordSlices* slices = nullptr, bool use_side = true) {
   const hipStream_t st = p.stream;
   // a stateless call keeps its records in the workspace; a plan, in slices of its own
   const TiledLayout L = tiled_layout(p, plan, true, mode == TiledMode::kFull);
   if ((mode == TiledMode::kFill || mode == TiledMode::kReplay) && !slices)
     return fail(RTMI_ERR_INVALID_ARG, "a plan's chunk records are missing");
+  unsigned long long* dropped = nullptr;
+  if (mode == TiledMode::kFull)
+    if (int32_t rc = dropped_counter(&dropped)) return rc;
   char* ws = given_ws;
   Scratch scratch;
   if (!ws) {
@@ -832,11 +868,11 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       sched.carve(ws + L.sched + launch * L.sched_bytes, L.tiles, L.pair_blocks);
       if (slices && launch < static_cast<int>(slices->off.size()))
         sched.apply(t, plan.item_chunks, slices->base + slices->off[launch], slices->count[launch]);
-      else   // launches alternate between the shared buffers
+      else   // launches alternate between the shared buffers, sized by a bound
         sched.apply(t, plan.item_chunks,
                     reinterpret_cast<uint2*>(ws + L.recs + (launch % L.rec_buffers) *
                                                                align256(size_t(L.rec_capacity) * sizeof(uint2))),
-                    L.rec_capacity);
+                    L.rec_capacity, dropped);
       launches.push_back({r, t, nb, blocks, fix_waves});
     }
   }
@@ -849,7 +885,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
   // the two streams). Without a side stream, each fill runs just before its tile pass.
   hipStream_t sched_st = st;
   SideStream side;
-  if (mode == TiledMode::kFull && side.open(st) == hipSuccess) sched_st = side.stream;
+  if (mode == TiledMode::kFull && use_side && side.open(st) == hipSuccess) sched_st = side.stream;
   if (mode == TiledMode::kFull || mode == TiledMode::kSchedule)
     for (const LaunchArgs& l : launches)
       if ((e = rtmi::launch_tile_schedule(l.t, L.tiles, sched_st)) != hipSuccess)
@@ -904,11 +940,12 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
     } else if (fill_each && (e = rtmi::launch_tile_fill(l.t, L.tiles, st)) != hipSuccess) {
       return hip_fail(e, "tile records");
     }
-    TimedLaunch tl;
-    if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl)) != hipSuccess) return hip_fail(e, "timing");
-    if ((e = rtmi::launch_tile_run(l.t, l.nb, plan.det, false, st)) != hipSuccess)
-      return hip_fail(e, "tile launch");
-    if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
+    for (int32_t b = 0; b < l.nb; ++b) {   // one tile pass (one kernel dispatch) per bin
+      TimedLaunch tl;
+      if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl)) != hipSuccess) return hip_fail(e, "timing");
+      if ((e = rtmi::launch_tile_bin(l.t, b, plan.det, false, st)) != hipSuccess) return hip_fail(e, "tile launch");
+      if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
+    }
     if (fill_ahead && li + 2 < launches.size()) {   // launch li + 2 reuses this launch's buffer
       if ((e = hipEventRecord(read[li], st)) != hipSuccess ||
           (e = hipStreamWaitEvent(sched_st, read[li], 0)) != hipSuccess ||
@@ -1067,6 +1104,8 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
   }
   const size_t sched_bytes = TileSchedule::bytes(tiles, max_blocks);
   const size_t rec_off = corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes) + sched_bytes;
+  unsigned long long* dropped = nullptr;
+  if (int32_t rc = dropped_counter(&dropped)) return rc;
   Scratch scratch;
   if (int32_t rc = acquire_scratch(rec_off + size_t(rec_capacity) * sizeof(uint2), st, kSlotAdjoint, &scratch))
     return rc;
@@ -1134,7 +1173,7 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
     t.tiles_x = tiles_x;
     t.tiles_y = tiles_y;
     t.tiles_z = tiles_z;
-    sched.apply(t, 0, recs, rec_capacity);
+    sched.apply(t, 0, recs, rec_capacity, dropped);
     if ((e = rtmi::launch_fill_zero(corner, 64, st)) != hipSuccess) return hip_fail(e, "fill");
     if (blocks > 0 && (e = rtmi::launch_adjoint_record(r, blocks, st)) != hipSuccess)
       return hip_fail(e, "adjoint launch");
@@ -1346,6 +1385,23 @@ int32_t rtmi_reserve(int64_t bytes) {
   hipError_t e = hipFreeAsync(p, nullptr);
   if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
   if (e != hipSuccess) return hip_fail(e, "rtmi_reserve");
+  return RTMI_OK;
+}
+
+int32_t rtmi_dropped_records(int64_t* count) {
+  if (!count) return fail(RTMI_ERR_INVALID_ARG, "null count pointer");
+  unsigned long long* d = nullptr;
+  if (int32_t rc = dropped_counter(&d)) return rc;
+  hipError_t e = hipDeviceSynchronize();
+  unsigned long long n = 0;
+  if (e == hipSuccess) e = hipMemcpy(&n, d, sizeof n, hipMemcpyDeviceToHost);
+  if (e == hipSuccess && n != 0) e = hipMemset(d, 0, sizeof n);
+  if (e != hipSuccess) return hip_fail(e, "rtmi_dropped_records");
+  *count = static_cast<int64_t>(n);
+  if (n != 0)
+    return fail(RTMI_ERR_RANGE, "%llu chunk records did not fit their buffers: those deposits are missing "
+                "from the fields of the calls since the last query", n);
+  g_error.clear();
   return RTMI_OK;
 }
 

@@ -106,6 +106,7 @@ struct TileArgs {
   long long* rec_total;           // chunk records of all tiles (before clipping)
   uint2* recs;                    // chunk records, grouped by tile
   long long rec_capacity;
+  unsigned long long* dropped;    // device counter of records beyond rec_capacity, or null
   int2* item_map;                 // [tiles * kMaxParts] work item -> (tile, part | parts << 16)
   int* item_total;                // number of work items
   int* item_next;                 // next unclaimed work item
@@ -212,6 +213,8 @@ hipError_t launch_tile_schedule(const TileArgs& a, int tiles, hipStream_t s);
 hipError_t launch_tile_fill(const TileArgs& a, int tiles, hipStream_t s);
 hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool deterministic, bool nearest,
                            hipStream_t s);
+// The tile pass of one bin of a launch (launch_tile_run runs every bin's in turn).
+hipError_t launch_tile_bin(const TileArgs& a, int bin, bool deterministic, bool nearest, hipStream_t s);
 hipError_t launch_adjoint_record(const AdjointArgs& a, int n_blocks, hipStream_t s);
 // loss[0] = scale * sum (field - target)^2 (overwritten), grad = 2 scale (field - target).
 hipError_t launch_field_mse(const float* field, const float* target, long long n, float scale, float* grad,

@@ -701,6 +701,10 @@ __device__ void schedule_tiles(const TileArgs& a, int n_tiles, ScheduleShared<TH
     *a.item_next = 0;
     *a.item_done = 0;
     *a.rec_total = sh.rec_carry;
+    // records beyond the buffer are never written; the tile passes skip them, and the
+    // count of such lost records is reported to the host
+    if (a.dropped && sh.rec_carry > a.rec_capacity)
+      atomicAdd(a.dropped, static_cast<unsigned long long>(sh.rec_carry - a.rec_capacity));
   }
 }
 
@@ -1140,19 +1144,24 @@ hipError_t launch_tile_fill(const TileArgs& a, int tiles, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool det, bool nearest, hipStream_t s) {
+hipError_t launch_tile_bin(const TileArgs& a, int bin, bool det, bool nearest, hipStream_t s) {
   // One pass per bin over the same schedule (each pass leaves it rewound for the next).
   // A one-bin LDS tile with its halo (49 KB) lets three work-groups share a compute unit;
   // tiles of several bins would hold one, and measured slower than repeating the geometry.
+  if (bin < 0 || bin >= kMaxBinsPerLaunch) return hipErrorInvalidValue;
+  TileArgs b = a;
+  b.V = a.V + bin * a.v_bin_stride;
+  if (a.out) b.out = a.out + bin * a.out_stride;
+  if (a.out_q) b.out_q = a.out_q + bin * a.out_stride;
+  b.corner = a.corner + bin * 8;
+  b.corner_q = a.corner_q + bin * 8;
+  return launch_tile_one_bin(b, det, nearest, s);
+}
+
+hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool det, bool nearest, hipStream_t s) {
   if (n_bins < 1 || n_bins > kMaxBinsPerLaunch) return hipErrorInvalidValue;
   for (int b0 = 0; b0 < n_bins; ++b0) {
-    TileArgs b = a;
-    b.V = a.V + b0 * a.v_bin_stride;
-    if (a.out) b.out = a.out + b0 * a.out_stride;
-    if (a.out_q) b.out_q = a.out_q + b0 * a.out_stride;
-    b.corner = a.corner + b0 * 8;
-    b.corner_q = a.corner_q + b0 * 8;
-    const hipError_t e = launch_tile_one_bin(b, det, nearest, s);
+    const hipError_t e = launch_tile_bin(a, b0, det, nearest, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;

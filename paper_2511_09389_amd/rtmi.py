@@ -40,7 +40,7 @@ class RtmiError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("accum_mode", ctypes.c_int32), ("directions", ctypes.c_void_p),
                 ("ray_weight", ctypes.c_float), ("path", ctypes.c_int32),
-                ("tile_item_chunks", ctypes.c_int32)]
+                ("tile_item_chunks", ctypes.c_int32), ("record_capacity", ctypes.c_int64)]
 
 
 def _load():
@@ -57,6 +57,7 @@ def _load():
         "rtmi_prepare": (I32, [I32]),
         "rtmi_reserve": (I32, [I64]),
         "rtmi_release_workspaces": (I32, []),
+        "rtmi_dropped_records": (I32, [ctypes.POINTER(ctypes.c_int64)]),
         "rtmi_trace_single": (I32, [P, P, I32, I32, I32, P, I32, F32, F32, F32, P, P]),
         "rtmi_trace_multi": (I32, [P, P, I32, I32, I32, I32, P, P, P, F32, F32, F32, P, P]),
         "rtmi_trace_bins": (I32, [P, I64, P, I64, P, I32, I32, I32, I32, I32, P, P, P, F32, F32,
@@ -161,6 +162,17 @@ def release_workspaces(device=None):
         _check(lib.rtmi_release_workspaces())
 
 
+def dropped_records(device=None):
+    """Wait for the device; return (and reset) the chunk records that stateless tiled calls
+    could not store since the last query. 0 means no deposit was lost."""
+    n = ctypes.c_int64(0)
+    with torch.cuda.device(device if device is not None else torch.cuda.current_device()):
+        code = lib.rtmi_dropped_records(ctypes.byref(n))
+    if code not in (OK, ERR_RANGE):
+        _check(code)
+    return int(n.value)
+
+
 def _new_field(shape, like):
     return torch.empty(shape, dtype=torch.float32, device=like.device)
 
@@ -213,7 +225,7 @@ def trace_multi(j_map, kappa_map, source_pos, num_rays, step_size, radiation_vel
 
 def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
                time_step, kappa_scale=None, substep_cap=None, out=None, deterministic=False,
-               directions=None, ray_weight=0.0, path=PATH_TILED, tile_item_chunks=0):
+               directions=None, ray_weight=0.0, path=PATH_TILED, tile_item_chunks=0, record_capacity=0):
     """Frequency bins as a batch axis. j_maps / kappa_maps are 3-D (shared by all bins) or
     4-D [B][nx][ny][nz]; a 3-D kappa with kappa_scale gives kappa_b = kappa * scale[b].
     Returns a [B][nx][ny][nz] float32 tensor."""
@@ -241,7 +253,7 @@ def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_ve
     out = _new_field((n_bins,) + grid, j_maps) if out is None else \
         _same(out, "out", (n_bins,) + grid, j_maps.device)
     opts = Options(ACCUM_DETERMINISTIC if deterministic else ACCUM_ATOMIC, None, float(ray_weight),
-                   int(path), int(tile_item_chunks))
+                   int(path), int(tile_item_chunks), int(record_capacity))
     dirs = None
     if directions is not None:
         dirs = _host_f32(directions, 3)

@@ -329,3 +329,43 @@ def test_errors_raise(rt, dev):
     assert e.value.code == rt.ERR_NONFINITE
     with pytest.raises(TypeError):
         rt.trace_single(j.double(), j, (1.0, 1.0, 1.0), 8, 0.5, 2.0, 1.0)
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_deterministic_mode_with_large_ray_weight_and_negative_kappa(rt, dev, path):
+    """The fixed-point scale is bounded with the caller's ray weight (here 160 times
+    4 pi / N) and widened for negative opacity, so such inputs still match the oracle."""
+    rng = np.random.default_rng(31)
+    shape = (14, 12, 10)
+    j = rng.random(shape).astype(np.float32)
+    kap = (0.05 * rng.random(shape) - 0.03).astype(np.float32)
+    dirs = oracle.fibonacci_directions(50).astype(np.float32)
+    src = np.array([[6.3, 5.1, 4.7]], np.float32)
+    got = rt.trace_bins(to_dev(j, dev), to_dev(kap, dev), src, 50, 0.5, 20.0, 1.0, deterministic=True,
+                        directions=dirs, ray_weight=40.0, path=PATHS[path])[0].cpu().numpy()
+    want = oracle.trace_single(j, kap, src[0], 50, 0.5, 20.0, 1.0, directions=dirs.astype(np.float64),
+                               weight=float(np.float32(40.0)))
+    assert_parity(got, want)
+
+
+def test_dropped_chunk_records_are_reported(rt, dev):
+    """A stateless call whose chunk-record buffer is too small (forced through the test
+    hook record_capacity) loses deposits: the schedule pass counts the records that did
+    not fit and rtmi_dropped_records reports them (and an error through the C ABI). With
+    the library's own bound nothing is dropped and the field matches the oracle."""
+    import ctypes
+    w = inputs.small_turbulent(n=24, n_src=3, num_rays=256, c=20.0)
+    jd, kd = to_dev(w.j_map, dev), to_dev(w.kappa_map, dev)
+    rt.dropped_records()   # start from zero
+    short = multi(rt, jd, kd, w.source_pos, 256, 0.5, 20.0, 1.0, record_capacity=100)
+    n = ctypes.c_int64(0)
+    code = rt.lib.rtmi_dropped_records(ctypes.byref(n))
+    note(f"capacity 100 records: {n.value} dropped")
+    assert code == rt.ERR_RANGE and n.value > 0
+    assert "did not fit" in rt.lib.rtmi_last_error().decode()
+    assert rt.dropped_records() == 0   # the query reset the count
+    full = multi(rt, jd, kd, w.source_pos, 256, 0.5, 20.0, 1.0)
+    assert rt.dropped_records() == 0
+    want = oracle.trace_multi(w.j_map, w.kappa_map, w.source_pos, 256, 0.5, 20.0, 1.0)
+    assert_parity(full.cpu().numpy(), want)
+    assert float(short.sum()) < float(full.sum())   # the lost deposits are missing, nothing else

@@ -59,13 +59,42 @@ def test_network_gradients_match_oracle(rt, dev):
     assert eg < 3e-2 and cos > 0.999
 
 
+def test_feature_and_output_kernels_match_oracle(rt, dev):
+    """rtmi_surrogate_features and rtmi_surrogate_output against the FP64 statement of the
+    transforms (oracle.surrogate.features / output) on a turbulent sample: the bf16 input
+    channels to bf16 rounding, the channels past the features exactly zero, the fp32
+    prediction and the error-check sums to binary32 rounding (float atomics for the sums)."""
+    w, j, k, cheap, full = sg.make_sample(77, dev, n=24, n_src=4, num_rays=512, c=24.0)
+    stats = sg.input_stats([(w, j, k, cheap, full)])
+    x, sums = rt.surrogate_features(j, k, cheap, stats)
+    want_x, s = S.features(f64(j), f64(k), f64(cheap), stats)
+    got_x = f64(x).reshape(-1, sg.C)
+    assert not got_x[:, sg.N_FEATURES:].any()
+    # bf16 keeps 8 significant bits; the 1e-5 absolute term covers binary32 cancellation in
+    # the standardised channels (values of order 1 that happen to be near zero)
+    err = np.abs(got_x[:, :sg.N_FEATURES] - want_x)
+    assert np.all(err <= 2.0 ** -8 * np.abs(want_x) + 1e-5), float(err.max())
+    assert abs(float(torch.sqrt(sums[0] / cheap.numel())) - s) <= 1e-5 * s
+    rng = np.random.default_rng(5)
+    y = torch.zeros((1,) + tuple(cheap.shape) + (sg.C,), dtype=torch.bfloat16, device=dev)
+    y[..., 0] = torch.from_numpy(rng.normal(0.0, 0.3, size=cheap.shape).astype(np.float32)).to(dev)
+    field, check = rt.surrogate_output(y.contiguous(), cheap, sums)
+    want_J, (a, b) = S.output(f64(y)[..., 0], f64(cheap))
+    got_J = f64(field).ravel()
+    assert np.all(np.abs(got_J - want_J) <= 1e-6 * (np.abs(want_J) + s))
+    c = f64(check)
+    assert abs(c[0] - a) <= 1e-5 * a and abs(c[1] - b) <= 1e-5 * b
+
+
 def test_train_and_fallback(rt, dev):
     """A small run of the whole recipe: generate samples with the march, train, calibrate
     the check on validation samples, and evaluate on held-out ones. The loss must fall; the
     network must bring the cheap march closer to the full one (what the learned part gains
-    at the cheap march's cost); and every returned field (surrogate or fallback) must be
-    within 2 % of the full march (the check was calibrated for 1 % on the validation
-    samples)."""
+    at the cheap march's cost); and every returned field must be within 1 % of the full
+    march, the target the check was calibrated for. A returned field is either a surrogate
+    prediction the check accepted or the full march itself: when no prediction passes the
+    check (accepted = 0 in the printed summary), this test exercises the fallback only and
+    says nothing about predictions within 1 %."""
     kw = dict(n=32, n_src=6, num_rays=1024, c=32.0)
     train = [sg.make_sample(s, dev, **kw) for s in range(24)]
     val = [sg.make_sample(1000 + s, dev, **kw) for s in range(8)]
@@ -78,4 +107,7 @@ def test_train_and_fallback(rt, dev):
     note(f"threshold {thr:.4f}; validation (check, error): {[(round(a, 4), round(b, 4)) for a, b in pairs]}")
     note(f"held-out: {res}; cheap march alone: mean error {np.mean(cheap_err):.4f}")
     assert np.median([p[1] for p in pairs]) < np.mean([sg.rel_l2(s[3], s[4]) for s in val])
-    assert res["max_err"] <= 0.02
+    note(f"accepted {res['accepted']} of {res['samples']} held-out predictions; "
+         f"surrogate path {res['surrogate_fields_per_s']:.0f} fields/s, plain march "
+         f"{res['march_fields_per_s']:.0f} fields/s")
+    assert res["max_err"] <= 0.01

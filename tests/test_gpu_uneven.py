@@ -1,0 +1,177 @@
+"""GPU parity on the uneven 256^3 batch (64 sources with N_Omega in {1024..16384} and
+substep caps in [64, 512], 4 frequency bins with kappa_nu = kappa (nu/nu0)^-3).
+
+Two views, both against the FP64 oracle with the field tolerances (relative L2 <= 1e-5,
+per-voxel relative error <= 1e-4 wherever the oracle exceeds 1e-6 of its maximum):
+
+* a 36-source subset that spans every N_Omega class (16384 rays with a 420-substep cap,
+  8192 rays with the largest cap, 502) and needs two source launches, so the second
+  record launch, the alternating chunk-record buffers and the side-stream refills run on
+  the full 256^3 grid; the whole field of every bin is compared, from the stateless call
+  on both paths and from an autotuned plan replayed as a HIP graph;
+* the whole batch, all 64 sources, run exactly as the benchmark runs it (an autotuned
+  plan captured in a HIP graph and replayed), checked voxel by voxel at sampled interior
+  voxels with oracle.trace_voxels, which marches only the rays that can reach them.
+
+The oracle work is spread over host processes (fields add over sources).
+"""
+
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle_pool
+from paper_2511_09389_amd import autotune, inputs
+
+pytestmark = pytest.mark.gpu
+
+REL_L2 = 1e-5
+PER_VOXEL = 1e-4
+FLOOR = 1e-6
+WORKLOAD = ("uneven_bins", {})
+
+
+def note(msg):
+    print(f"[gpu-uneven] {msg}", file=sys.stderr, flush=True)
+
+
+def assert_parity(got, want):
+    got = np.asarray(got, dtype=np.float64)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    mask = want > FLOOR * want.max()
+    rel = np.abs(got[mask] - want[mask]) / want[mask]
+    assert err <= REL_L2, f"rel L2 {err:.3e} > {REL_L2}"
+    assert rel.max() <= PER_VOXEL, f"max per-voxel rel {rel.max():.3e} > {PER_VOXEL}"
+    return err, float(rel.max())
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def uneven(dev):
+    w = inputs.uneven_bins()
+    return w, torch.from_numpy(w.j_map).to(dev), torch.from_numpy(w.kappa_map).to(dev)
+
+
+def subset_picks(w):
+    """36 sources: the two heaviest classes' largest-cap representatives among the 16384-
+    and 8192-ray sources, placed in the first launch, and the 34 cheapest others."""
+    cost = w.num_rays.astype(np.int64) * w.substep_cap
+    big = int(np.flatnonzero(w.num_rays == 16384)[np.argmax(w.substep_cap[w.num_rays == 16384])])
+    long_cap = int(np.argmax(np.where(w.num_rays == 8192, w.substep_cap, -1)))
+    rest = [int(i) for i in np.argsort(cost, kind="stable") if int(i) not in (big, long_cap)][:34]
+    return rest[:20] + [big, long_cap] + rest[20:]
+
+
+@pytest.fixture(scope="module")
+def subset(uneven):
+    w = uneven[0]
+    picks = subset_picks(w)
+    assert len(picks) > 32 and set(w.num_rays[picks].tolist()) == {1024, 2048, 4096, 8192, 16384}
+    note(f"oracle: 36 sources x 4 bins on 256^3 ({oracle_pool.host_workers()} host processes)")
+    want = oracle_pool.trace_bins_subset(*WORKLOAD, picks)
+    return picks, want
+
+
+@pytest.mark.parametrize("path", ["tiled", "direct"])
+def test_two_launch_subset_full_field(rt, uneven, subset, path):
+    w, j, k = uneven
+    picks, want = subset
+    note(f"trace_bins, 36 sources (rays {sorted(set(w.num_rays[picks].tolist()))}, caps up to "
+         f"{w.substep_cap[picks].max()}), path={path}")
+    got = rt.trace_bins(j, k, w.source_pos[picks], w.num_rays[picks], w.step_size, w.radiation_velocity,
+                        w.time_step, kappa_scale=w.kappa_scale, substep_cap=w.substep_cap[picks],
+                        path=rt.PATH_TILED if path == "tiled" else rt.PATH_DIRECT).cpu().numpy()
+    for b in range(w.n_bins):
+        err, mx = assert_parity(got[b], want[b])
+        note(f"  bin {b}: rel L2 {err:.2e}, max per-voxel {mx:.2e}")
+
+
+def test_two_launch_subset_tuned_plan_graph(rt, uneven, subset, tmp_path, monkeypatch):
+    """The autotuned plan of the subset, captured in a HIP graph: every replay matches the
+    oracle over the whole field."""
+    w, j, k = uneven
+    picks, want = subset
+    monkeypatch.setenv("RTMI_TUNE_CACHE", str(tmp_path / "tune.json"))
+    plan = autotune.tuned_plan(j, k, w.source_pos[picks], w.num_rays[picks], w.step_size,
+                               w.radiation_velocity, w.time_step, n_bins=w.n_bins,
+                               kappa_scale=w.kappa_scale, substep_cap=w.substep_cap[picks])
+    out = torch.empty((w.n_bins,) + w.shape, device=j.device)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.execute(j, k, out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.execute(j, k, out)
+    for rep in range(2):
+        out.fill_(-1.0)
+        graph.replay()
+        torch.cuda.synchronize()
+        got = out.cpu().numpy()
+        for b in range(w.n_bins):
+            err, mx = assert_parity(got[b], want[b])
+            note(f"  replay {rep} bin {b}: rel L2 {err:.2e}, max per-voxel {mx:.2e}")
+    del graph
+    plan.close()
+
+
+def sample_voxels(w, field_b, rng, n_random=48, n_near=16):
+    """Interior voxels: random ones, some within three voxels of sources, and the field's
+    largest interior voxel."""
+    n = np.array(w.shape)
+    rand = rng.integers(1, n - 1, size=(n_random, 3))
+    srcs = rng.choice(w.n_src, size=n_near, replace=False)
+    near = np.clip(np.rint(w.source_pos[srcs]).astype(np.int64) + rng.integers(-3, 4, size=(n_near, 3)), 1, n - 2)
+    inner = field_b[1:-1, 1:-1, 1:-1]
+    top = np.array(np.unravel_index(int(np.argmax(inner)), inner.shape)) + 1
+    vox = np.unique(np.concatenate([rand, near, top[None, :]]), axis=0)
+    return vox
+
+
+def test_full_batch_as_benchmarked_sampled_voxels(rt, uneven):
+    """All 64 sources x 4 bins through the autotuned plan replayed as a HIP graph (the
+    benchmark's configuration): sampled interior voxels of every bin against the oracle,
+    per-voxel relative error <= 1e-4 where the field exceeds 1e-6 of the bin's maximum."""
+    w, j, k = uneven
+    plan = autotune.tuned_plan(j, k, w.source_pos, w.num_rays, w.step_size, w.radiation_velocity, w.time_step,
+                               n_bins=w.n_bins, kappa_scale=w.kappa_scale, substep_cap=w.substep_cap)
+    out = torch.empty((w.n_bins,) + w.shape, device=j.device)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        plan.execute(j, k, out)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        plan.execute(j, k, out)
+    out.fill_(-1.0)
+    graph.replay()
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    del graph
+    plan.close()
+    rng = np.random.default_rng(2024)
+    voxels = [sample_voxels(w, got[b], rng) for b in range(w.n_bins)]
+    note(f"full batch: {sum(len(v) for v in voxels)} sampled voxels, oracle on host processes")
+    want = oracle_pool.trace_voxels_bins(*WORKLOAD, voxels)
+    for b in range(w.n_bins):
+        vmax = float(got[b].max())
+        g = got[b][voxels[b][:, 0], voxels[b][:, 1], voxels[b][:, 2]].astype(np.float64)
+        mask = want[b] > FLOOR * vmax
+        rel = np.abs(g[mask] - want[b][mask]) / want[b][mask]
+        note(f"  bin {b}: {mask.sum()} voxels above the floor, max per-voxel {rel.max():.2e}, "
+             f"largest sampled value {want[b].max():.3e} (field max {vmax:.3e})")
+        assert mask.sum() >= 20
+        assert rel.max() <= PER_VOXEL, f"bin {b}: per-voxel {rel.max():.3e}"
+        # voxels below the floor must still be small, not wrong by orders of magnitude
+        assert np.all(np.abs(g - want[b]) <= PER_VOXEL * np.maximum(want[b], FLOOR * vmax))
