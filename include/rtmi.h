@@ -197,6 +197,38 @@ int32_t rtmi_trace_bins(const float* j_maps, int64_t j_bin_stride,
                         float radiation_velocity, float time_step,
                         float* out_fields, const rtmi_options* opts, void* stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc. The same call as rtmi_trace_bins (same
+ * arguments, the same field; in the deterministic mode the same bits), with no
+ * allocation of any kind: every buffer the call needs beyond its inputs and outputs (the
+ * tiled path's gather table, deposit rows, tile schedules and chunk records, or the
+ * deterministic mode's fixed-point field) is carved from one static device array of
+ * rtmi_static_scratch_bytes() bytes (384 MiB) that the library holds on each device it
+ * runs on until the process ends. The geometry passes run on `stream` itself (no side
+ * stream, no events), and kernel timing (rtmi_timing_enable) does not record these calls.
+ * Errors, all before anything is enqueued:
+ *  - RTMI_ERR_RANGE when the call needs more scratch than the array holds (the message
+ *    gives the size it needs; a 128^3 grid with 16 sources x 4096 rays x 256 substeps
+ *    fits);
+ *  - RTMI_ERR_UNSUPPORTED when a source's N_Omega has no direction table on this device
+ *    (call rtmi_prepare(N_Omega) first) or when opts->directions is set (that table is
+ *    uploaded per call).
+ * Every call on one device shares that device's array and leaves its contents behind
+ * (the call clears what must start at zero itself). Calls ordered on one stream are safe;
+ * calls that may overlap on one device (concurrent streams, several host threads) race on
+ * the array and must be serialised by the caller. */
+int32_t rtmi_trace_bins_static(const float* j_maps, int64_t j_bin_stride,
+                               const float* kappa_maps, int64_t kappa_bin_stride,
+                               const float* kappa_scale, int32_t n_bins,
+                               int32_t nx, int32_t ny, int32_t nz, int32_t n_src,
+                               const float* source_pos, const int32_t* num_rays,
+                               const int32_t* substep_cap, float step_size,
+                               float radiation_velocity, float time_step,
+                               float* out_fields, const rtmi_options* opts, void* stream);
+
+/* Size in bytes of the static scratch of rtmi_trace_bins_static, per device. */
+int64_t rtmi_static_scratch_bytes(void);
+
 /* ---- Plans: the batched multi-source, multi-bin march set up once, run many times ----
  *
  * The multi-source routine (Sec. 2, "loop-and-sum") and the frequency bins (Sec. 2,

@@ -367,6 +367,33 @@ int32_t dropped_counter(unsigned long long** out) {
   return RTMI_OK;
 }
 
+// ---- the scratch of rtmi_trace_bins_static: a fixed device array, nothing allocated ----
+// Each device that runs the library holds its own copy of this array for the life of the
+// process. Host code never passes the array's name to a kernel or a copy (on the host it
+// only names the symbol): it looks up the array's address on each device once, with that
+// device current, and uses that address.
+constexpr size_t kStaticScratchBytes = size_t(384) << 20;
+static __device__ __align__(256) unsigned char g_static_scratch[kStaticScratchBytes];
+
+std::mutex g_static_mu;
+std::map<int, char*> g_static_ptr;   // device -> address of its copy of g_static_scratch
+
+int32_t static_scratch(char** out) {
+  int dev = 0;
+  if (int32_t st = current_device(&dev)) return st;
+  std::lock_guard<std::mutex> lock(g_static_mu);
+  auto it = g_static_ptr.find(dev);
+  if (it == g_static_ptr.end()) {
+    char* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(reinterpret_cast<void**>(&ptr), HIP_SYMBOL(g_static_scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(static scratch)");
+    if (!ptr) return fail(RTMI_ERR_HIP, "hipGetSymbolAddress(static scratch) returned a null address");
+    it = g_static_ptr.emplace(dev, ptr).first;
+  }
+  *out = it->second;
+  return RTMI_OK;
+}
+
 // ---- measurement hooks: event pairs around kernel launches, per kernel kind ----
 std::mutex g_tmu;
 bool g_timing = false;
@@ -380,9 +407,10 @@ struct TimedLaunch {
   int kind = 0;
 };
 
-hipError_t timed_begin(hipStream_t s, int kind, TimedLaunch* t) {
+// (allowed = false: a call that may not allocate, so it creates no events either)
+hipError_t timed_begin(hipStream_t s, int kind, TimedLaunch* t, bool allowed = true) {
   std::lock_guard<std::mutex> lock(g_tmu);
-  t->on = g_timing;
+  t->on = g_timing && allowed;
   t->kind = kind;
   if (!g_timing) return hipSuccess;
   if (g_free.empty()) {
@@ -430,6 +458,7 @@ struct Plan {
   bool explicit_dirs = false;
   int32_t item_chunks = 0;  // tile work-item size; 0: kItemChunks
   int64_t record_capacity = 0;  // > 0: stateless chunk-record buffers capped (test hook)
+  bool no_alloc = false;        // the call may not allocate (static scratch, no events)
   std::vector<int32_t> nsub;
   std::vector<DevTable> tables;
   double bound_per_unit_j = 0.0;
@@ -924,7 +953,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       return hip_fail(e, "fill");
     if (l.blocks > 0) {
       TimedLaunch tl;
-      if ((e = timed_begin(st, RTMI_KERNEL_RECORD, &tl)) != hipSuccess) return hip_fail(e, "timing");
+      if ((e = timed_begin(st, RTMI_KERNEL_RECORD, &tl, !plan.no_alloc)) != hipSuccess) return hip_fail(e, "timing");
       if ((e = rtmi::launch_record(l.r, l.nb, p.j_stride == 0, plan.det, l.blocks, st)) != hipSuccess)
         return hip_fail(e, "record launch");
       if (l.fix_waves > 0 && (e = rtmi::launch_fixup(l.r, l.nb, plan.det, l.fix_waves, st)) != hipSuccess)
@@ -942,7 +971,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
     }
     for (int32_t b = 0; b < l.nb; ++b) {   // one tile pass (one kernel dispatch) per bin
       TimedLaunch tl;
-      if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl)) != hipSuccess) return hip_fail(e, "timing");
+      if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl, !plan.no_alloc)) != hipSuccess) return hip_fail(e, "timing");
       if ((e = rtmi::launch_tile_bin(l.t, b, plan.det, false, st)) != hipSuccess) return hip_fail(e, "tile launch");
       if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
     }
@@ -1001,7 +1030,7 @@ int32_t run_direct(const Problem& p, const Plan& plan, unsigned long long* out_q
       a.blk_begin[ns] = blocks;
       if (blocks == 0) continue;
       TimedLaunch tl;
-      if ((e = timed_begin(st, RTMI_KERNEL_DIRECT, &tl)) != hipSuccess) return hip_fail(e, "timing");
+      if ((e = timed_begin(st, RTMI_KERNEL_DIRECT, &tl, !plan.no_alloc)) != hipSuccess) return hip_fail(e, "timing");
       if ((e = rtmi::launch_march(a, nb, p.j_stride == 0, plan.det, blocks, st)) != hipSuccess)
         return hip_fail(e, "march launch");
       if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
@@ -1010,11 +1039,30 @@ int32_t run_direct(const Problem& p, const Plan& plan, unsigned long long* out_q
   return RTMI_OK;
 }
 
-int32_t run(const Problem& p) {
+// no_alloc: the call takes every buffer from the static scratch (or fails before it
+// enqueues anything), uses only direction tables prepared beforehand, and runs the tile
+// geometry passes on the caller's stream (no side stream, no events).
+int32_t run(const Problem& p, bool no_alloc = false) {
   Plan plan;
   if (int32_t st = validate(p, &plan)) return st;
+  plan.no_alloc = no_alloc;
   const hipStream_t st = p.stream;
   hipError_t e;
+
+  const int64_t total = plan.cells * p.n_bins;
+  char* fixed_ws = nullptr;   // no_alloc: the tiled workspace, then the fixed-point field
+  size_t fixed_off = 0;
+  if (no_alloc) {
+    if (plan.explicit_dirs)
+      return fail(RTMI_ERR_UNSUPPORTED, "explicit directions are uploaded per call, which allocates; "
+                  "this entry point takes the prepared Fibonacci tables only");
+    if (plan.tiled) fixed_off = align256(tiled_layout(p, plan, true, true).total);
+    const size_t need = fixed_off + (plan.det ? align256(size_t(total) * 8 + 16) : 0);
+    if (need > kStaticScratchBytes)
+      return fail(RTMI_ERR_RANGE, "the call needs %zu bytes of scratch, more than the %zu bytes of the "
+                  "static scratch", need, kStaticScratchBytes);
+    if (int32_t rc = static_scratch(&fixed_ws)) return rc;
+  }
 
   // directions: cached Fibonacci tables, or this call's explicit table
   plan.tables.resize(p.n_src);
@@ -1036,16 +1084,16 @@ int32_t run(const Problem& p) {
     for (int32_t s = 0; s < p.n_src; ++s) plan.tables[s] = dt;
   } else {
     for (int32_t s = 0; s < p.n_src; ++s)
-      if (int32_t rc = get_dirs(p.nrays[s], st, &plan.tables[s])) return rc;
+      if (int32_t rc = get_dirs(p.nrays[s], st, &plan.tables[s], !no_alloc)) return rc;
   }
 
   // deterministic mode: fixed-point field and its scale
-  const int64_t total = plan.cells * p.n_bins;
   unsigned long long* out_q = nullptr;
   double* det_scale = nullptr;
   Scratch fixed;
   if (plan.det) {
-    if (int32_t rc = acquire_scratch(size_t(total) * 8 + 16, st, kSlotFixedPoint, &fixed)) return rc;
+    if (no_alloc) fixed.ptr = fixed_ws + fixed_off;
+    else if (int32_t rc = acquire_scratch(size_t(total) * 8 + 16, st, kSlotFixedPoint, &fixed)) return rc;
     out_q = reinterpret_cast<unsigned long long*>(fixed.ptr);
     det_scale = reinterpret_cast<double*>(out_q + total);
     if (!plan.tiled && (e = rtmi::launch_fill_zero_u64(out_q, total, st)) != hipSuccess)
@@ -1053,7 +1101,9 @@ int32_t run(const Problem& p) {
     if ((e = det_scale_launch(p, plan, det_scale)) != hipSuccess) return hip_fail(e, "det_scale");
   }
 
-  const int32_t rc = plan.tiled ? run_tiled(p, plan, out_q, det_scale) : run_direct(p, plan, out_q, det_scale);
+  const int32_t rc = !plan.tiled ? run_direct(p, plan, out_q, det_scale)
+                   : no_alloc ? run_tiled(p, plan, out_q, det_scale, TiledMode::kFull, fixed_ws, nullptr, false)
+                              : run_tiled(p, plan, out_q, det_scale);
   if (rc != RTMI_OK) return rc;
 
   if (plan.det) {
@@ -1462,6 +1512,22 @@ int32_t rtmi_trace_bins(const float* j_maps, int64_t j_bin_stride, const float* 
                   out_fields, opts, static_cast<hipStream_t>(stream)};
   return run(p);
 }
+
+int32_t rtmi_trace_bins_static(const float* j_maps, int64_t j_bin_stride, const float* kappa_maps,
+                               int64_t kappa_bin_stride, const float* kappa_scale, int32_t n_bins,
+                               int32_t nx, int32_t ny, int32_t nz, int32_t n_src,
+                               const float* source_pos, const int32_t* num_rays,
+                               const int32_t* substep_cap, float step_size, float radiation_velocity,
+                               float time_step, float* out_fields, const rtmi_options* opts,
+                               void* stream) {
+  const Problem p{j_maps, j_bin_stride, kappa_maps, kappa_bin_stride,
+                  kappa_bin_stride ? nullptr : kappa_scale, n_bins, nx, ny, nz, n_src,
+                  source_pos, num_rays, substep_cap, step_size, radiation_velocity, time_step,
+                  out_fields, opts, static_cast<hipStream_t>(stream)};
+  return run(p, true);
+}
+
+int64_t rtmi_static_scratch_bytes(void) { return static_cast<int64_t>(kStaticScratchBytes); }
 
 int32_t rtmi_trace_vjp(const float* j_map, const float* kappa_map, int32_t nx, int32_t ny,
                        int32_t nz, int32_t n_src, const float* source_pos,

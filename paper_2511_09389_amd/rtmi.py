@@ -62,6 +62,9 @@ def _load():
         "rtmi_trace_multi": (I32, [P, P, I32, I32, I32, I32, P, P, P, F32, F32, F32, P, P]),
         "rtmi_trace_bins": (I32, [P, I64, P, I64, P, I32, I32, I32, I32, I32, P, P, P, F32, F32,
                                   F32, P, ctypes.POINTER(Options), P]),
+        "rtmi_trace_bins_static": (I32, [P, I64, P, I64, P, I32, I32, I32, I32, I32, P, P, P, F32, F32,
+                                         F32, P, ctypes.POINTER(Options), P]),
+        "rtmi_static_scratch_bytes": (I64, []),
         "rtmi_field_mse": (I32, [P, P, I64, F32, P, P, P]),
         "rtmi_debug_rays": (I32, [P, P, I32, I32, I32, P, I32, F32, F32, F32, I32, P, P, P]),
         "rtmi_trace_vjp": (I32, [P, P, I32, I32, I32, I32, P, P, P, F32, F32, F32, P, P, P, P]),
@@ -229,6 +232,29 @@ def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_ve
     """Frequency bins as a batch axis. j_maps / kappa_maps are 3-D (shared by all bins) or
     4-D [B][nx][ny][nz]; a 3-D kappa with kappa_scale gives kappa_b = kappa * scale[b].
     Returns a [B][nx][ny][nz] float32 tensor."""
+    return _bins_call(lib.rtmi_trace_bins, j_maps, kappa_maps, source_pos, num_rays, step_size,
+                      radiation_velocity, time_step, kappa_scale, substep_cap, out, deterministic,
+                      directions, ray_weight, path, tile_item_chunks, record_capacity)
+
+
+def trace_bins_static(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
+                      time_step, kappa_scale=None, substep_cap=None, out=None, deterministic=False,
+                      path=PATH_TILED, tile_item_chunks=0, record_capacity=0):
+    """trace_bins through rtmi_trace_bins_static, which allocates nothing: its scratch is
+    the library's static per-device array (static_scratch_bytes()). Every N_Omega must have
+    been prepared (prepare()); pass `out` to keep this call free of allocation in torch too."""
+    return _bins_call(lib.rtmi_trace_bins_static, j_maps, kappa_maps, source_pos, num_rays, step_size,
+                      radiation_velocity, time_step, kappa_scale, substep_cap, out, deterministic,
+                      None, 0.0, path, tile_item_chunks, record_capacity)
+
+
+def static_scratch_bytes():
+    return int(lib.rtmi_static_scratch_bytes())
+
+
+def _bins_call(entry, j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
+               time_step, kappa_scale, substep_cap, out, deterministic, directions, ray_weight, path,
+               tile_item_chunks, record_capacity):
     grid = tuple(j_maps.shape[-3:])
     if tuple(kappa_maps.shape[-3:]) != grid:
         raise ValueError("j and kappa grids differ")
@@ -259,7 +285,7 @@ def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_ve
         dirs = _host_f32(directions, 3)
         opts.directions = dirs.ctypes.data
     with torch.cuda.device(j_maps.device):
-        _check(lib.rtmi_trace_bins(
+        _check(entry(
             _dev(j_maps, "j_maps", (3, 4)), cells if (j_maps.dim() == 4 and b_j > 1) else 0,
             _dev(kappa_maps, "kappa_maps", (3, 4)), cells if (kappa_maps.dim() == 4 and b_k > 1) else 0,
             None if scale is None else scale.ctypes.data_as(ctypes.c_void_p), n_bins,
