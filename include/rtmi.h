@@ -372,11 +372,11 @@ int32_t rtmi_debug_rays(const float* j_map, const float* kappa_map,
  * by a pair of HIP events recorded on its launch stream, tallied per kernel kind:
  * RTMI_KERNEL_RECORD (a record dispatch with its segment fix-up, if any),
  * RTMI_KERNEL_TILE (one tile-pass dispatch: one bin of one source launch),
- * RTMI_KERNEL_DIRECT. Reading
+ * RTMI_KERNEL_DIRECT, RTMI_KERNEL_TABLE (the gather-table build of a tiled call). Reading
  * waits for that kind's recorded events, returns the summed elapsed milliseconds and the
  * number of launches since the last enable or read of that kind, and resets them. Do
  * not enable timing while a stream is being captured. */
-enum { RTMI_KERNEL_RECORD = 0, RTMI_KERNEL_TILE = 1, RTMI_KERNEL_DIRECT = 2 };
+enum { RTMI_KERNEL_RECORD = 0, RTMI_KERNEL_TILE = 1, RTMI_KERNEL_DIRECT = 2, RTMI_KERNEL_TABLE = 3 };
 int32_t rtmi_timing_enable(int32_t on);
 int32_t rtmi_timing_read(int32_t kind, double* total_ms, int64_t* launches);
 

@@ -398,7 +398,7 @@ int32_t static_scratch(char** out) {
 std::mutex g_tmu;
 bool g_timing = false;
 using EventPair = std::pair<hipEvent_t, hipEvent_t>;
-std::vector<EventPair> g_pending[3];  // recorded, not yet read
+std::vector<EventPair> g_pending[4];  // recorded, not yet read
 std::vector<EventPair> g_free;
 
 struct TimedLaunch {
@@ -938,8 +938,13 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
     return hip_fail(e, "side stream");
   }
 
-  if (L.interleaved && (e = rtmi::launch_cell_table(p.j, p.kap, med, p.nx, p.ny, p.nz, st)) != hipSuccess)
-    return hip_fail(e, "gather table");
+  if (L.interleaved) {
+    TimedLaunch tl;
+    if ((e = timed_begin(st, RTMI_KERNEL_TABLE, &tl, !plan.no_alloc)) != hipSuccess) return hip_fail(e, "timing");
+    if ((e = rtmi::launch_cell_table(p.j, p.kap, med, p.nx, p.ny, p.nz, st)) != hipSuccess)
+      return hip_fail(e, "gather table");
+    if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
+  }
   {   // every tile launch adds into the zeroed field
     const int64_t total = plan.cells * p.n_bins;
     if (plan.det) e = rtmi::launch_fill_zero_u64(out_q, total, st);
@@ -1765,7 +1770,7 @@ int32_t rtmi_timing_enable(int32_t on) {
 
 int32_t rtmi_timing_read(int32_t kind, double* total_ms, int64_t* launches) {
   if (!total_ms || !launches) return fail(RTMI_ERR_INVALID_ARG, "null output pointer");
-  if (kind < 0 || kind > 2) return fail(RTMI_ERR_INVALID_ARG, "unknown kernel kind %d", kind);
+  if (kind < 0 || kind > 3) return fail(RTMI_ERR_INVALID_ARG, "unknown kernel kind %d", kind);
   std::lock_guard<std::mutex> lock(g_tmu);
   double sum = 0.0;
   for (auto& ev : g_pending[kind]) {

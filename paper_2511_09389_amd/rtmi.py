@@ -29,6 +29,7 @@ PATH_DIRECT = 1
 KERNEL_RECORD = 0
 KERNEL_TILE = 1
 KERNEL_DIRECT = 2
+KERNEL_TABLE = 3
 
 
 class RtmiError(RuntimeError):

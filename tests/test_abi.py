@@ -42,6 +42,23 @@ def test_library_exports_every_declared_symbol(lib):
         assert hasattr(raw, name), name
 
 
+def test_peaks_library_exports_every_declared_symbol():
+    path = os.path.join(ROOT, "paper_2511_09389_amd", "librtmi_peaks.so")
+    if not os.path.exists(path):
+        pytest.fail("librtmi_peaks.so is not built (run __graft_entry__.build())")
+    text = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "rtmi_peaks.h")).read(), flags=re.S)
+    names = sorted(set(re.findall(r"\b(rtmi_peak_[a-z0-9_]+)\s*\(", text)))
+    assert len(names) == 4
+    import torch  # noqa: F401  (its HIP runtime first, as the binding does)
+    raw = ctypes.CDLL(path)
+    for name in names:
+        assert hasattr(raw, name), name
+    # argument checks run before any device call
+    rate = ctypes.c_double(0.0)
+    raw.rtmi_peak_copy.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]
+    assert raw.rtmi_peak_copy(16, 1, ctypes.byref(rate), None) == -1
+
+
 def test_fibonacci_table_is_bitwise_the_oracle_table(lib):
     from paper_2511_09389_amd import rtmi
     for n in (1, 2, 3, 64, 255, 256, 1000, 4096, 16384):
