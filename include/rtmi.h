@@ -88,6 +88,12 @@ typedef struct rtmi_options {
    * (rtmi_dropped_records) can be exercised. 0: the bound. Plans ignore it (they count
    * their records exactly). */
   int64_t record_capacity;
+  /* Tiled path with j and kappa shared by the bins: where the record pass gathers them.
+   * 1: a table built per call holding, per voxel, the eight corners of j and of kappa in
+   * one 64-byte line (one line per sample; 64 bytes of workspace per voxel). 2: the maps
+   * themselves (nine 4-byte loads per sample, no table). 0 picks by the grid size. Changes
+   * the speed, not the field. */
+  int32_t gather_table;
 } rtmi_options;
 
 /* Execution paths (rtmi_options.path). Both compute the same field.

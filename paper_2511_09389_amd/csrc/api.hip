@@ -459,6 +459,7 @@ struct Plan {
   int32_t item_chunks = 0;  // tile work-item size; 0: kItemChunks
   int64_t record_capacity = 0;  // > 0: stateless chunk-record buffers capped (test hook)
   bool no_alloc = false;        // the call may not allocate (static scratch, no events)
+  int32_t gather_table = 0;     // 0 auto, 1 gather j and kappa from the 64-byte table, 2 from the maps
   std::vector<int32_t> nsub;
   std::vector<DevTable> tables;
   double bound_per_unit_j = 0.0;
@@ -506,6 +507,9 @@ int32_t validate(const Problem& p, Plan* plan, bool maps_given = true) {
     if (p.opts->record_capacity < 0)
       return fail(RTMI_ERR_INVALID_ARG, "record_capacity must be >= 0");
     plan->record_capacity = p.opts->record_capacity;
+    if (p.opts->gather_table < 0 || p.opts->gather_table > 2)
+      return fail(RTMI_ERR_INVALID_ARG, "gather_table must be 0, 1 or 2 (got %d)", p.opts->gather_table);
+    plan->gather_table = p.opts->gather_table;
     if (plan->explicit_dirs && p.opts->ray_weight > 0.0f && !std::isfinite(p.opts->ray_weight))
       return fail(RTMI_ERR_NONFINITE, "ray_weight is not finite");
   }
@@ -644,19 +648,46 @@ int64_t row_stride(int32_t nsub) { return (int64_t(nsub) + kRowAlign - 1) / kRow
 
 // ---- tiled path: record + tile per (bin chunk, source chunk) ----
 
-// Workspace of a tiled execution: corner sums, tile schedules (one shared by all launches,
-// or one per launch when a plan keeps them), the interleaved (j, kappa) copy and the
-// recorded rows of the largest launch.
+// Source groups of the tiled path: runs of consecutive sources that one record launch
+// and one tile pass per bin cover. A group ends where its deposit rows would pass
+// kGroupRowBytes (so the workspace stays bounded for thousands of sources) or at
+// kMaxSrcPerTiledLaunch sources.
+constexpr int64_t kGroupRowBytes = int64_t(4) << 30;
+
+struct SourceGroup {
+  int32_t s0 = 0, ns = 0;
+};
+
+std::vector<SourceGroup> source_groups(const Problem& p, const Plan& plan) {
+  const int64_t nb = std::min(kMaxBinsPerLaunch, p.n_bins);
+  std::vector<SourceGroup> g;
+  int64_t bytes = 0;
+  for (int32_t s = 0; s < p.n_src; ++s) {
+    const int64_t b = plan.nsub[s] > 0 ? int64_t(p.nrays[s]) * row_stride(plan.nsub[s]) * nb * 4 : 0;
+    if (g.empty() || (g.back().ns > 0 && bytes + b > kGroupRowBytes) || g.back().ns >= rtmi::kMaxSrcPerTiledLaunch) {
+      g.push_back({s, 0});
+      bytes = 0;
+    }
+    g.back().ns += 1;
+    bytes += b;
+  }
+  return g;
+}
+
+// Workspace of a tiled execution: corner sums, the device source table, tile schedules
+// (one shared by all launches, or one per launch when a plan keeps them), the
+// interleaved (j, kappa) copy and the recorded rows of the largest launch.
 struct TiledLayout {
   int tiles_x = 0, tiles_y = 0, tiles_z = 0, tiles = 0;
   int n_launch = 0;
   bool interleaved = false;
-  size_t corner = 0, sched = 0, med = 0, v = 0, p = 0, segtot = 0, recs = 0, total = 0;   // byte offsets / size
+  size_t corner = 0, srcs = 0, sched = 0, med = 0, v = 0, p = 0, segtot = 0, recs = 0, total = 0;   // byte offsets / size
   size_t sched_bytes = 0;
   int pair_blocks = 0;        // most pair blocks of any launch
   int64_t rec_capacity = 0;   // chunk records of each shared buffer (0: a plan's own slices)
   int rec_buffers = 1;        // shared buffers: two when several launches alternate
-  std::vector<int> seg_len;   // per source chunk: substeps per record run (0: whole rays)
+  std::vector<SourceGroup> groups;
+  std::vector<int> seg_len;   // per source group: substeps per record run (0: whole rays)
 };
 
 // Substeps per record run for a launch of `rays` rays of at most max_nsub substeps: the
@@ -682,18 +713,26 @@ int record_run_length(int64_t rays, int32_t max_nsub) {
 
 constexpr size_t kCornerBytes = 256;   // [4][8] floats, then (next 256 B) [4][8] u64
 
+// The 64-byte-per-voxel gather table measured faster than gathering from the maps at
+// every grid size tried (128^3: record pass 0.13 vs 0.43 ms; 256^3, where the table no
+// longer fits the Infinity Cache: 1.06 vs 2.05 ms).
+bool use_gather_table(const Plan& plan) {
+  if (plan.gather_table != 0) return plan.gather_table == 1;
+  return true;
+}
+
 TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_launch, bool shared_records) {
   TiledLayout L;
   L.tiles_x = (p.nx + kTile - 1) / kTile;
   L.tiles_y = (p.ny + kTile - 1) / kTile;
   L.tiles_z = (p.nz + kTile - 1) / kTile;
   L.tiles = L.tiles_x * L.tiles_y * L.tiles_z;
+  L.groups = source_groups(p, plan);
   int64_t v_elems_max = 0, p_elems_max = 0, t_elems_max = 0;
-  int src_chunks = 0;
-  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch, ++src_chunks) {
+  for (const SourceGroup& g : L.groups) {
     int64_t e = 0, rays = 0;
     int32_t max_nsub = 0;
-    for (int32_t s = s0; s < std::min(p.n_src, s0 + kMaxSrcPerLaunch); ++s)
+    for (int32_t s = g.s0; s < g.s0 + g.ns; ++s)
       if (plan.nsub[s] > 0) {
         e += int64_t(p.nrays[s]) * row_stride(plan.nsub[s]);
         rays += p.nrays[s];
@@ -702,25 +741,25 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
     const int len = record_run_length(rays, max_nsub);
     L.seg_len.push_back(len);
     if (shared_records)
-      L.rec_capacity = std::max(L.rec_capacity, record_bound(p, plan, s0, std::min(kMaxSrcPerLaunch, p.n_src - s0),
-                                                             L.tiles_x, L.tiles_y, L.tiles_z));
-    L.pair_blocks = std::max(L.pair_blocks, pair_blocks(p, plan, s0, std::min(kMaxSrcPerLaunch, p.n_src - s0)));
+      L.rec_capacity = std::max(L.rec_capacity, record_bound(p, plan, g.s0, g.ns, L.tiles_x, L.tiles_y, L.tiles_z));
+    L.pair_blocks = std::max(L.pair_blocks, pair_blocks(p, plan, g.s0, g.ns));
     int64_t t = 0;
     if (len > 0)
-      for (int32_t s = s0; s < std::min(p.n_src, s0 + kMaxSrcPerLaunch); ++s)
+      for (int32_t s = g.s0; s < g.s0 + g.ns; ++s)
         if (plan.nsub[s] > 0) t += int64_t(p.nrays[s]) * ((plan.nsub[s] + len - 1) / len);
     v_elems_max = std::max(v_elems_max, e);
     p_elems_max = std::max(p_elems_max, len > 0 ? e : int64_t(0));
     t_elems_max = std::max(t_elems_max, t);
   }
   if (shared_records && plan.record_capacity > 0) L.rec_capacity = std::min(L.rec_capacity, plan.record_capacity);
-  L.n_launch = src_chunks * ((p.n_bins + kMaxBinsPerLaunch - 1) / kMaxBinsPerLaunch);
+  L.n_launch = static_cast<int>(L.groups.size()) * ((p.n_bins + kMaxBinsPerLaunch - 1) / kMaxBinsPerLaunch);
   const int32_t nb_max = std::min(kMaxBinsPerLaunch, p.n_bins);
   // a shared j and a shared (scaled) kappa are gathered from one interleaved copy
-  L.interleaved = p.j_stride == 0 && p.k_stride == 0;
+  L.interleaved = p.j_stride == 0 && p.k_stride == 0 && use_gather_table(plan);
   L.sched_bytes = TileSchedule::bytes(L.tiles, L.pair_blocks);
   L.corner = 0;
-  L.sched = 2 * kCornerBytes;
+  L.srcs = 2 * kCornerBytes;
+  L.sched = L.srcs + align256(size_t(p.n_src) * sizeof(rtmi::SrcRec));
   L.med = L.sched + L.sched_bytes * (sched_per_launch ? L.n_launch : 1);
   L.v = L.med + (L.interleaved ? align256(size_t(plan.cells) * 4 * sizeof(float4)) : 0);
   L.p = L.v + align256(size_t(v_elems_max) * nb_max * sizeof(float));
@@ -729,6 +768,102 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
   L.rec_buffers = L.n_launch > 1 ? 2 : 1;
   L.total = L.recs + size_t(L.rec_buffers) * align256(size_t(L.rec_capacity) * sizeof(uint2));
   return L;
+}
+
+// A source group's device table in record-block order: sources are given to the XCDs
+// greedily by cost (longest processing time first: blocks x substeps per block), and each
+// XCD's sources run most costly first. Fills the table entries (without tmax and marg,
+// which the device completes), the XCD group bounds of the record launch, and the pairs
+// and fix-up totals of the group.
+struct GroupTable {
+  std::vector<rtmi::SrcRec> rec;
+  int xcd_src[rtmi::kXcds + 1] = {0};
+  int xcd_blocks[rtmi::kXcds] = {0};
+  int n_pairs = 0, fix_waves = 0;
+  int64_t v_elems = 0, t_elems = 0;
+};
+
+GroupTable group_table(const Problem& p, const Plan& plan, const SourceGroup& g, int seg_len) {
+  constexpr int X = rtmi::kXcds;
+  struct Item {
+    int32_t s;
+    int blocks;
+    int64_t cost;
+  };
+  std::vector<Item> items;
+  for (int32_t s = g.s0; s < g.s0 + g.ns; ++s) {
+    const int32_t nr = plan.nsub[s] > 0 ? p.nrays[s] : 0;
+    const int nseg = (seg_len > 0 && nr > 0) ? (plan.nsub[s] + seg_len - 1) / seg_len : 1;
+    const int blocks = nseg * ((nr + kBlock - 1) / kBlock);
+    const int per_block = seg_len > 0 ? std::min(seg_len, plan.nsub[s]) : plan.nsub[s];
+    items.push_back({s, blocks, int64_t(blocks) * per_block});
+  }
+  std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+  std::vector<std::vector<Item>> per_xcd(X);
+  int64_t load[X] = {0};
+  for (const Item& it : items) {
+    const int x = static_cast<int>(std::min_element(load, load + X) - load);
+    per_xcd[x].push_back(it);
+    load[x] += it.cost;
+  }
+  GroupTable T;
+  int pairs = 0, fix = 0;
+  for (int x = 0; x < X; ++x) {
+    T.xcd_src[x] = static_cast<int>(T.rec.size());
+    // each XCD's blocks most costly first: sort by the cost of one block
+    std::stable_sort(per_xcd[x].begin(), per_xcd[x].end(), [&](const Item& a, const Item& b) {
+      return plan.nsub[a.s] > plan.nsub[b.s];
+    });
+    int blk = 0;
+    for (const Item& it : per_xcd[x]) {
+      const int32_t s = it.s;
+      const int32_t nr = plan.nsub[s] > 0 ? p.nrays[s] : 0;
+      const int nseg = (seg_len > 0 && nr > 0) ? (plan.nsub[s] + seg_len - 1) / seg_len : 1;
+      rtmi::SrcRec r;
+      std::memset(&r, 0, sizeof r);
+      r.sx = p.src[3 * s];
+      r.sy = p.src[3 * s + 1];
+      r.sz = p.src[3 * s + 2];
+      r.wray = ray_weight(p, plan, s);
+      r.nrays = nr;
+      r.nsub = plan.nsub[s];
+      r.vbase = T.v_elems;
+      r.sbase = T.t_elems;
+      r.dirs = plan.tables[s].dirs;
+      r.pbounds = plan.tables[s].bounds;
+      r.blk_begin = blk;
+      r.pbegin = pairs;
+      r.nseg = nseg;
+      r.fbegin = fix;
+      T.rec.push_back(r);
+      blk += it.blocks;
+      pairs += (nr + kPatch - 1) / kPatch;
+      fix += nr * (nseg - 1);
+      T.v_elems += int64_t(nr) * row_stride(plan.nsub[s]);
+      T.t_elems += int64_t(nr) * nseg;
+    }
+    T.xcd_blocks[x] = blk;
+  }
+  T.xcd_src[X] = static_cast<int>(T.rec.size());
+  T.n_pairs = pairs;
+  T.fix_waves = fix;
+  return T;
+}
+
+// Writes a group's table at table[first ..] in launches of kSrcPerWrite entries.
+hipError_t write_group_table(const GroupTable& T, rtmi::SrcRec* table, float ds, hipStream_t st) {
+  for (size_t i0 = 0; i0 < T.rec.size(); i0 += rtmi::kSrcPerWrite) {
+    rtmi::SrcWrite w;
+    std::memset(&w, 0, sizeof w);
+    w.count = static_cast<int>(std::min<size_t>(rtmi::kSrcPerWrite, T.rec.size() - i0));
+    for (int i = 0; i < w.count; ++i) w.rec[i] = T.rec[i0 + i];
+    w.table = table;
+    w.first = static_cast<int>(i0);
+    w.ds = ds;
+    const hipError_t e = rtmi::launch_write_sources(w, st);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 // What the tiled path enqueues: kFull (schedules and records computed in line, the
@@ -825,47 +960,40 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
   float2* segtot = reinterpret_cast<float2*>(ws + L.segtot);
   hipError_t e;
 
+  // the device source tables: one per source group, written in every mode that computes
+  // schedules (a plan's replays reuse the ones written at its creation)
+  rtmi::SrcRec* srcs = reinterpret_cast<rtmi::SrcRec*>(ws + L.srcs);
+  std::vector<GroupTable> tables;
+  for (size_t gi = 0; gi < L.groups.size(); ++gi) tables.push_back(group_table(p, plan, L.groups[gi], L.seg_len[gi]));
+  if (mode == TiledMode::kFull || mode == TiledMode::kSchedule)
+    for (size_t gi = 0; gi < L.groups.size(); ++gi)
+      if ((e = write_group_table(tables[gi], srcs + L.groups[gi].s0, p.ds, st)) != hipSuccess)
+        return hip_fail(e, "source table");
+
   std::vector<LaunchArgs> launches;
   int launch = 0;
   for (int32_t b0 = 0; b0 < p.n_bins; b0 += kMaxBinsPerLaunch) {
     const int32_t nb = std::min(kMaxBinsPerLaunch, p.n_bins - b0);
-    for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch, ++launch) {
-      const int32_t ns = std::min(kMaxSrcPerLaunch, p.n_src - s0);
+    for (size_t gi = 0; gi < L.groups.size(); ++gi, ++launch) {
+      const GroupTable& T = tables[gi];
+      const rtmi::SrcRec* gsrc = srcs + L.groups[gi].s0;
       rtmi::RecordArgs r;
       rtmi::TileArgs t;
       std::memset(&r, 0, sizeof r);
       std::memset(&t, 0, sizeof t);
-      int64_t v_elems = 0, t_elems = 0;
-      int blocks = 0, patches = 0, fix_waves = 0;
-      const int seg_len = L.seg_len[s0 / kMaxSrcPerLaunch];
-      r.seg_len = seg_len;
-      for (int32_t i = 0; i < ns; ++i) {
-        const int32_t s = s0 + i;
-        const int32_t nr = plan.nsub[s] > 0 ? p.nrays[s] : 0;
-        const int nseg = (seg_len > 0 && nr > 0) ? (plan.nsub[s] + seg_len - 1) / seg_len : 1;
-        r.blk_begin[i] = blocks;
-        r.fbegin[i] = fix_waves;
-        r.nseg[i] = nseg;
-        r.sbase[i] = t_elems;
-        t_elems += int64_t(nr) * nseg;
-        fix_waves += nr * (nseg - 1);
-        t.pbegin[i] = patches;
-        r.sx[i] = t.sx[i] = p.src[3 * s];
-        r.sy[i] = t.sy[i] = p.src[3 * s + 1];
-        r.sz[i] = t.sz[i] = p.src[3 * s + 2];
-        r.wray[i] = ray_weight(p, plan, s);
-        r.nrays[i] = t.nrays[i] = nr;
-        r.nsub[i] = t.nsub[i] = plan.nsub[s];
-        r.vbase[i] = t.vbase[i] = v_elems;
-        r.dirs[i] = t.dirs[i] = plan.tables[s].dirs;
-        t.pbounds[i] = plan.tables[s].bounds;
-        v_elems += int64_t(nr) * row_stride(plan.nsub[s]);
-        blocks += nseg * ((nr + kBlock - 1) / kBlock);
-        patches += (nr + kPatch - 1) / kPatch;
+      int blocks = 0;
+      for (int x = 0; x < rtmi::kXcds; ++x) {
+        r.xcd_src[x] = T.xcd_src[x];
+        r.xcd_blocks[x] = T.xcd_blocks[x];
+        blocks += T.xcd_blocks[x];
       }
-      r.blk_begin[ns] = blocks;
-      r.fbegin[ns] = fix_waves;
-      t.pbegin[ns] = patches;
+      r.xcd_src[rtmi::kXcds] = T.xcd_src[rtmi::kXcds];
+      r.src = t.src = gsrc;
+      r.n_src = t.n_src = L.groups[gi].ns;
+      t.n_pairs = T.n_pairs;
+      const int seg_len = L.seg_len[gi];
+      r.seg_len = seg_len;
+      r.fix_waves = T.fix_waves;
       r.P = seg_len > 0 ? Prow : nullptr;
       r.segtot = seg_len > 0 ? segtot : nullptr;
       r.med = med;
@@ -876,7 +1004,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       for (int32_t b = 0; b < nb; ++b) r.kscale[b] = p.kscale ? p.kscale[b0 + b] : 1.0f;
       r.V = V;
       t.V = V;
-      r.v_bin_stride = t.v_bin_stride = v_elems;
+      r.v_bin_stride = t.v_bin_stride = T.v_elems;
       r.corner = corner;
       r.corner_q = corner_q;
       t.corner = corner;
@@ -886,7 +1014,6 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       r.ny = t.ny = p.ny;
       r.nz = t.nz = p.nz;
       r.ds = t.ds = p.ds;
-      r.n_src = t.n_src = ns;
       t.out = p.out ? p.out + b0 * plan.cells : nullptr;
       t.out_q = out_q ? out_q + b0 * plan.cells : nullptr;
       t.out_stride = plan.cells;
@@ -902,7 +1029,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
                     reinterpret_cast<uint2*>(ws + L.recs + (launch % L.rec_buffers) *
                                                                align256(size_t(L.rec_capacity) * sizeof(uint2))),
                     L.rec_capacity, dropped);
-      launches.push_back({r, t, nb, blocks, fix_waves});
+      launches.push_back({r, t, nb, blocks, T.fix_waves});
     }
   }
 
@@ -1158,7 +1285,8 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
     max_blocks = std::max(max_blocks, pair_blocks(p, plan, s0, std::min(kMaxSrcPerLaunch, p.n_src - s0)));
   }
   const size_t sched_bytes = TileSchedule::bytes(tiles, max_blocks);
-  const size_t rec_off = corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes) + sched_bytes;
+  const size_t srcs_bytes = align256(size_t(kMaxSrcPerLaunch) * sizeof(rtmi::SrcRec));
+  const size_t rec_off = corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes) + sched_bytes + srcs_bytes;
   unsigned long long* dropped = nullptr;
   if (int32_t rc = dropped_counter(&dropped)) return rc;
   Scratch scratch;
@@ -1168,6 +1296,7 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
   TileSchedule sched;
   sched.carve(ws + corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes), tiles, max_blocks);
   uint2* recs = reinterpret_cast<uint2*>(ws + rec_off);
+  rtmi::SrcRec* srcs = reinterpret_cast<rtmi::SrcRec*>(ws + rec_off - srcs_bytes);
   float* corner = reinterpret_cast<float*>(ws);  // [0..7] for dL/dj, [8..15] for dL/dkappa
   float4* med = reinterpret_cast<float4*>(ws + corner_bytes);
   float* Vj = reinterpret_cast<float*>(ws + corner_bytes + med_bytes);
@@ -1188,29 +1317,44 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
     std::memset(&t, 0, sizeof t);
     int64_t v_elems = 0, c_elems = 0;
     int blocks = 0, patches = 0;
+    GroupTable T;   // the tile passes' source table, in launch order
     for (int32_t i = 0; i < ns; ++i) {
       const int32_t s = s0 + i;
       const int32_t nr = plan.nsub[s] > 0 ? p.nrays[s] : 0;
       r.blk_begin[i] = blocks;
-      t.pbegin[i] = patches;
-      r.sx[i] = t.sx[i] = p.src[3 * s];
-      r.sy[i] = t.sy[i] = p.src[3 * s + 1];
-      r.sz[i] = t.sz[i] = p.src[3 * s + 2];
+      r.sx[i] = p.src[3 * s];
+      r.sy[i] = p.src[3 * s + 1];
+      r.sz[i] = p.src[3 * s + 2];
       r.wray[i] = ray_weight(p, plan, s);
-      r.nrays[i] = t.nrays[i] = nr;
-      r.nsub[i] = t.nsub[i] = plan.nsub[s];
-      r.vbase[i] = t.vbase[i] = v_elems;
+      r.nrays[i] = nr;
+      r.nsub[i] = plan.nsub[s];
+      r.vbase[i] = v_elems;
       r.cstride[i] = (plan.nsub[s] + rtmi::kSeg - 1) / rtmi::kSeg;
       r.cbase[i] = c_elems;
-      r.dirs[i] = t.dirs[i] = plan.tables[s].dirs;
-      t.pbounds[i] = plan.tables[s].bounds;
+      r.dirs[i] = plan.tables[s].dirs;
+      rtmi::SrcRec q;
+      std::memset(&q, 0, sizeof q);
+      q.sx = r.sx[i];
+      q.sy = r.sy[i];
+      q.sz = r.sz[i];
+      q.wray = r.wray[i];
+      q.nrays = nr;
+      q.nsub = plan.nsub[s];
+      q.vbase = v_elems;
+      q.dirs = plan.tables[s].dirs;
+      q.pbounds = plan.tables[s].bounds;
+      q.pbegin = patches;
+      q.nseg = 1;
+      T.rec.push_back(q);
       v_elems += int64_t(nr) * row_stride(plan.nsub[s]);
       c_elems += int64_t(nr) * r.cstride[i];
       blocks += (nr + kBlock - 1) / kBlock;
       patches += (nr + kPatch - 1) / kPatch;
     }
     r.blk_begin[ns] = blocks;
-    t.pbegin[ns] = patches;
+    if ((e = write_group_table(T, srcs, p.ds, st)) != hipSuccess) return hip_fail(e, "source table");
+    t.src = srcs;
+    t.n_pairs = patches;
     r.med = med;
     r.grad = grad;
     r.Vj = Vj;

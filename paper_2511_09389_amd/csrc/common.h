@@ -46,6 +46,35 @@ struct MarchArgs {
   const float4* dirs[kMaxSrcPerLaunch];
 };
 
+// One source of a tiled launch as the record and tile kernels read it, from a table in
+// the launch's workspace (so that one launch can cover any number of sources). The table
+// is written on the device by launch_write_sources from host data passed by value, which
+// keeps a call free of host-to-device copies (and capturable in a graph).
+struct alignas(16) SrcRec {
+  float sx, sy, sz;           // position
+  float tmax;                 // distance of the last substep (written on the device)
+  float marg;                 // tile-geometry position margin (written on the device)
+  float wray;                 // ray weight, 4 pi / N_Omega
+  int nrays, nsub;            // rays (0 when N_s = 0), substeps
+  long long vbase;            // workspace row base of the source's rays
+  long long sbase;            // segment mode: first run end state of the source
+  const float4* dirs;         // directions, one float4 per ray
+  const float* pbounds;       // per 64-ray patch: kPatchRec floats (bounds and cone)
+  int blk_begin;              // first record block, counted within the source's XCD group
+  int pbegin;                 // first (source, patch) pair of the source in the launch
+  int nseg;                   // segment mode: runs per ray
+  int fbegin;                 // segment mode: first fix-up wave
+};
+
+constexpr int kSrcPerWrite = 24;    // sources one table-writing launch carries by value
+struct SrcWrite {
+  SrcRec rec[kSrcPerWrite];
+  SrcRec* table;              // destination: table[first + i] = rec[i]
+  int first, count;
+  float ds;
+};
+constexpr int kMaxSrcPerTiledLaunch = 1 << 13;   // the chunk records hold 13 bits of source
+
 // Phase 1 of the two-phase march: per-ray recurrence, deposit values to the workspace.
 struct RecordArgs {
   const float4* med;          // gather table (8 corners of j, then of kappa, per voxel), or null
@@ -61,25 +90,23 @@ struct RecordArgs {
   const double* det_scale;
   int nx, ny, nz;
   float ds;
+  // The launch's sources, grouped by the XCD their record blocks run on: work-group i
+  // runs on XCD i mod kXcds and takes block i / kXcds of that XCD's group, whose sources
+  // are src[xcd_src[x] .. xcd_src[x + 1]) with xcd_blocks[x] blocks in all, most costly
+  // first.
+  const SrcRec* src;
   int n_src;
-  int blk_begin[kMaxSrcPerLaunch + 1];
-  float sx[kMaxSrcPerLaunch], sy[kMaxSrcPerLaunch], sz[kMaxSrcPerLaunch];
-  float wray[kMaxSrcPerLaunch];
-  int nrays[kMaxSrcPerLaunch];
-  int nsub[kMaxSrcPerLaunch];
-  long long vbase[kMaxSrcPerLaunch];
-  const float4* dirs[kMaxSrcPerLaunch];
+  int xcd_src[kXcds + 1];
+  int xcd_blocks[kXcds];
   // Segments: with seg_len > 0 each ray's substeps are cut into runs of seg_len (a
   // multiple of kRowAlign) marched by separate lanes from I = 0, E = 1. Eq. (2) is linear
   // in the entry state (I0, E0): I_k = I0 P_k + E0 Q_k with P, Q the run's values from
   // (0, 1), so a later pass (fixup) turns the stored wray Q_k and P_k into the deposit
   // values once the runs' end states are chained.
   int seg_len;                // 0: whole rays
-  int nseg[kMaxSrcPerLaunch]; // runs per ray
+  int fix_waves;              // fix-up waves of the launch (sum of nrays (nseg - 1))
   float* P;                   // rows like V: P_k of runs after the first
   float2* segtot;             // [(sbase + ray * nseg + run) * NB + bin]: (Q, P) at the run's end
-  long long sbase[kMaxSrcPerLaunch];
-  int fbegin[kMaxSrcPerLaunch + 1];  // prefix sums over sources of nrays * (nseg - 1)
 };
 
 // Phase 2: tile-owned accumulation of the recorded deposit values.
@@ -95,7 +122,9 @@ struct TileArgs {
   int nx, ny, nz;
   int tiles_x, tiles_y, tiles_z;
   float ds;
+  const SrcRec* src;              // the launch's sources (any order)
   int n_src;
+  int n_pairs;                    // (source, 64-ray patch) pairs of the launch
   // Schedule, written by the cost, schedule and fill kernels and read by the tile kernel
   // (the field must be zeroed before the tile kernel adds into it).
   unsigned long long* tile_cost;  // [tiles] chunks per tile
@@ -112,13 +141,6 @@ struct TileArgs {
   int* item_next;                 // next unclaimed work item
   int* item_done;                 // work-groups finished (the last one rewinds the counters)
   int item_chunks;                // target chunk records per work item
-  int pbegin[kMaxSrcPerLaunch + 1];  // prefix sums of patch counts over sources
-  float sx[kMaxSrcPerLaunch], sy[kMaxSrcPerLaunch], sz[kMaxSrcPerLaunch];
-  int nrays[kMaxSrcPerLaunch];
-  int nsub[kMaxSrcPerLaunch];
-  long long vbase[kMaxSrcPerLaunch];
-  const float4* dirs[kMaxSrcPerLaunch];
-  const float* pbounds[kMaxSrcPerLaunch];  // per patch: kPatchRec floats (bounds and cone)
 };
 
 // Adjoint of the march: per-ray reverse sweep with checkpointed recomputation.
@@ -222,6 +244,8 @@ hipError_t launch_field_mse(const float* field, const float* target, long long n
 // Gather table of j and kappa (64 bytes per voxel) for the record and adjoint kernels.
 hipError_t launch_cell_table(const float* j, const float* kap, float4* table, int nx, int ny, int nz,
                              hipStream_t s);
+// Writes w.rec[0 .. count) to w.table[first ..), completing tmax and marg.
+hipError_t launch_write_sources(const SrcWrite& w, hipStream_t s);
 hipError_t launch_fill_zero(float* p, long long n, hipStream_t s);
 hipError_t launch_fill_zero_u64(unsigned long long* p, long long n, hipStream_t s);
 // scale_out[0] = the fixed-point scale, a power of two with bound * scale <= 2^62, where

@@ -71,28 +71,36 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
   }
   __syncthreads();
 
-  // Work-group i runs on XCD i mod 8; give each XCD a contiguous run of logical blocks
-  // (whole sources) so that one source's rays share that XCD's L2.
-  const int nblk = a.blk_begin[a.n_src];
-  const int per_xcd = (nblk + kXcds - 1) / kXcds;
-  const int blk = (static_cast<int>(blockIdx.x) % kXcds) * per_xcd + static_cast<int>(blockIdx.x) / kXcds;
-  int s = 0;
-  while (s + 1 < a.n_src && blk >= a.blk_begin[s + 1]) ++s;
+  // Work-group i runs on XCD i mod kXcds and takes the (i / kXcds)-th block of that XCD's
+  // group of sources (their rays then share the XCD's L2), most costly blocks first.
+  const int xcd = static_cast<int>(blockIdx.x) % kXcds;
+  const int blk = static_cast<int>(blockIdx.x) / kXcds;
+  const bool have = blk < a.xcd_blocks[xcd];
+  SrcRec S{};
+  if (have) {   // the group's last source whose first block is <= blk
+    int lo = a.xcd_src[xcd], hi = a.xcd_src[xcd + 1];
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.src[mid].blk_begin <= blk) lo = mid;
+      else hi = mid;
+    }
+    S = a.src[lo];
+  }
   // blocks of a source: run-major, then ray blocks
-  const int rblocks = (a.nrays[s] + kBlock - 1) / kBlock;
-  const int seg = (a.seg_len > 0 && rblocks > 0) ? (blk - a.blk_begin[s]) / rblocks : 0;
-  const int ray = ((blk - a.blk_begin[s]) - seg * rblocks) * kBlock + tid;
-  if (blk < nblk && ray < a.nrays[s]) {
-    const float4 d = a.dirs[s][ray];
-    const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
-    const float wray = a.wray[s];
+  const int rblocks = (S.nrays + kBlock - 1) / kBlock;
+  const int seg = (a.seg_len > 0 && rblocks > 0) ? (blk - S.blk_begin) / rblocks : 0;
+  const int ray = ((blk - S.blk_begin) - seg * rblocks) * kBlock + tid;
+  if (have && ray < S.nrays) {
+    const float4 d = S.dirs[ray];
+    const float sx = S.sx, sy = S.sy, sz = S.sz;
+    const float wray = S.wray;
     const int k_begin = a.seg_len > 0 ? seg * a.seg_len : 0;
-    const int nsub = a.seg_len > 0 ? min(a.nsub[s], k_begin + a.seg_len) : a.nsub[s];   // run end
+    const int nsub = a.seg_len > 0 ? min(S.nsub, k_begin + a.seg_len) : S.nsub;   // run end
     const float ds = a.ds;
     const int nx = a.nx, ny = a.ny, nz = a.nz, nyz = ny * nz;
     const bool shared_k = (a.k_stride == 0);
-    const long long vb = a.vbase[s];
-    const int vn = a.nrays[s];
+    const long long vb = S.vbase;
+    const int vn = S.nrays;
     // runs after the first keep their attenuation P_k, and their samples collapsed onto a
     // box corner are summed by the fixup, which knows the entry state
     float* prow = seg > 0 ? a.P : nullptr;
@@ -278,7 +286,7 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
       }
     }
     if (a.seg_len > 0) {   // the run's end state, in units of wray for Q
-      float2* st = a.segtot + (a.sbase[s] + static_cast<long long>(ray) * a.nseg[s] + seg) * NB;
+      float2* st = a.segtot + (S.sbase + static_cast<long long>(ray) * S.nseg + seg) * NB;
 #pragma unroll
       for (int b = 0; b < NB; ++b) st[b] = make_float2(I[b], E[b]);
     }
@@ -320,13 +328,18 @@ __global__ void __launch_bounds__(kFixupThreads) fixup_kernel(const RecordArgs a
   }
   __syncthreads();
   const int w = static_cast<int>(blockIdx.x) * (kFixupThreads / 64) + (tid >> 6);
-  if (w < a.fbegin[a.n_src]) {
-    int s = 0;
-    while (s + 1 < a.n_src && w >= a.fbegin[s + 1]) ++s;
-    const int local = w - a.fbegin[s];
-    const int nrays = a.nrays[s];
+  if (w < a.fix_waves) {
+    int lo = 0, hi = a.n_src;   // the last source whose first fix-up wave is <= w
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.src[mid].fbegin <= w) lo = mid;
+      else hi = mid;
+    }
+    const SrcRec S = a.src[lo];
+    const int local = w - S.fbegin;
+    const int nrays = S.nrays;
     const int seg = 1 + local / nrays, ray = local % nrays;
-    const float2* st = a.segtot + (a.sbase[s] + static_cast<long long>(ray) * a.nseg[s]) * NB;
+    const float2* st = a.segtot + (S.sbase + static_cast<long long>(ray) * S.nseg) * NB;
     float I0[NB], E0[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -341,11 +354,11 @@ __global__ void __launch_bounds__(kFixupThreads) fixup_kernel(const RecordArgs a
         E0[b] = E0[b] * qp.y;
       }
     }
-    const float wray = a.wray[s];
-    const float4 d = a.dirs[s][ray];
-    const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
-    const int k_begin = seg * a.seg_len, k_end = min(a.nsub[s], k_begin + a.seg_len);
-    const long long vb = a.vbase[s];
+    const float wray = S.wray;
+    const float4 d = S.dirs[ray];
+    const float sx = S.sx, sy = S.sy, sz = S.sz;
+    const int k_begin = seg * a.seg_len, k_end = min(S.nsub, k_begin + a.seg_len);
+    const long long vb = S.vbase;
     double det_scale = 0.0;
     if constexpr (DET) det_scale = *a.det_scale;
     for (int k = k_begin + lane; k < k_end; k += 64) {
@@ -481,40 +494,13 @@ __device__ __forceinline__ TileGeom tile_geom(const TileArgs& a, int t) {
   return g;
 }
 
-// The launch's sources, staged in LDS once per work-group (the kernel-argument arrays
-// would otherwise be read with per-lane indices).
-struct SrcTable {
-  float4 pos[kMaxSrcPerLaunch];   // x, y, z, distance of the last substep
-  float marg[kMaxSrcPerLaunch];   // position tolerance: rounding of x_k and of 1/n
-  int pbegin[kMaxSrcPerLaunch + 1];
-  int nsub[kMaxSrcPerLaunch];
-  int nrays[kMaxSrcPerLaunch];
-  const float* pbounds[kMaxSrcPerLaunch];
-  const float4* dirs[kMaxSrcPerLaunch];
-  long long vbase[kMaxSrcPerLaunch];   // workspace row base of the source's rays
-};
-
-__device__ __forceinline__ void load_sources(const TileArgs& a, SrcTable& S, int tid) {
-  if (tid < a.n_src) {
-    const float sx = a.sx[tid], sy = a.sy[tid], sz = a.sz[tid];
-    const float tmax = sample_distance(a.nsub[tid] - 1, a.ds);
-    S.pos[tid] = make_float4(sx, sy, sz, tmax);
-    S.marg[tid] = 5.0e-7f * (fmaxf(fabsf(sx), fmaxf(fabsf(sy), fabsf(sz))) + tmax + 2.0f) + 1.0e-6f;
-    S.nsub[tid] = a.nsub[tid];
-    S.nrays[tid] = a.nrays[tid];
-    S.pbounds[tid] = a.pbounds[tid];
-    S.dirs[tid] = a.dirs[tid];
-    S.vbase[tid] = a.vbase[tid];
-  }
-  if (tid <= a.n_src) S.pbegin[tid] = a.pbegin[tid];
-}
-
-// Source s of pair p: pbegin[s] <= p < pbegin[s + 1].
-__device__ __forceinline__ int pair_source(const SrcTable& S, int n_src, int p) {
-  int lo = 0, hi = n_src;
+// Source s of pair p: the last source whose first pair is <= p (sources without rays
+// share their successor's first pair).
+__device__ __forceinline__ int pair_source(const TileArgs& a, int p) {
+  int lo = 0, hi = a.n_src;
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
-    if (S.pbegin[mid] <= p) lo = mid;
+    if (a.src[mid].pbegin <= p) lo = mid;
     else hi = mid;
   }
   return lo;
@@ -523,11 +509,10 @@ __device__ __forceinline__ int pair_source(const SrcTable& S, int n_src, int p) 
 // Can a ray of patch `patch` of source s reach the tile? The bounding box of the patch's
 // segments [0, tmax] (its direction bounds are exact), then, for interior tiles, the
 // cone holding the patch's directions against the sphere around the widened tile.
-__device__ __forceinline__ bool pair_reaches(const TileArgs& a, const SrcTable& S, const TileGeom& g,
-                                             int s, int patch) {
-  const float4 P = S.pos[s];
-  const float sx = P.x, sy = P.y, sz = P.z, tmax = P.w, m = S.marg[s];
-  const float* pb = S.pbounds[s] + static_cast<long long>(patch) * kPatchRec;
+__device__ __forceinline__ bool pair_reaches(const TileArgs& a, const TileGeom& g, int s, int patch) {
+  const SrcRec& S = a.src[s];
+  const float sx = S.sx, sy = S.sy, sz = S.sz, tmax = S.tmax, m = S.marg;
+  const float* pb = S.pbounds + static_cast<long long>(patch) * kPatchRec;
   bool reach = !(sx + fmaxf(0.0f, tmax * pb[3]) + m < g.Ax || sx + fminf(0.0f, tmax * pb[0]) - m >= g.Bx ||
                  sy + fmaxf(0.0f, tmax * pb[4]) + m < g.Ay || sy + fminf(0.0f, tmax * pb[1]) - m >= g.By ||
                  sz + fmaxf(0.0f, tmax * pb[5]) + m < g.Az || sz + fminf(0.0f, tmax * pb[2]) - m >= g.Bz);
@@ -555,16 +540,16 @@ __device__ __forceinline__ bool pair_reaches(const TileArgs& a, const SrcTable& 
 
 // Substep range [ka, kb] of one ray that can touch the tile (kb < ka: none) and its
 // direction (zero for a lane past the source's last ray).
-__device__ __forceinline__ void ray_range(const TileArgs& a, const SrcTable& S, const TileGeom& g,
-                                          int s, int ray, int& ka, int& kb, float4& d) {
+__device__ __forceinline__ void ray_range(const TileArgs& a, const TileGeom& g, int s, int ray, int& ka, int& kb,
+                                          float4& d) {
   ka = 0;
   kb = -1;
   d = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  if (ray >= S.nrays[s]) return;
-  const float4 P = S.pos[s];
-  const float sx = P.x, sy = P.y, sz = P.z, tmax = P.w, m = S.marg[s];
+  const SrcRec& S = a.src[s];
+  if (ray >= S.nrays) return;
+  const float sx = S.sx, sy = S.sy, sz = S.sz, tmax = S.tmax, m = S.marg;
   const int nx = a.nx, ny = a.ny, nz = a.nz;
-  d = S.dirs[s][ray];
+  d = S.dirs[ray];
   const float ix = __builtin_amdgcn_rcpf(d.x), iy = __builtin_amdgcn_rcpf(d.y),
               iz = __builtin_amdgcn_rcpf(d.z);
   float t0 = 0.0f, t1 = tmax;
@@ -592,7 +577,7 @@ __device__ __forceinline__ void ray_range(const TileArgs& a, const SrcTable& S, 
   if (t0 <= t1) {
     // one substep of margin on each side covers the rounding of t = k ds
     ka = max(0, static_cast<int>(floorf(t0 / a.ds)) - 1);
-    kb = min(S.nsub[s] - 1, static_cast<int>(fminf(ceilf(t1 / a.ds), 1.0e8f)) + 1);
+    kb = min(S.nsub - 1, static_cast<int>(fminf(ceilf(t1 / a.ds), 1.0e8f)) + 1);
   }
 }
 
@@ -722,14 +707,17 @@ __global__ void __launch_bounds__(kScheduleThreads) tile_schedule_kernel(const T
 // pair_mask. FILL = true takes only the marked pairs (no cull, no pair without chunks). FILL = true: a wave reserves the chunks
 // of the four pairs it holds with one atomic add at the tile's fill cursor and writes one
 // record per chunk,
-//   x = source << kRecRayBits | ray,
-//   y = chunk << 6 | (first substep - chunk start) << 3 | (last substep - chunk start),
+//   x = (source mod 256) << kRecRayBits | ray,
+//   y = (source / 256) << kRecChunkEnd | chunk << 6 | (first substep - chunk start) << 3
+//       | (last substep - chunk start),
 // never past the tile's count or the record buffer. Both passes run the same code on
 // the same inputs, so they agree on every count; the tile kernel also trusts only records
 // below the cursor. Blocks hold a modest number of pairs because next to a source every
 // pair of a block reaches the tile and each needs its rays' ranges.
 constexpr int kCostThreads = 256;
-constexpr int kRecRayBits = 24;   // rays per source < 2^24
+constexpr int kRecRayBits = 24;    // rays per source < 2^24
+constexpr int kRecChunkEnd = 27;   // chunk index < 2^21 (N_s <= 2^24); 13 bits of source above it
+static_assert(kMaxSrcPerTiledLaunch <= (1 << (32 - kRecChunkEnd + 8)), "source index does not fit the records");
 
 __device__ __forceinline__ long long shfl_ll(long long v, int src) {
   const int lo = __shfl(static_cast<int>(static_cast<unsigned long long>(v) & 0xffffffffull), src, 64);
@@ -740,21 +728,19 @@ __device__ __forceinline__ long long shfl_ll(long long v, int src) {
 
 template <bool FILL>
 __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs a) {
-  __shared__ SrcTable S;
   __shared__ int list[kPairBlock];
   __shared__ int count;
   __shared__ unsigned long long total;
   constexpr int kMaskWords = kPairBlock / 32;
   __shared__ unsigned mask[kMaskWords];   // pairs of the block with chunks in the tile
   const int tid = static_cast<int>(threadIdx.x), wave = tid >> 6, lane = tid & 63;
-  load_sources(a, S, tid);
   if (tid == 0) {
     count = 0;
     total = 0ull;
   }
   const int t = static_cast<int>(blockIdx.x);
   const TileGeom g = tile_geom(a, t);
-  const int npairs = a.pbegin[a.n_src];
+  const int npairs = a.n_pairs;
   const int nblocks = (npairs + kPairBlock - 1) / kPairBlock;
   long long rec_end = 0;   // records of this tile end here (FILL)
   if constexpr (FILL) {
@@ -774,8 +760,8 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
       if constexpr (FILL) {   // only the pairs the count pass found chunks for
         if ((block_mask[tid >> 5] >> (tid & 31)) & 1u) list[atomicAdd(&count, 1)] = p;
       } else {
-        const int s = pair_source(S, a.n_src, p);
-        if (pair_reaches(a, S, g, s, p - S.pbegin[s])) list[atomicAdd(&count, 1)] = p;
+        const int s = pair_source(a, p);
+        if (pair_reaches(a, g, s, p - a.src[s].pbegin)) list[atomicAdd(&count, 1)] = p;
       }
     }
     __syncthreads();
@@ -793,10 +779,10 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
         ray[u] = 0;
         if (i < count) {
           const int q = list[i];
-          src[u] = pair_source(S, a.n_src, q);
-          ray[u] = (q - S.pbegin[src[u]]) * kPatch + lane;
+          src[u] = pair_source(a, q);
+          ray[u] = (q - a.src[src[u]].pbegin) * kPatch + lane;
           float4 d;
-          ray_range(a, S, g, src[u], ray[u], ka[u], kb[u], d);
+          ray_range(a, g, src[u], ray[u], ka[u], kb[u], d);
         }
       }
       if constexpr (!FILL) {
@@ -838,11 +824,12 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
 #pragma unroll
         for (int u = 0; u < kUnroll; ++u) {
           long long idx = base + incl[u] - c[u];
-          const unsigned rx = (static_cast<unsigned>(src[u]) << kRecRayBits) | static_cast<unsigned>(ray[u]);
+          const unsigned rx = (static_cast<unsigned>(src[u] & 0xff) << kRecRayBits) | static_cast<unsigned>(ray[u]);
+          const unsigned ry = static_cast<unsigned>(src[u] >> 8) << kRecChunkEnd;
           for (int q = 0; q < c[u] && idx < rec_end; ++q, ++idx) {
             const int cb = ka[u] / kChunk + q, kblk = cb * kChunk;
             const int ob = max(ka[u], kblk) - kblk, oe = min(kb[u], kblk + kChunk - 1) - kblk;
-            a.recs[idx] = make_uint2(rx, (static_cast<unsigned>(cb) << 6) | static_cast<unsigned>(ob << 3) |
+            a.recs[idx] = make_uint2(rx, ry | (static_cast<unsigned>(cb) << 6) | static_cast<unsigned>(ob << 3) |
                                              static_cast<unsigned>(oe));
           }
         }
@@ -871,14 +858,12 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
   using T = typename std::conditional<DET, unsigned long long, double>::type;
   constexpr int kThreads = kTileThreads;
   __shared__ T acc[kPadVox];
-  __shared__ SrcTable S;
   __shared__ int2 claimed;
   const int tid = static_cast<int>(threadIdx.x);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const float ds = a.ds;
   double det_scale = 0.0;
   if constexpr (DET) det_scale = *a.det_scale;
-  load_sources(a, S, tid);
   const int n_items = *a.item_total;
 
   for (;;) {
@@ -909,14 +894,17 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
     rend = min(rend, min(a.tile_fill[t], a.rec_capacity));
     for (long long i = rbegin + rcount * part / parts + tid; i < rend; i += kThreads) {
       const uint2 rec = a.recs[i];
-      const int s = static_cast<int>(rec.x >> kRecRayBits);
+      const int s = static_cast<int>((rec.x >> kRecRayBits) | ((rec.y >> kRecChunkEnd) << 8));
       const int ray = static_cast<int>(rec.x & ((1u << kRecRayBits) - 1u));
-      if (s >= a.n_src || ray >= S.nrays[s]) continue;   // (not produced by the fill pass)
-      const int kblk = static_cast<int>(rec.y >> 6) * kChunk;
+      if (s >= a.n_src) continue;   // (not produced by the fill pass)
+      const SrcRec* sr = a.src + s;
+      const int nrays = sr->nrays;
+      if (ray >= nrays) continue;
+      const int kblk = static_cast<int>((rec.y >> 6) & ((1u << (kRecChunkEnd - 6)) - 1u)) * kChunk;
       const int kbeg = kblk + static_cast<int>((rec.y >> 3) & 7u), kend = kblk + static_cast<int>(rec.y & 7u);
-      const float4 dd = S.dirs[s][ray];
-      const float4 src = S.pos[s];
-      const float* vrow = a.V + row_slot(S.vbase[s], S.nrays[s], ray, kblk);
+      const float4 dd = sr->dirs[ray];
+      const float4 src = make_float4(sr->sx, sr->sy, sr->sz, 0.0f);
+      const float* vrow = a.V + row_slot(sr->vbase, nrays, ray, kblk);
       // the chunk's recorded values, fetched before any of them is needed
       float vv[kChunk];
 #pragma unroll
@@ -930,22 +918,28 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
       // A lane sums the weighted corners of consecutive samples that share a lower corner
       // (the nearest voxel, for NEAREST) in registers: samples less than a voxel apart
       // often do. The sums reach the tile when the ray moves on to another cell and at the
-      // end of the chunk, which takes a third or more of the LDS atomics away.
+      // end of the chunk, which takes a third or more of the LDS atomics away. Such a run
+      // has at most kChunk terms, so in the float mode it is summed in binary32 (error below
+      // kChunk units in the last place of the sum of the terms' magnitudes; the terms share
+      // the sign of the ray's I, which changes only where j does) and only the tile is
+      // binary64. The nearest-voxel deposits of the adjoint mix signs: their runs stay binary64.
       constexpr int kCorners = NEAREST ? 1 : 8;
+      using R = typename std::conditional<DET, unsigned long long,
+                                          typename std::conditional<NEAREST, double, float>::type>::type;
       int cell = -1;   // padded slot of the current lower corner (nearest voxel)
-      T run[kCorners];
+      R run[kCorners];
       auto flush = [&]() {
         if (cell < 0) return;
 #pragma unroll
         for (int c = 0; c < kCorners; ++c)
-          atomicAdd(&acc[cell + (c >> 2) * kPadPlane + ((c >> 1) & 1) * kPadRow + (c & 1)], run[c]);
+          atomicAdd(&acc[cell + (c >> 2) * kPadPlane + ((c >> 1) & 1) * kPadRow + (c & 1)], static_cast<T>(run[c]));
       };
       auto move_to = [&](int slot) {
         if (slot == cell) return;
         flush();
         cell = slot;
 #pragma unroll
-        for (int c = 0; c < kCorners; ++c) run[c] = T(0);
+        for (int c = 0; c < kCorners; ++c) run[c] = R(0);
       };
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) {
@@ -970,7 +964,7 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
               (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
             continue;
           move_to(pad_slot(lx + 1, ly + 1, lz + 1));
-          run[0] += tile_value<T>(vv[u], det_scale);
+          run[0] += tile_value<R>(vv[u], det_scale);
         } else {
           // some corner lies in the tile iff the lower corner is in [origin - 1, origin +
           // extent - 1] on every axis (a collapsed axis, lower = upper corner, only occurs on
@@ -988,7 +982,7 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
 #pragma unroll
           for (int c = 0; c < 8; ++c) {
             const float w = (wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1];
-            run[c] += tile_value<T>(vv[u] * w, det_scale);
+            run[c] += tile_value<R>(vv[u] * w, det_scale);
           }
         }
       }
@@ -1036,9 +1030,12 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
 }
 
 template <int NB>
-hipError_t launch_record_nb(const RecordArgs& a, bool shared_j, bool det, int blocks, hipStream_t s) {
-  // a multiple of the XCD count, so the block remapping is a bijection onto [0, blocks)
-  const dim3 grid((blocks + kXcds - 1) / kXcds * kXcds), block(kBlock);
+hipError_t launch_record_nb(const RecordArgs& a, bool shared_j, bool det, int, hipStream_t s) {
+  // kXcds work-groups per round, one per XCD group, as many rounds as the largest group has blocks
+  int rounds = 0;
+  for (int x = 0; x < kXcds; ++x) rounds = max(rounds, a.xcd_blocks[x]);
+  if (rounds == 0) return hipSuccess;
+  const dim3 grid(rounds * kXcds), block(kBlock);
   if (a.med) {
     if (det) hipLaunchKernelGGL((record_kernel<NB, true, true, true>), grid, block, 0, s, a);
     else hipLaunchKernelGGL((record_kernel<NB, true, false, true>), grid, block, 0, s, a);
@@ -1083,8 +1080,19 @@ hipError_t launch_tile_one_bin(const TileArgs& a, bool det, bool nearest, hipStr
   return det ? launch_tile_variant<true, false>(a, s) : launch_tile_variant<false, false>(a, s);
 }
 
+// One lane per source: copy the record, completing the distance of its last substep and
+// the position margin of the tile geometry (binary32, as the kernels that read them).
+__global__ void __launch_bounds__(64) write_sources_kernel(const SrcWrite w) {
+  const int i = static_cast<int>(threadIdx.x);
+  if (i >= w.count) return;
+  SrcRec r = w.rec[i];
+  r.tmax = sample_distance(r.nsub - 1, w.ds);
+  r.marg = 5.0e-7f * (fmaxf(fabsf(r.sx), fmaxf(fabsf(r.sy), fabsf(r.sz))) + r.tmax + 2.0f) + 1.0e-6f;
+  w.table[w.first + i] = r;
+}
+
 dim3 pairs_grid(const TileArgs& a, int tiles) {
-  const int nblocks = (a.pbegin[a.n_src] + kPairBlock - 1) / kPairBlock;
+  const int nblocks = (a.n_pairs + kPairBlock - 1) / kPairBlock;
   return dim3(tiles, nblocks < 65535 ? nblocks : 65535);
 }
 
@@ -1119,6 +1127,12 @@ hipError_t launch_record(const RecordArgs& a, int n_bins, bool shared_j, bool de
   }
 }
 
+hipError_t launch_write_sources(const SrcWrite& w, hipStream_t s) {
+  if (w.count < 1 || w.count > kSrcPerWrite) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(write_sources_kernel, dim3(1), dim3(64), 0, s, w);
+  return hipGetLastError();
+}
+
 hipError_t launch_cell_table(const float* j, const float* kap, float4* table, int nx, int ny, int nz,
                              hipStream_t s) {
   const long long cells = static_cast<long long>(nx) * ny * nz;
@@ -1132,14 +1146,14 @@ hipError_t launch_cell_table(const float* j, const float* kap, float4* table, in
 hipError_t launch_tile_schedule(const TileArgs& a, int tiles, hipStream_t s) {
   hipError_t e = launch_fill_zero_u64(a.tile_cost, tiles, s);
   if (e != hipSuccess) return e;
-  if (a.pbegin[a.n_src] > 0)   // (without rays every tile keeps a zero count)
+  if (a.n_pairs > 0)   // (without rays every tile keeps a zero count)
     hipLaunchKernelGGL(tile_pairs_kernel<false>, pairs_grid(a, tiles), dim3(kCostThreads), 0, s, a);
   hipLaunchKernelGGL(tile_schedule_kernel, dim3(1), dim3(kScheduleThreads), 0, s, a, tiles);
   return hipGetLastError();
 }
 
 hipError_t launch_tile_fill(const TileArgs& a, int tiles, hipStream_t s) {
-  if (a.pbegin[a.n_src] > 0 && a.rec_capacity > 0)
+  if (a.n_pairs > 0 && a.rec_capacity > 0)
     hipLaunchKernelGGL(tile_pairs_kernel<true>, pairs_grid(a, tiles), dim3(kCostThreads), 0, s, a);
   return hipGetLastError();
 }
