@@ -81,16 +81,16 @@ class Setup:
         self.units = workload_units(w, self.n_s)
         for n in sorted(set(int(v) for v in w.num_rays)):
             rtmi.prepare(n)
-        self.tuned, self.tune_ms = 0, {}
+        self.tuned, self.tune_ms = dict(autotune.DEFAULTS), {}
         if tune_reps > 0:
             import tempfile
             os.environ.setdefault("RTMI_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "rtmi_bench_tune.json"))
-            self.tuned, self.tune_ms = autotune.tune_item_chunks(
+            self.tuned, self.tune_ms = autotune.tune(
                 self.j, self.k, w.source_pos, w.num_rays, w.step_size, w.radiation_velocity, w.time_step,
                 n_bins=w.n_bins, kappa_scale=w.kappa_scale, substep_cap=w.substep_cap, reps=tune_reps)
         self.plan = rtmi.Plan(w.shape, w.source_pos, w.num_rays, w.step_size, w.radiation_velocity,
                               w.time_step, n_bins=w.n_bins, kappa_scale=w.kappa_scale,
-                              substep_cap=w.substep_cap, tile_item_chunks=self.tuned)
+                              substep_cap=w.substep_cap, **self.tuned)
 
     def execute(self):
         self.plan.execute(self.j, self.k, self.out)
@@ -252,7 +252,7 @@ def measure(name, steps, warmup, peaks, tune_reps=3):
            "eager_plan_ms_per_step": 1e3 * eager_elapsed / steps,
            "stateless_ms_per_step": 1e3 * stateless_elapsed / steps,
            "stateless_value": s.units * steps / stateless_elapsed,
-           "tile_item_chunks": s.tuned, "autotune_ms": {str(c): round(t, 4) for c, t in s.tune_ms.items()},
+           "tuned": s.tuned, "autotune_ms": {str(c): round(t, 4) for c, t in s.tune_ms.items()},
            "kernels": rl, "counters_file": COUNTER_FILES.get(name) if counters_doc else None,
            "roofline": contract_roofline(rl, counters_doc)}
     s.close()
@@ -375,7 +375,7 @@ def main():
         "config": {"workload": main_res["workload"], "grid": main_res["grid"], "sources": main_res["sources"],
                    "rays_per_source": main_res["rays_per_source"], "bins": main_res["bins"],
                    "ray_substeps_per_step": main_res["ray_substeps_per_step"],
-                   "execution": "plan (geometry set up once) replayed as one HIP graph"},
+                   "execution": "plan (geometry set up once, knobs autotuned) replayed as one HIP graph"},
         "roofline": main_res["roofline"],
         "detail": {k: v for k, v in main_res.items() if k not in ("roofline",)},
         "peaks_measured": peaks,

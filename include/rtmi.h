@@ -91,9 +91,18 @@ typedef struct rtmi_options {
   /* Tiled path with j and kappa shared by the bins: where the record pass gathers them.
    * 1: a table built per call holding, per voxel, the eight corners of j and of kappa in
    * one 64-byte line (one line per sample; 64 bytes of workspace per voxel). 2: the maps
-   * themselves (nine 4-byte loads per sample, no table). 0 picks by the grid size. Changes
-   * the speed, not the field. */
+   * themselves (nine 4-byte loads per sample, no table). 0 picks the table. Changes the
+   * speed, and the field only by rounding (the two round the interpolation of a sample
+   * clamped on a box face differently, also in the deterministic mode). */
   int32_t gather_table;
+  /* Tiled path: > 0 caps the sources one record launch (and its tile passes) covers;
+   * the sources are then marched in consecutive groups of at most this many, each group's
+   * tile passes adding into the field. 0: every source in one launch unless their deposit
+   * rows pass 4 GiB. Changes the speed and the workspace, not the field. */
+  int32_t sources_per_launch;
+  /* Tiled path: > 0 caps the work-groups of the persistent tile pass at this many per
+   * compute unit (0: as many as fit, three). A tuning knob: changes the speed only. */
+  int32_t tile_groups_per_cu;
 } rtmi_options;
 
 /* Execution paths (rtmi_options.path). Both compute the same field.

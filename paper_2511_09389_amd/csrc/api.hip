@@ -460,6 +460,8 @@ struct Plan {
   int64_t record_capacity = 0;  // > 0: stateless chunk-record buffers capped (test hook)
   bool no_alloc = false;        // the call may not allocate (static scratch, no events)
   int32_t gather_table = 0;     // 0 auto, 1 gather j and kappa from the 64-byte table, 2 from the maps
+  int32_t sources_per_launch = 0;   // > 0: at most this many sources per record launch
+  int32_t tile_groups_per_cu = 0;   // > 0: cap on the persistent tile grid per compute unit
   std::vector<int32_t> nsub;
   std::vector<DevTable> tables;
   double bound_per_unit_j = 0.0;
@@ -510,6 +512,12 @@ int32_t validate(const Problem& p, Plan* plan, bool maps_given = true) {
     if (p.opts->gather_table < 0 || p.opts->gather_table > 2)
       return fail(RTMI_ERR_INVALID_ARG, "gather_table must be 0, 1 or 2 (got %d)", p.opts->gather_table);
     plan->gather_table = p.opts->gather_table;
+    if (p.opts->sources_per_launch < 0)
+      return fail(RTMI_ERR_INVALID_ARG, "sources_per_launch must be >= 0 (got %d)", p.opts->sources_per_launch);
+    plan->sources_per_launch = p.opts->sources_per_launch;
+    if (p.opts->tile_groups_per_cu < 0)
+      return fail(RTMI_ERR_INVALID_ARG, "tile_groups_per_cu must be >= 0 (got %d)", p.opts->tile_groups_per_cu);
+    plan->tile_groups_per_cu = p.opts->tile_groups_per_cu;
     if (plan->explicit_dirs && p.opts->ray_weight > 0.0f && !std::isfinite(p.opts->ray_weight))
       return fail(RTMI_ERR_NONFINITE, "ray_weight is not finite");
   }
@@ -651,7 +659,7 @@ int64_t row_stride(int32_t nsub) { return (int64_t(nsub) + kRowAlign - 1) / kRow
 // Source groups of the tiled path: runs of consecutive sources that one record launch
 // and one tile pass per bin cover. A group ends where its deposit rows would pass
 // kGroupRowBytes (so the workspace stays bounded for thousands of sources) or at
-// kMaxSrcPerTiledLaunch sources.
+// kMaxSrcPerTiledLaunch sources (or the caller's sources_per_launch).
 constexpr int64_t kGroupRowBytes = int64_t(4) << 30;
 
 struct SourceGroup {
@@ -664,7 +672,9 @@ std::vector<SourceGroup> source_groups(const Problem& p, const Plan& plan) {
   int64_t bytes = 0;
   for (int32_t s = 0; s < p.n_src; ++s) {
     const int64_t b = plan.nsub[s] > 0 ? int64_t(p.nrays[s]) * row_stride(plan.nsub[s]) * nb * 4 : 0;
-    if (g.empty() || (g.back().ns > 0 && bytes + b > kGroupRowBytes) || g.back().ns >= rtmi::kMaxSrcPerTiledLaunch) {
+    const int32_t cap = plan.sources_per_launch > 0 ? std::min(plan.sources_per_launch, rtmi::kMaxSrcPerTiledLaunch)
+                                                    : rtmi::kMaxSrcPerTiledLaunch;
+    if (g.empty() || (g.back().ns > 0 && bytes + b > kGroupRowBytes) || g.back().ns >= cap) {
       g.push_back({s, 0});
       bytes = 0;
     }
@@ -738,7 +748,9 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
         rays += p.nrays[s];
         max_nsub = std::max(max_nsub, plan.nsub[s]);
       }
-    const int len = record_run_length(rays, max_nsub);
+    // (the deterministic mode marches whole rays: runs chained by the fix-up round their
+    // values differently, and their length depends on the launch, so its bits would too)
+    const int len = plan.det ? 0 : record_run_length(rays, max_nsub);
     L.seg_len.push_back(len);
     if (shared_records)
       L.rec_capacity = std::max(L.rec_capacity, record_bound(p, plan, g.s0, g.ns, L.tiles_x, L.tiles_y, L.tiles_z));
@@ -1020,6 +1032,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       t.tiles_x = L.tiles_x;
       t.tiles_y = L.tiles_y;
       t.tiles_z = L.tiles_z;
+      t.groups_per_cu = plan.tile_groups_per_cu;
       TileSchedule sched;
       sched.carve(ws + L.sched + launch * L.sched_bytes, L.tiles, L.pair_blocks);
       if (slices && launch < static_cast<int>(slices->off.size()))
@@ -1552,7 +1565,7 @@ extern "C" {
 
 const char* rtmi_last_error(void) { return g_error.c_str(); }
 
-int32_t rtmi_version(void) { return 310; }
+int32_t rtmi_version(void) { return 320; }
 
 int64_t rtmi_num_substeps(float step_size, float radiation_velocity, float time_step,
                           int32_t cap) {

@@ -141,6 +141,7 @@ struct TileArgs {
   int* item_next;                 // next unclaimed work item
   int* item_done;                 // work-groups finished (the last one rewinds the counters)
   int item_chunks;                // target chunk records per work item
+  int groups_per_cu;              // persistent tile grid: work-groups per compute unit (0: all that fit)
 };
 
 // Adjoint of the march: per-ray reverse sweep with checkpointed recomputation.

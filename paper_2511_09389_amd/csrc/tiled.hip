@@ -1069,8 +1069,17 @@ int resident_groups(K kernel, int threads, int* cache) {
 template <bool DET, bool NEAREST>
 hipError_t launch_tile_variant(const TileArgs& a, hipStream_t s) {
   static int cache[kCacheDevices] = {0};   // one per kernel variant and device
+  static int cus[kCacheDevices] = {0};
   const auto kernel = tile_kernel<DET, NEAREST>;
-  const int groups = resident_groups(kernel, kTileThreads, cache);
+  int groups = resident_groups(kernel, kTileThreads, cache);
+  if (a.groups_per_cu > 0) {   // fewer resident work-groups than fit (a tuning knob)
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kCacheDevices) dev = 0;
+    if (cus[dev] == 0 && (hipDeviceGetAttribute(&cus[dev], hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+                          cus[dev] < 1))
+      cus[dev] = 1;
+    groups = min(groups, a.groups_per_cu * cus[dev]);
+  }
   hipLaunchKernelGGL(kernel, dim3(groups), dim3(kTileThreads), 0, s, a);
   return hipGetLastError();
 }

@@ -42,7 +42,8 @@ class Options(ctypes.Structure):
     _fields_ = [("accum_mode", ctypes.c_int32), ("directions", ctypes.c_void_p),
                 ("ray_weight", ctypes.c_float), ("path", ctypes.c_int32),
                 ("tile_item_chunks", ctypes.c_int32), ("record_capacity", ctypes.c_int64),
-                ("gather_table", ctypes.c_int32)]
+                ("gather_table", ctypes.c_int32), ("sources_per_launch", ctypes.c_int32),
+                ("tile_groups_per_cu", ctypes.c_int32)]
 
 
 def _load():
@@ -231,24 +232,26 @@ def trace_multi(j_map, kappa_map, source_pos, num_rays, step_size, radiation_vel
 def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
                time_step, kappa_scale=None, substep_cap=None, out=None, deterministic=False,
                directions=None, ray_weight=0.0, path=PATH_TILED, tile_item_chunks=0, record_capacity=0,
-               gather_table=0):
+               gather_table=0, sources_per_launch=0):
     """Frequency bins as a batch axis. j_maps / kappa_maps are 3-D (shared by all bins) or
     4-D [B][nx][ny][nz]; a 3-D kappa with kappa_scale gives kappa_b = kappa * scale[b].
     Returns a [B][nx][ny][nz] float32 tensor."""
     return _bins_call(lib.rtmi_trace_bins, j_maps, kappa_maps, source_pos, num_rays, step_size,
                       radiation_velocity, time_step, kappa_scale, substep_cap, out, deterministic,
-                      directions, ray_weight, path, tile_item_chunks, record_capacity, gather_table)
+                      directions, ray_weight, path, tile_item_chunks, record_capacity, gather_table,
+                      sources_per_launch)
 
 
 def trace_bins_static(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
                       time_step, kappa_scale=None, substep_cap=None, out=None, deterministic=False,
-                      path=PATH_TILED, tile_item_chunks=0, record_capacity=0, gather_table=0):
+                      path=PATH_TILED, tile_item_chunks=0, record_capacity=0, gather_table=0,
+                      sources_per_launch=0):
     """trace_bins through rtmi_trace_bins_static, which allocates nothing: its scratch is
     the library's static per-device array (static_scratch_bytes()). Every N_Omega must have
     been prepared (prepare()); pass `out` to keep this call free of allocation in torch too."""
     return _bins_call(lib.rtmi_trace_bins_static, j_maps, kappa_maps, source_pos, num_rays, step_size,
                       radiation_velocity, time_step, kappa_scale, substep_cap, out, deterministic,
-                      None, 0.0, path, tile_item_chunks, record_capacity, gather_table)
+                      None, 0.0, path, tile_item_chunks, record_capacity, gather_table, sources_per_launch)
 
 
 def static_scratch_bytes():
@@ -257,7 +260,7 @@ def static_scratch_bytes():
 
 def _bins_call(entry, j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
                time_step, kappa_scale, substep_cap, out, deterministic, directions, ray_weight, path,
-               tile_item_chunks, record_capacity, gather_table=0):
+               tile_item_chunks, record_capacity, gather_table=0, sources_per_launch=0):
     grid = tuple(j_maps.shape[-3:])
     if tuple(kappa_maps.shape[-3:]) != grid:
         raise ValueError("j and kappa grids differ")
@@ -282,7 +285,8 @@ def _bins_call(entry, j_maps, kappa_maps, source_pos, num_rays, step_size, radia
     out = _new_field((n_bins,) + grid, j_maps) if out is None else \
         _same(out, "out", (n_bins,) + grid, j_maps.device)
     opts = Options(ACCUM_DETERMINISTIC if deterministic else ACCUM_ATOMIC, None, float(ray_weight),
-                   int(path), int(tile_item_chunks), int(record_capacity), int(gather_table))
+                   int(path), int(tile_item_chunks), int(record_capacity), int(gather_table),
+                   int(sources_per_launch))
     dirs = None
     if directions is not None:
         dirs = _host_f32(directions, 3)
@@ -309,7 +313,8 @@ class Plan:
     def __init__(self, grid, source_pos, num_rays, step_size, radiation_velocity, time_step,
                  n_bins=1, kappa_scale=None, per_bin_j=False, per_bin_kappa=False,
                  substep_cap=None, deterministic=False, directions=None, ray_weight=0.0,
-                 tile_item_chunks=0, gather_table=0, device=None):
+                 tile_item_chunks=0, gather_table=0, sources_per_launch=0, tile_groups_per_cu=0,
+                 device=None):
         self.grid = tuple(int(v) for v in grid)
         cells = self.grid[0] * self.grid[1] * self.grid[2]
         src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
@@ -323,7 +328,8 @@ class Plan:
         self.n_bins = int(n_bins)
         self.per_bin_j, self.per_bin_kappa = bool(per_bin_j), bool(per_bin_kappa)
         opts = Options(ACCUM_DETERMINISTIC if deterministic else ACCUM_ATOMIC, None,
-                       float(ray_weight), PATH_TILED, int(tile_item_chunks), 0, int(gather_table))
+                       float(ray_weight), PATH_TILED, int(tile_item_chunks), 0, int(gather_table),
+                       int(sources_per_launch), int(tile_groups_per_cu))
         dirs = None
         if directions is not None:
             dirs = _host_f32(directions, 3)

@@ -265,17 +265,21 @@ def test_long_march_piles_up_on_box_corners(rt, dev):
 
 
 def test_many_sources_span_launches(rt, dev):
-    """More sources than one launch describes: later launches add into the field."""
+    """70 sources in one record launch and, capped at 32 sources per launch, in three
+    launches whose tile passes add into the field."""
     rng = np.random.default_rng(11)
     shape = (20, 20, 20)
     j = rng.random(shape).astype(np.float32)
     kap = (0.1 * rng.random(shape)).astype(np.float32)
     src = rng.uniform(0, 19, size=(70, 3)).astype(np.float32)
     rays = rng.integers(1, 90, size=70)
+    want = oracle.trace_multi(j, kap, src, rays, 0.5, 10.0, 1.0)
     for path in PATHS.values():
         got = multi(rt, to_dev(j, dev), to_dev(kap, dev), src, rays, 0.5, 10.0, 1.0, path=path).cpu().numpy()
-        want = oracle.trace_multi(j, kap, src, rays, 0.5, 10.0, 1.0)
         assert_parity(got, want)
+    got = multi(rt, to_dev(j, dev), to_dev(kap, dev), src, rays, 0.5, 10.0, 1.0, path=PATHS["tiled"],
+                sources_per_launch=32).cpu().numpy()
+    assert_parity(got, want)
 
 
 def test_many_launches_share_record_buffers(rt, dev):
@@ -289,14 +293,17 @@ def test_many_launches_share_record_buffers(rt, dev):
     kap = (0.1 * rng.random(shape)).astype(np.float32)
     src = rng.uniform(0, 19, size=(150, 3)).astype(np.float32)
     rays = rng.integers(1, 200, size=150)
-    note("150 sources (5 launches), 24x20x28, tiled path")
+    note("150 sources (5 launches of at most 32), 24x20x28, tiled path")
     jd, kd = to_dev(j, dev), to_dev(kap, dev)
-    got = multi(rt, jd, kd, src, rays, 0.5, 12.0, 1.0, path=PATHS["tiled"]).cpu().numpy()
+    got = multi(rt, jd, kd, src, rays, 0.5, 12.0, 1.0, path=PATHS["tiled"], sources_per_launch=32).cpu().numpy()
     assert_parity(got, oracle.trace_multi(j, kap, src, rays, 0.5, 12.0, 1.0))
-    a = multi(rt, jd, kd, src, rays, 0.5, 12.0, 1.0, path=PATHS["tiled"], deterministic=True).cpu().numpy()
+    a = multi(rt, jd, kd, src, rays, 0.5, 12.0, 1.0, path=PATHS["tiled"], deterministic=True,
+              sources_per_launch=32).cpu().numpy()
     b = multi(rt, jd, kd, src[::-1].copy(), rays[::-1].copy(), 0.5, 12.0, 1.0, path=PATHS["tiled"],
-              deterministic=True).cpu().numpy()
+              deterministic=True, sources_per_launch=32).cpu().numpy()
+    one = multi(rt, jd, kd, src, rays, 0.5, 12.0, 1.0, path=PATHS["tiled"], deterministic=True).cpu().numpy()
     assert np.array_equal(a, b)
+    assert np.array_equal(a, one)   # one launch of all 150 sources: the same bits
     assert_parity(a, oracle.trace_multi(j, kap, src, rays, 0.5, 12.0, 1.0))
 
 

@@ -5,10 +5,11 @@ Two views, both against the FP64 oracle with the field tolerances (relative L2 <
 per-voxel relative error <= 1e-4 wherever the oracle exceeds 1e-6 of its maximum):
 
 * a 36-source subset that spans every N_Omega class (16384 rays with a 420-substep cap,
-  8192 rays with the largest cap, 502) and needs two source launches, so the second
-  record launch, the alternating chunk-record buffers and the side-stream refills run on
-  the full 256^3 grid; the whole field of every bin is compared, from the stateless call
-  on both paths and from an autotuned plan replayed as a HIP graph;
+  8192 rays with the largest cap, 502); the whole field of every bin is compared, from the
+  stateless call on both paths (the tiled one as one record launch over all 36 sources,
+  and capped at 32 sources per launch, so that a second record launch, the alternating
+  chunk-record buffers and the side-stream refills run on the full 256^3 grid) and from an
+  autotuned plan replayed as a HIP graph;
 * the whole batch, all 64 sources, run exactly as the benchmark runs it (an autotuned
   plan captured in a HIP graph and replayed), checked voxel by voxel at sampled interior
   voxels with oracle.trace_voxels, which marches only the rays that can reach them.
@@ -61,7 +62,7 @@ def uneven(dev):
 
 def subset_picks(w):
     """36 sources: the two heaviest classes' largest-cap representatives among the 16384-
-    and 8192-ray sources, placed in the first launch, and the 34 cheapest others."""
+    and 8192-ray sources, among the first 32, and the 34 cheapest others."""
     cost = w.num_rays.astype(np.int64) * w.substep_cap
     big = int(np.flatnonzero(w.num_rays == 16384)[np.argmax(w.substep_cap[w.num_rays == 16384])])
     long_cap = int(np.argmax(np.where(w.num_rays == 8192, w.substep_cap, -1)))
@@ -79,21 +80,22 @@ def subset(uneven):
     return picks, want
 
 
-@pytest.mark.parametrize("path", ["tiled", "direct"])
-def test_two_launch_subset_full_field(rt, uneven, subset, path):
+@pytest.mark.parametrize("path", ["tiled", "tiled_two_launches", "direct"])
+def test_subset_full_field(rt, uneven, subset, path):
     w, j, k = uneven
     picks, want = subset
     note(f"trace_bins, 36 sources (rays {sorted(set(w.num_rays[picks].tolist()))}, caps up to "
          f"{w.substep_cap[picks].max()}), path={path}")
     got = rt.trace_bins(j, k, w.source_pos[picks], w.num_rays[picks], w.step_size, w.radiation_velocity,
                         w.time_step, kappa_scale=w.kappa_scale, substep_cap=w.substep_cap[picks],
-                        path=rt.PATH_TILED if path == "tiled" else rt.PATH_DIRECT).cpu().numpy()
+                        path=rt.PATH_DIRECT if path == "direct" else rt.PATH_TILED,
+                        sources_per_launch=32 if path == "tiled_two_launches" else 0).cpu().numpy()
     for b in range(w.n_bins):
         err, mx = assert_parity(got[b], want[b])
         note(f"  bin {b}: rel L2 {err:.2e}, max per-voxel {mx:.2e}")
 
 
-def test_two_launch_subset_tuned_plan_graph(rt, uneven, subset, tmp_path, monkeypatch):
+def test_subset_tuned_plan_graph(rt, uneven, subset, tmp_path, monkeypatch):
     """The autotuned plan of the subset, captured in a HIP graph: every replay matches the
     oracle over the whole field."""
     w, j, k = uneven
