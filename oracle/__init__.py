@@ -33,4 +33,4 @@ from .march import (  # noqa: F401
     trace_bins,
     trace_voxels,
 )
-from .adjoint import trace_single_vjp, trace_multi_vjp  # noqa: F401
+from .adjoint import trace_single_vjp, trace_multi_vjp, trace_bins_vjp  # noqa: F401

@@ -108,3 +108,48 @@ def trace_multi_vjp(j_map, kappa_map, source_pos, num_rays, step_size, radiation
         dk += b
     return dj, dk
 
+
+
+def trace_bins_vjp(j_maps, kappa_map, kappa_scale, source_pos, num_rays, step_size,
+                   radiation_velocity, time_step, grad_fields, caps=None, kappa_maps=None, **kw):
+    """VJP of the frequency-bin march (oracle.march.trace_bins) for upstream gradients
+    G_b = dL/dJ_b, grad_fields of shape (B, nx, ny, nz).
+
+    Each bin is an independent multi-source problem (Sec. 2, "Frequency-bin agnosticism"),
+    so its derivative is the single-bin one, and the shared inputs collect the bins'
+    contributions by the chain rule:
+      j shared by the bins:       dL/dj = sum_b dL/dj_b      (a 4-D j_maps: dL/dj_b each)
+      kappa_b = s_b kappa:        dL/dkappa = sum_b s_b dL/dkappa_b,
+                                  dL/ds_b   = sum_v kappa[v] dL/dkappa_b[v]
+      per-bin kappa maps:         dL/dkappa_b each (no scales)
+    where dL/dj_b, dL/dkappa_b are trace_multi_vjp at (j_b, kappa_b). Returns (dj, dk, ds),
+    ds an array of B values, or None with per-bin kappa maps.
+    """
+    G = np.asarray(grad_fields, dtype=np.float64)
+    n_bins = G.shape[0]
+    jm = np.asarray(j_maps, dtype=np.float64)
+    if kappa_maps is not None:
+        km = np.asarray(kappa_maps, dtype=np.float64)
+        kappas = [km[b] for b in range(n_bins)]
+        scales = None
+    else:
+        base = np.asarray(kappa_map, dtype=np.float64)
+        scales = [float(np.float32(v)) for v in np.asarray(kappa_scale, dtype=np.float64).ravel()]
+        kappas = [base * scales[b] for b in range(n_bins)]
+    dj = np.zeros(jm.shape)
+    dk = np.zeros((n_bins,) + jm.shape[-3:]) if scales is None else np.zeros(jm.shape[-3:])
+    ds = None if scales is None else np.zeros(n_bins)
+    for b in range(n_bins):
+        j_b = jm if jm.ndim == 3 else jm[b]
+        a, k = trace_multi_vjp(j_b, kappas[b], source_pos, num_rays, step_size, radiation_velocity,
+                               time_step, G[b], caps=caps, **kw)
+        if jm.ndim == 3:
+            dj += a
+        else:
+            dj[b] = a
+        if scales is None:
+            dk[b] = k
+        else:
+            dk += scales[b] * k
+            ds[b] = float(np.sum(base * k))
+    return dj, dk, ds

@@ -113,3 +113,106 @@ def test_adjoint_pins_catch_mutant(name):
         except Exception:  # noqa: BLE001
             failed.append(pin.__name__)
     assert failed, f"no pin catches: {name}"
+
+
+# ---- frequency bins (Sec. 2: bins are independent copies of the problem) ----
+
+BIN_SCALES = np.array([1.0, 0.296875, 0.125], np.float32)   # exact in binary32
+
+
+def _bins_case(seed):
+    shape = (5, 4, 6)
+    j, kap = rand_medium(shape, seed, kappa_scale=0.5)
+    src = np.array([[2.2, 1.7, 2.9], [1.1, 2.6, 3.8]])
+    G = np.random.default_rng(seed + 1).normal(size=(3,) + shape)
+    return shape, j.astype(np.float64), kap.astype(np.float64), src, G
+
+
+def _bins_loss(j, kap_maps, src, G):
+    """sum_b <G_b, J_b> with bin b's opacity given as a full FP64 map."""
+    J = oracle.trace_bins(j, None, None, src, [9, 6], 0.5, 3.0, 1.0, caps=[0, 5], kappa_maps=kap_maps)
+    return float(np.sum(G * J))
+
+
+def pin_bins_scale_finite_differences(m):
+    """dL/ds_b against central differences in the bin scale (opacity maps kappa (s_b +- h))."""
+    shape, j, kap, src, G = _bins_case(71)
+    _, _, ds = m.trace_bins_vjp(j, kap, BIN_SCALES, src, [9, 6], 0.5, 3.0, 1.0, G, caps=[0, 5])
+    h = 1e-6
+    for b in range(3):
+        maps = [kap * float(s) for s in BIN_SCALES]
+        up = [mm.copy() for mm in maps]
+        dn = [mm.copy() for mm in maps]
+        up[b] = kap * (float(BIN_SCALES[b]) + h)
+        dn[b] = kap * (float(BIN_SCALES[b]) - h)
+        fd = (_bins_loss(j, np.stack(up), src, G) - _bins_loss(j, np.stack(dn), src, G)) / (2 * h)
+        assert abs(fd - ds[b]) <= 1e-6 * max(1.0, abs(fd)), (b, fd, ds[b])
+
+
+def pin_bins_kappa_finite_differences(m):
+    """dL/dkappa of the shared base opacity (every bin scales it) against central differences."""
+    shape, j, kap, src, G = _bins_case(72)
+    _, dk, _ = m.trace_bins_vjp(j, kap, BIN_SCALES, src, [9, 6], 0.5, 3.0, 1.0, G, caps=[0, 5])
+    h = 1e-6
+    for v in np.argsort(-np.abs(dk.ravel()))[:8]:
+        e = np.zeros(kap.size)
+        e[v] = h
+        e = e.reshape(shape)
+        fd = (_bins_loss(j, np.stack([(kap + e) * float(s) for s in BIN_SCALES]), src, G) -
+              _bins_loss(j, np.stack([(kap - e) * float(s) for s in BIN_SCALES]), src, G)) / (2 * h)
+        assert abs(fd - dk.ravel()[v]) <= 1e-6 * max(1.0, abs(fd)), (v, fd, dk.ravel()[v])
+
+
+def pin_bins_j_jacobian_transpose(m):
+    """L is linear in j: dL/dj[v] = sum_b <G_b, J_b(e_v)> by unit impulses, for a j shared by
+    the bins and, per bin, for a stack of j maps."""
+    shape, j, kap, src, G = _bins_case(73)
+    maps = np.stack([kap * float(s) for s in BIN_SCALES])
+    dj, _, _ = m.trace_bins_vjp(j, kap, BIN_SCALES, src, [9, 6], 0.5, 3.0, 1.0, G, caps=[0, 5])
+    stack = np.stack([j, 0.5 * j, 2.0 * j])
+    djb, dkb, dsb = m.trace_bins_vjp(stack, None, None, src, [9, 6], 0.5, 3.0, 1.0, G, caps=[0, 5],
+                                     kappa_maps=maps)
+    assert dsb is None and dkb.shape == (3,) + shape
+    for v in range(int(np.prod(shape))):
+        e = np.zeros(int(np.prod(shape)))
+        e[v] = 1.0
+        J = oracle.trace_bins(e.reshape(shape), None, None, src, [9, 6], 0.5, 3.0, 1.0, caps=[0, 5],
+                              kappa_maps=maps)
+        per_bin = np.sum(G * J, axis=(1, 2, 3))
+        assert np.isclose(dj.ravel()[v], per_bin.sum(), rtol=1e-10, atol=1e-12)
+        assert np.allclose(djb.reshape(3, -1)[:, v], per_bin, rtol=1e-10, atol=1e-12)
+
+
+BIN_PINS = [pin_bins_scale_finite_differences, pin_bins_kappa_finite_differences, pin_bins_j_jacobian_transpose]
+
+
+@pytest.mark.parametrize("pin", BIN_PINS, ids=lambda p: p.__name__)
+def test_bins_adjoint_pin(pin):
+    pin(oracle)
+
+
+BIN_MUTANTS = {
+    "shared kappa gradient without the bin scale": ("dk += scales[b] * k", "dk += k"),
+    "scale gradient against the scaled kappa": ("ds[b] = float(np.sum(base * k))",
+                                                "ds[b] = float(np.sum(kappas[b] * k))"),
+    "shared j keeps one bin": ("            dj += a\n", "            dj = a\n"),
+    "bins read the base kappa": ("kappas = [base * scales[b] for b in range(n_bins)]",
+                                 "kappas = [base for b in range(n_bins)]"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(BIN_MUTANTS))
+def test_bins_adjoint_pins_catch_mutant(name):
+    src = open(oracle_adjoint.__file__).read()
+    old, new = BIN_MUTANTS[name]
+    assert old in src
+    mod = types.ModuleType("adjoint_mutant")
+    mod.__dict__["__package__"] = "oracle"
+    exec(compile(src.replace(old, new, 1), "adjoint_mutant", "exec"), mod.__dict__)
+    failed = []
+    for pin in BIN_PINS:
+        try:
+            pin(mod)
+        except Exception:  # noqa: BLE001
+            failed.append(pin.__name__)
+    assert failed, f"no pin catches: {name}"
