@@ -364,6 +364,39 @@ int32_t rtmi_trace_vjp(const float* j_map, const float* kappa_map,
                        float radiation_velocity, float time_step, const float* grad_field,
                        float* grad_j, float* grad_kappa, void* stream);
 
+/* Adjoint of rtmi_trace_bins (Sec. 4, "Gradient-based inversion", with the frequency
+ * bins of Sec. 2, "Frequency-bin agnosticism": each bin is an independent problem, so its
+ * gradient is the one-bin adjoint above at (j_b, kappa_b), and inputs shared by the bins
+ * collect every bin's contribution). grad_fields = dL/dJ_b (DEVICE float[n_bins][cells]).
+ * Outputs (DEVICE, overwritten):
+ *  - grad_j: dL/dj, float[cells] when j is shared (j_bin_stride 0: the sum over bins),
+ *    else float[n_bins][cells] (dL/dj_b);
+ *  - grad_kappa: with a shared kappa and kappa_b = kappa_scale[b] kappa (kappa_bin_stride
+ *    0), float[cells] holding sum_b kappa_scale[b] dL/dkappa_b; with per-bin kappa maps,
+ *    float[n_bins][cells] holding dL/dkappa_b;
+ *  - grad_kappa_scale: NULL, or (shared kappa only) float[n_bins] holding
+ *    dL/dkappa_scale[b] = sum_v kappa[v] dL/dkappa_b[v], summed in binary64.
+ * Other arguments as rtmi_trace_bins (options are not taken: the float tiled path with the
+ * Fibonacci directions). RTMI_ERR_INVALID_ARG when grad_kappa_scale is given with per-bin
+ * kappa maps. Workspace as rtmi_trace_vjp, reused bin after bin. */
+int32_t rtmi_trace_bins_vjp(const float* j_maps, int64_t j_bin_stride,
+                            const float* kappa_maps, int64_t kappa_bin_stride,
+                            const float* kappa_scale, int32_t n_bins,
+                            int32_t nx, int32_t ny, int32_t nz, int32_t n_src,
+                            const float* source_pos, const int32_t* num_rays,
+                            const int32_t* substep_cap, float step_size,
+                            float radiation_velocity, float time_step, const float* grad_fields,
+                            float* grad_j, float* grad_kappa, float* grad_kappa_scale, void* stream);
+
+/* Helpers of the parameter fits (Sec. 4: a scalar amplitude recovered through the
+ * tracer; here also a global opacity scale). rtmi_dot: out[0] = sum_i a[i] b[i] (DEVICE
+ * float[count] each; out DEVICE float[1], overwritten), summed in binary64 by one
+ * work-group in a fixed order. rtmi_scaled_copy: out[i] = scale[0] * in[i] with the
+ * scale read from DEVICE memory (so a fitted parameter never leaves the device). */
+int32_t rtmi_dot(const float* a, const float* b, int64_t count, float* out, void* stream);
+int32_t rtmi_scaled_copy(const float* in, const float* scale, float* out, int64_t count,
+                         void* stream);
+
 /* Squared field error of the inverse problem (Sec. 4, "Gradient-based inversion": a
  * loss on the traced field, minimised through the tracer's gradient): *loss =
  * scale * sum_i (field[i] - target[i])^2 (DEVICE float[1], overwritten) and grad[i] =

@@ -19,7 +19,8 @@ namespace {
 
 struct SampleAD {
   float j;      // trilinear j
-  float kap;    // nearest kappa
+  float kap;    // nearest kappa of this bin (table kappa x kscale)
+  float kraw;   // nearest kappa as the table holds it
   float g;      // c * trilinear G
   int cid;      // box corner the sample has collapsed onto, or -1
 };
@@ -52,15 +53,16 @@ __device__ __forceinline__ SampleAD adjoint_sample(const AdjointArgs& a, float s
   const int nsel = (X.nearest != X.lo ? 4 : 0) | (Y.nearest != Y.lo ? 2 : 0) | (Z.nearest != Z.lo ? 1 : 0);
   SampleAD r;
   r.j = 0.0f;
-  r.kap = kc[0];
+  r.kraw = kc[0];
   float gsum = 0.0f;
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     r.j += (cx[c >> 2] * cy[(c >> 1) & 1]) * cz[c & 1] * jc[c];
-    r.kap = c == nsel ? kc[c] : r.kap;
+    r.kraw = c == nsel ? kc[c] : r.kraw;
     gsum += (wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1] * a.grad[ox[c >> 2] + oy[(c >> 1) & 1] + oz[c & 1]];
   }
   r.g = wray * gsum;
+  r.kap = r.kraw * a.kscale;
   const bool out3 = axis_clamped(x, nx) && axis_clamped(y, ny) && axis_clamped(z, nz);
   r.cid = out3 ? ((x >= 0.0f ? 4 : 0) | (y >= 0.0f ? 2 : 0) | (z >= 0.0f ? 1 : 0)) : -1;
   return r;
@@ -78,6 +80,7 @@ __global__ void __launch_bounds__(kBlock) adjoint_record_kernel(const AdjointArg
   int s = 0;
   while (s + 1 < a.n_src && blk >= a.blk_begin[s + 1]) ++s;
   const int ray = (blk - a.blk_begin[s]) * kBlock + tid;
+  double dsc = 0.0;   // sum of table kappa(nearest) x dL/dkappa_bin over this lane's samples
   if (blk < nblk && ray < a.nrays[s]) {
     const float4 d = a.dirs[s][ray];
     const float sx = a.sx[s], sy = a.sy[s], sz = a.sz[s];
@@ -112,7 +115,7 @@ __global__ void __launch_bounds__(kBlock) adjoint_record_kernel(const AdjointArg
     for (int seg = nseg - 1; seg >= 0; --seg) {
       const float2 c0 = ck[seg];
       float Ir = c0.x, Er = c0.y;
-      float jk[kSeg], ak[kSeg], Ik[kSeg], Ek[kSeg], gk[kSeg];
+      float jk[kSeg], ak[kSeg], Ik[kSeg], Ek[kSeg], gk[kSeg], kr[kSeg];
       int cid[kSeg];
 #pragma unroll
       for (int t = 0; t < kSeg; ++t) {
@@ -122,6 +125,7 @@ __global__ void __launch_bounds__(kBlock) adjoint_record_kernel(const AdjointArg
         jk[t] = q.j;
         ak[t] = att;
         gk[t] = q.g;
+        kr[t] = q.kraw;
         cid[t] = q.cid;
         Ik[t] = Ir;
         Ek[t] = Er;
@@ -136,7 +140,9 @@ __global__ void __launch_bounds__(kBlock) adjoint_record_kernel(const AdjointArg
         if (seg * kSeg + t < nsub) {
           const float ibar = gk[t] + ibar_next * a_next;
           float vjv = ibar * Ek[t] * ds;
-          float vkv = -ds * (ibar * Ik[t] * ak[t] + suffix);
+          float vkv = -ds * (ibar * Ik[t] * ak[t] + suffix);   // dL/dkappa_bin of the sample
+          dsc += static_cast<double>(kr[t]) * static_cast<double>(vkv);
+          vkv *= a.kgrad_scale;
           suffix += ibar * jk[t] * Ek[t] * ds;
           ibar_next = ibar;
           a_next = ak[t];
@@ -167,6 +173,11 @@ __global__ void __launch_bounds__(kBlock) adjoint_record_kernel(const AdjointArg
       atomicAdd(&ctail[0][corner], tail_j);
       atomicAdd(&ctail[1][corner], tail_k);
     }
+  }
+  if (a.dscale) {   // (all lanes here; those without a ray hold zero)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) dsc += __shfl_xor(dsc, off, 64);
+    if ((tid & 63) == 0 && dsc != 0.0) atomicAdd(a.dscale, dsc);
   }
   __syncthreads();
   if (tid < 16) {
@@ -204,6 +215,59 @@ hipError_t launch_field_mse(const float* field, const float* target, long long n
   hipLaunchKernelGGL(zero_word_kernel, dim3(1), dim3(64), 0, s, loss);
   hipLaunchKernelGGL(field_mse_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, field, target, n,
                      scale, grad, loss);
+  return hipGetLastError();
+}
+
+namespace {
+constexpr int kDotThreads = 1024;
+
+// out[0] = sum_i a[i] b[i], by one work-group in a fixed order (binary64 partial sums), so
+// the result does not depend on scheduling.
+__global__ void __launch_bounds__(kDotThreads) dot_kernel(const float* __restrict__ a, const float* __restrict__ b,
+                                                          long long n, float* __restrict__ out) {
+  __shared__ double part[kDotThreads];
+  const int tid = static_cast<int>(threadIdx.x);
+  double acc = 0.0;
+  for (long long i = tid; i < n; i += kDotThreads) acc += static_cast<double>(a[i]) * static_cast<double>(b[i]);
+  part[tid] = acc;
+  __syncthreads();
+  for (int w = kDotThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) part[tid] += part[tid + w];
+    __syncthreads();
+  }
+  if (tid == 0) out[0] = static_cast<float>(part[0]);
+}
+
+// out[i] = scale[0] * in[i], the scale read from device memory
+__global__ void scaled_copy_kernel(const float* __restrict__ in, const float* __restrict__ scale, float* __restrict__ out,
+                                   long long n) {
+  const float s = scale[0];
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    out[i] = s * in[i];
+}
+
+__global__ void f64_to_f32_kernel(const double* __restrict__ in, float* __restrict__ out, int n) {
+  const int i = static_cast<int>(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n) out[i] = static_cast<float>(in[i]);
+}
+}  // namespace
+
+hipError_t launch_f64_to_f32(const double* in, float* out, int n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(f64_to_f32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(const float* a, const float* b, long long n, float* out, hipStream_t s) {
+  hipLaunchKernelGGL(dot_kernel, dim3(1), dim3(kDotThreads), 0, s, a, b, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_scaled_copy(const float* in, const float* scale, float* out, long long n, hipStream_t s) {
+  long long blocks = (n + 1023) / 1024;
+  blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
+  hipLaunchKernelGGL(scaled_copy_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, in, scale, out, n);
   return hipGetLastError();
 }
 

@@ -1263,10 +1263,19 @@ int32_t run(const Problem& p, bool no_alloc = false) {
 }
 
 // ---- adjoint: checkpointed reverse sweep + tile deposits of dL/dj and dL/dkappa ----
-int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_k) {
+// Bins are independent problems (Sec. 2, "Frequency-bin agnosticism"), so each bin's
+// adjoint is the one-bin adjoint at (j_b, kappa_b), run bin after bin. A j or kappa shared
+// by the bins collects every bin's gradient in one output (the tile passes add into it);
+// with kappa_b = s_b kappa, a bin's dL/dkappa deposits are multiplied by s_b, and
+// dL/ds_b = sum over samples of kappa(nearest voxel) x the sample's dL/dkappa_b.
+int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_k, float* grad_scale) {
   Plan plan;
   if (int32_t st = validate(p, &plan)) return st;
   if (!grad || !grad_j || !grad_k) return fail(RTMI_ERR_INVALID_ARG, "null gradient pointer");
+  if (grad_scale && p.k_stride != 0)
+    return fail(RTMI_ERR_INVALID_ARG, "grad_kappa_scale needs a kappa shared by the bins (kappa_bin_stride 0)");
+  if (plan.det || !plan.tiled || plan.explicit_dirs)
+    return fail(RTMI_ERR_UNSUPPORTED, "the adjoint runs the float tiled path with the Fibonacci directions");
   const hipStream_t st = p.stream;
   plan.tables.resize(p.n_src);
   for (int32_t s = 0; s < p.n_src; ++s)
@@ -1299,7 +1308,9 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
   }
   const size_t sched_bytes = TileSchedule::bytes(tiles, max_blocks);
   const size_t srcs_bytes = align256(size_t(kMaxSrcPerLaunch) * sizeof(rtmi::SrcRec));
-  const size_t rec_off = corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes) + sched_bytes + srcs_bytes;
+  const size_t dscale_bytes = align256(size_t(p.n_bins) * sizeof(double));
+  const size_t rec_off = corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes) + sched_bytes + srcs_bytes +
+                         dscale_bytes;
   unsigned long long* dropped = nullptr;
   if (int32_t rc = dropped_counter(&dropped)) return rc;
   Scratch scratch;
@@ -1309,99 +1320,112 @@ int32_t run_vjp(const Problem& p, const float* grad, float* grad_j, float* grad_
   TileSchedule sched;
   sched.carve(ws + corner_bytes + med_bytes + 2 * v_bytes + align256(c_bytes), tiles, max_blocks);
   uint2* recs = reinterpret_cast<uint2*>(ws + rec_off);
-  rtmi::SrcRec* srcs = reinterpret_cast<rtmi::SrcRec*>(ws + rec_off - srcs_bytes);
+  rtmi::SrcRec* srcs = reinterpret_cast<rtmi::SrcRec*>(ws + rec_off - dscale_bytes - srcs_bytes);
+  double* dscale = reinterpret_cast<double*>(ws + rec_off - dscale_bytes);
   float* corner = reinterpret_cast<float*>(ws);  // [0..7] for dL/dj, [8..15] for dL/dkappa
   float4* med = reinterpret_cast<float4*>(ws + corner_bytes);
   float* Vj = reinterpret_cast<float*>(ws + corner_bytes + med_bytes);
   float* Vk = reinterpret_cast<float*>(ws + corner_bytes + med_bytes + v_bytes);
   float2* ckpt = reinterpret_cast<float2*>(ws + corner_bytes + med_bytes + 2 * v_bytes);
   hipError_t e;
-  if ((e = rtmi::launch_cell_table(p.j, p.kap, med, p.nx, p.ny, p.nz, st)) != hipSuccess)
-    return hip_fail(e, "gather table");
-  if ((e = rtmi::launch_fill_zero(grad_j, plan.cells, st)) != hipSuccess ||
-      (e = rtmi::launch_fill_zero(grad_k, plan.cells, st)) != hipSuccess)
+  // every bin's deposits add into these, zeroed once
+  if ((e = rtmi::launch_fill_zero(grad_j, plan.cells * (p.j_stride ? p.n_bins : 1), st)) != hipSuccess ||
+      (e = rtmi::launch_fill_zero(grad_k, plan.cells * (p.k_stride ? p.n_bins : 1), st)) != hipSuccess ||
+      (grad_scale && (e = rtmi::launch_fill_zero_u64(reinterpret_cast<unsigned long long*>(dscale), p.n_bins, st)) !=
+                         hipSuccess))
     return hip_fail(e, "fill");
 
-  for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
-    const int32_t ns = std::min(kMaxSrcPerLaunch, p.n_src - s0);
-    rtmi::AdjointArgs r;
-    rtmi::TileArgs t;
-    std::memset(&r, 0, sizeof r);
-    std::memset(&t, 0, sizeof t);
-    int64_t v_elems = 0, c_elems = 0;
-    int blocks = 0, patches = 0;
-    GroupTable T;   // the tile passes' source table, in launch order
-    for (int32_t i = 0; i < ns; ++i) {
-      const int32_t s = s0 + i;
-      const int32_t nr = plan.nsub[s] > 0 ? p.nrays[s] : 0;
-      r.blk_begin[i] = blocks;
-      r.sx[i] = p.src[3 * s];
-      r.sy[i] = p.src[3 * s + 1];
-      r.sz[i] = p.src[3 * s + 2];
-      r.wray[i] = ray_weight(p, plan, s);
-      r.nrays[i] = nr;
-      r.nsub[i] = plan.nsub[s];
-      r.vbase[i] = v_elems;
-      r.cstride[i] = (plan.nsub[s] + rtmi::kSeg - 1) / rtmi::kSeg;
-      r.cbase[i] = c_elems;
-      r.dirs[i] = plan.tables[s].dirs;
-      rtmi::SrcRec q;
-      std::memset(&q, 0, sizeof q);
-      q.sx = r.sx[i];
-      q.sy = r.sy[i];
-      q.sz = r.sz[i];
-      q.wray = r.wray[i];
-      q.nrays = nr;
-      q.nsub = plan.nsub[s];
-      q.vbase = v_elems;
-      q.dirs = plan.tables[s].dirs;
-      q.pbounds = plan.tables[s].bounds;
-      q.pbegin = patches;
-      q.nseg = 1;
-      T.rec.push_back(q);
-      v_elems += int64_t(nr) * row_stride(plan.nsub[s]);
-      c_elems += int64_t(nr) * r.cstride[i];
-      blocks += (nr + kBlock - 1) / kBlock;
-      patches += (nr + kPatch - 1) / kPatch;
+  for (int32_t b = 0; b < p.n_bins; ++b) {
+    const float s_b = (p.k_stride == 0 && p.kscale) ? p.kscale[b] : 1.0f;
+    if ((e = rtmi::launch_cell_table(p.j + b * p.j_stride, p.kap + b * p.k_stride, med, p.nx, p.ny, p.nz, st)) !=
+        hipSuccess)
+      return hip_fail(e, "gather table");
+    for (int32_t s0 = 0; s0 < p.n_src; s0 += kMaxSrcPerLaunch) {
+      const int32_t ns = std::min(kMaxSrcPerLaunch, p.n_src - s0);
+      rtmi::AdjointArgs r;
+      rtmi::TileArgs t;
+      std::memset(&r, 0, sizeof r);
+      std::memset(&t, 0, sizeof t);
+      int64_t v_elems = 0, c_elems = 0;
+      int blocks = 0, patches = 0;
+      GroupTable T;   // the tile passes' source table, in launch order
+      for (int32_t i = 0; i < ns; ++i) {
+        const int32_t s = s0 + i;
+        const int32_t nr = plan.nsub[s] > 0 ? p.nrays[s] : 0;
+        r.blk_begin[i] = blocks;
+        r.sx[i] = p.src[3 * s];
+        r.sy[i] = p.src[3 * s + 1];
+        r.sz[i] = p.src[3 * s + 2];
+        r.wray[i] = ray_weight(p, plan, s);
+        r.nrays[i] = nr;
+        r.nsub[i] = plan.nsub[s];
+        r.vbase[i] = v_elems;
+        r.cstride[i] = (plan.nsub[s] + rtmi::kSeg - 1) / rtmi::kSeg;
+        r.cbase[i] = c_elems;
+        r.dirs[i] = plan.tables[s].dirs;
+        rtmi::SrcRec q;
+        std::memset(&q, 0, sizeof q);
+        q.sx = r.sx[i];
+        q.sy = r.sy[i];
+        q.sz = r.sz[i];
+        q.wray = r.wray[i];
+        q.nrays = nr;
+        q.nsub = plan.nsub[s];
+        q.vbase = v_elems;
+        q.dirs = plan.tables[s].dirs;
+        q.pbounds = plan.tables[s].bounds;
+        q.pbegin = patches;
+        q.nseg = 1;
+        T.rec.push_back(q);
+        v_elems += int64_t(nr) * row_stride(plan.nsub[s]);
+        c_elems += int64_t(nr) * r.cstride[i];
+        blocks += (nr + kBlock - 1) / kBlock;
+        patches += (nr + kPatch - 1) / kPatch;
+      }
+      r.blk_begin[ns] = blocks;
+      if ((e = write_group_table(T, srcs, p.ds, st)) != hipSuccess) return hip_fail(e, "source table");
+      t.src = srcs;
+      t.n_pairs = patches;
+      r.med = med;
+      r.grad = grad + b * plan.cells;
+      r.Vj = Vj;
+      r.Vk = Vk;
+      r.ckpt = ckpt;
+      r.corner_j = corner;
+      r.corner_k = corner + 8;
+      r.kscale = s_b;
+      r.kgrad_scale = s_b;
+      r.dscale = grad_scale ? dscale + b : nullptr;
+      r.nx = t.nx = p.nx;
+      r.ny = t.ny = p.ny;
+      r.nz = t.nz = p.nz;
+      r.ds = t.ds = p.ds;
+      r.n_src = t.n_src = ns;
+      t.v_bin_stride = v_elems;
+      t.out_stride = plan.cells;
+      t.tiles_x = tiles_x;
+      t.tiles_y = tiles_y;
+      t.tiles_z = tiles_z;
+      sched.apply(t, 0, recs, rec_capacity, dropped);
+      if ((e = rtmi::launch_fill_zero(corner, 64, st)) != hipSuccess) return hip_fail(e, "fill");
+      if (blocks > 0 && (e = rtmi::launch_adjoint_record(r, blocks, st)) != hipSuccess)
+        return hip_fail(e, "adjoint launch");
+      t.V = Vj;
+      t.corner = corner;
+      t.out = grad_j + b * (p.j_stride ? plan.cells : 0);
+      // one schedule and one set of records serve both deposits (same rays, same tiles)
+      if ((e = rtmi::launch_tile_schedule(t, tiles, st)) != hipSuccess ||
+          (e = rtmi::launch_tile_fill(t, tiles, st)) != hipSuccess ||
+          (e = rtmi::launch_tile_run(t, 1, false, false, st)) != hipSuccess)
+        return hip_fail(e, "tile launch");
+      t.V = Vk;
+      t.corner = corner + 8;
+      t.out = grad_k + b * (p.k_stride ? plan.cells : 0);
+      if ((e = rtmi::launch_tile_run(t, 1, false, true, st)) != hipSuccess) return hip_fail(e, "tile launch");
     }
-    r.blk_begin[ns] = blocks;
-    if ((e = write_group_table(T, srcs, p.ds, st)) != hipSuccess) return hip_fail(e, "source table");
-    t.src = srcs;
-    t.n_pairs = patches;
-    r.med = med;
-    r.grad = grad;
-    r.Vj = Vj;
-    r.Vk = Vk;
-    r.ckpt = ckpt;
-    r.corner_j = corner;
-    r.corner_k = corner + 8;
-    r.nx = t.nx = p.nx;
-    r.ny = t.ny = p.ny;
-    r.nz = t.nz = p.nz;
-    r.ds = t.ds = p.ds;
-    r.n_src = t.n_src = ns;
-    t.v_bin_stride = v_elems;
-    t.out_stride = plan.cells;
-    t.tiles_x = tiles_x;
-    t.tiles_y = tiles_y;
-    t.tiles_z = tiles_z;
-    sched.apply(t, 0, recs, rec_capacity, dropped);
-    if ((e = rtmi::launch_fill_zero(corner, 64, st)) != hipSuccess) return hip_fail(e, "fill");
-    if (blocks > 0 && (e = rtmi::launch_adjoint_record(r, blocks, st)) != hipSuccess)
-      return hip_fail(e, "adjoint launch");
-    t.V = Vj;
-    t.corner = corner;
-    t.out = grad_j;
-    // one schedule and one set of records serve both deposits (same rays, same tiles)
-    if ((e = rtmi::launch_tile_schedule(t, tiles, st)) != hipSuccess ||
-        (e = rtmi::launch_tile_fill(t, tiles, st)) != hipSuccess ||
-        (e = rtmi::launch_tile_run(t, 1, false, false, st)) != hipSuccess)
-      return hip_fail(e, "tile launch");
-    t.V = Vk;
-    t.corner = corner + 8;
-    t.out = grad_k;
-    if ((e = rtmi::launch_tile_run(t, 1, false, true, st)) != hipSuccess) return hip_fail(e, "tile launch");
   }
+  if (grad_scale && (e = rtmi::launch_f64_to_f32(dscale, grad_scale, p.n_bins, st)) != hipSuccess)
+    return hip_fail(e, "scale gradient");
   if ((e = scratch.release(st)) != hipSuccess) return hip_fail(e, "workspace release");
   g_error.clear();
   return RTMI_OK;
@@ -1699,7 +1723,38 @@ int32_t rtmi_trace_vjp(const float* j_map, const float* kappa_map, int32_t nx, i
   const Problem p{j_map, 0, kappa_map, 0, nullptr, 1, nx, ny, nz, n_src, source_pos, num_rays,
                   substep_cap, step_size, radiation_velocity, time_step, grad_j, nullptr,
                   static_cast<hipStream_t>(stream)};
-  return run_vjp(p, grad_field, grad_j, grad_kappa);
+  return run_vjp(p, grad_field, grad_j, grad_kappa, nullptr);
+}
+
+int32_t rtmi_trace_bins_vjp(const float* j_maps, int64_t j_bin_stride, const float* kappa_maps,
+                            int64_t kappa_bin_stride, const float* kappa_scale, int32_t n_bins, int32_t nx,
+                            int32_t ny, int32_t nz, int32_t n_src, const float* source_pos,
+                            const int32_t* num_rays, const int32_t* substep_cap, float step_size,
+                            float radiation_velocity, float time_step, const float* grad_fields,
+                            float* grad_j, float* grad_kappa, float* grad_kappa_scale, void* stream) {
+  const Problem p{j_maps, j_bin_stride, kappa_maps, kappa_bin_stride,
+                  kappa_bin_stride ? nullptr : kappa_scale, n_bins, nx, ny, nz, n_src,
+                  source_pos, num_rays, substep_cap, step_size, radiation_velocity, time_step,
+                  grad_j, nullptr, static_cast<hipStream_t>(stream)};
+  return run_vjp(p, grad_fields, grad_j, grad_kappa, grad_kappa_scale);
+}
+
+int32_t rtmi_dot(const float* a, const float* b, int64_t count, float* out, void* stream) {
+  if (!a || !b || !out) return fail(RTMI_ERR_INVALID_ARG, "null pointer");
+  if (count < 1) return fail(RTMI_ERR_INVALID_ARG, "count must be >= 1");
+  const hipError_t e = rtmi::launch_dot(a, b, count, out, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "rtmi_dot");
+  g_error.clear();
+  return RTMI_OK;
+}
+
+int32_t rtmi_scaled_copy(const float* in, const float* scale, float* out, int64_t count, void* stream) {
+  if (!in || !scale || !out) return fail(RTMI_ERR_INVALID_ARG, "null pointer");
+  if (count < 1) return fail(RTMI_ERR_INVALID_ARG, "count must be >= 1");
+  const hipError_t e = rtmi::launch_scaled_copy(in, scale, out, count, static_cast<hipStream_t>(stream));
+  if (e != hipSuccess) return hip_fail(e, "rtmi_scaled_copy");
+  g_error.clear();
+  return RTMI_OK;
 }
 
 int32_t rtmi_field_mse(const float* field, const float* target, int64_t count, float scale,

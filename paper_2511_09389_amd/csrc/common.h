@@ -153,6 +153,9 @@ struct AdjointArgs {
   float2* ckpt;               // (I, E) at the start of every segment of every ray
   float* corner_j;            // [8] sums of collapsed samples per box corner
   float* corner_k;            // [8]
+  float kscale;               // this bin's opacity: table kappa x kscale (binary32, as the forward)
+  float kgrad_scale;          // dL/dkappa deposits are multiplied by this (the bin scale of a shared kappa)
+  double* dscale;             // or null: += sum over samples of table kappa(nearest) x dL/dkappa_bin
   int nx, ny, nz;
   float ds;
   int n_src;
@@ -239,6 +242,10 @@ hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool deterministic, bo
 // The tile pass of one bin of a launch (launch_tile_run runs every bin's in turn).
 hipError_t launch_tile_bin(const TileArgs& a, int bin, bool deterministic, bool nearest, hipStream_t s);
 hipError_t launch_adjoint_record(const AdjointArgs& a, int n_blocks, hipStream_t s);
+// out[i] = (float) in[i], i < n (the scale gradients, summed in binary64)
+hipError_t launch_f64_to_f32(const double* in, float* out, int n, hipStream_t s);
+hipError_t launch_dot(const float* a, const float* b, long long n, float* out, hipStream_t s);
+hipError_t launch_scaled_copy(const float* in, const float* scale, float* out, long long n, hipStream_t s);
 // loss[0] = scale * sum (field - target)^2 (overwritten), grad = 2 scale (field - target).
 hipError_t launch_field_mse(const float* field, const float* target, long long n, float scale, float* grad,
                             float* loss, hipStream_t s);

@@ -69,8 +69,12 @@ def _load():
                                          F32, P, ctypes.POINTER(Options), P]),
         "rtmi_static_scratch_bytes": (I64, []),
         "rtmi_field_mse": (I32, [P, P, I64, F32, P, P, P]),
+        "rtmi_dot": (I32, [P, P, I64, P, P]),
+        "rtmi_scaled_copy": (I32, [P, P, P, I64, P]),
         "rtmi_debug_rays": (I32, [P, P, I32, I32, I32, P, I32, F32, F32, F32, I32, P, P, P]),
         "rtmi_trace_vjp": (I32, [P, P, I32, I32, I32, I32, P, P, P, F32, F32, F32, P, P, P, P]),
+        "rtmi_trace_bins_vjp": (I32, [P, I64, P, I64, P, I32, I32, I32, I32, I32, P, P, P, F32, F32, F32,
+                                      P, P, P, P, P]),
         "rtmi_plan_create": (I32, [I32, I32, I32, I32, P, P, P, I32, I64, I64, P, F32, F32, F32,
                                    ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_void_p)]),
         "rtmi_plan_execute": (I32, [P, P, P, P, P]),
@@ -400,6 +404,81 @@ def trace_vjp(j_map, kappa_map, source_pos, num_rays, step_size, radiation_veloc
                                   _dev(grad_field, "grad_field", 3), _dev(grad_j, "grad_j", 3),
                                   _dev(grad_kappa, "grad_kappa", 3), _stream(j_map.device)))
     return grad_j, grad_kappa
+
+
+def trace_bins_vjp(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity, time_step,
+                   grad_fields, kappa_scale=None, substep_cap=None, scale_grad=False, grad_j=None,
+                   grad_kappa=None, grad_kappa_scale=None):
+    """Adjoint of trace_bins for dL/dJ_b = grad_fields ([B][nx][ny][nz]). j_maps and
+    kappa_maps are 3-D (shared by the bins) or 4-D [B][...], as for trace_bins. Returns
+    (dL/dj, dL/dkappa, dL/dkappa_scale): gradients of shared maps are 3-D (summed over bins,
+    kappa's through each bin's scale), of per-bin maps 4-D; the scale gradient is a [B]
+    float32 device tensor when scale_grad is set (a shared kappa only), else None."""
+    grid = tuple(j_maps.shape[-3:])
+    if tuple(kappa_maps.shape[-3:]) != grid:
+        raise ValueError("j and kappa grids differ")
+    cells = grid[0] * grid[1] * grid[2]
+    n_bins = grad_fields.shape[0] if grad_fields.dim() == 4 else 0
+    if n_bins < 1:
+        raise ValueError("grad_fields must be [B][nx][ny][nz]")
+    _same(grad_fields, "grad_fields", (n_bins,) + grid, j_maps.device)
+    for t, what in ((j_maps, "j_maps"), (kappa_maps, "kappa_maps")):
+        if t.dim() == 4 and t.shape[0] != n_bins:
+            raise ValueError(f"{what} has {t.shape[0]} bins, expected {n_bins}")
+        if t.device != j_maps.device:
+            raise ValueError("j_maps and kappa_maps must be on one device")
+    per_j, per_k = j_maps.dim() == 4, kappa_maps.dim() == 4
+    scale = None
+    if per_k:
+        if kappa_scale is not None or scale_grad:
+            raise ValueError("kappa_scale and its gradient apply to a shared 3-D kappa only")
+    elif kappa_scale is not None:
+        scale = _host_f32(kappa_scale).ravel()
+        if scale.size != n_bins:
+            raise ValueError("kappa_scale must have one entry per bin")
+    src, nr, cap = _per_source(source_pos, num_rays, substep_cap)
+    gj_shape = (n_bins,) + grid if per_j else grid
+    gk_shape = (n_bins,) + grid if per_k else grid
+    grad_j = _new_field(gj_shape, j_maps) if grad_j is None else _same(grad_j, "grad_j", gj_shape, j_maps.device)
+    grad_kappa = _new_field(gk_shape, j_maps) if grad_kappa is None else \
+        _same(grad_kappa, "grad_kappa", gk_shape, j_maps.device)
+    gs = None
+    if scale_grad:
+        gs = _new_field((n_bins,), j_maps) if grad_kappa_scale is None else \
+            _same(grad_kappa_scale, "grad_kappa_scale", (n_bins,), j_maps.device)
+    with torch.cuda.device(j_maps.device):
+        _check(lib.rtmi_trace_bins_vjp(
+            _dev(j_maps, "j_maps", (3, 4)), cells if per_j else 0,
+            _dev(kappa_maps, "kappa_maps", (3, 4)), cells if per_k else 0,
+            None if scale is None else scale.ctypes.data_as(ctypes.c_void_p), n_bins,
+            grid[0], grid[1], grid[2], src.shape[0], src.ctypes.data_as(ctypes.c_void_p),
+            nr.ctypes.data_as(ctypes.c_void_p), None if cap is None else cap.ctypes.data_as(ctypes.c_void_p),
+            step_size, radiation_velocity, time_step, _dev(grad_fields, "grad_fields", 4),
+            _dev(grad_j, "grad_j", (3, 4)), _dev(grad_kappa, "grad_kappa", (3, 4)),
+            None if gs is None else _dev(gs, "grad_kappa_scale", 1), _stream(j_maps.device)))
+    return grad_j, grad_kappa, gs
+
+
+def dot(a, b, out=None):
+    """out[0] = sum(a * b) over two equal-sized float32 device tensors (binary64 sum)."""
+    if a.numel() != b.numel() or a.numel() < 1:
+        raise ValueError("dot needs two non-empty tensors of one size")
+    out = torch.empty(1, dtype=torch.float32, device=a.device) if out is None else _same(out, "out", (1,), a.device)
+    with torch.cuda.device(a.device):
+        _check(lib.rtmi_dot(_dev(a, "a"), _dev(_same(b, "b", tuple(b.shape), a.device), "b"), a.numel(),
+                            _dev(out, "out", 1), _stream(a.device)))
+    return out
+
+
+def scaled_copy(x, scale, out=None):
+    """out = scale[0] * x, with scale a float32 device tensor of at least one element."""
+    if scale.numel() < 1:
+        raise ValueError("scale needs one element")
+    out = torch.empty_like(x) if out is None else _same(out, "out", tuple(x.shape), x.device)
+    with torch.cuda.device(x.device):
+        _check(lib.rtmi_scaled_copy(_dev(x, "x"), _dev(_same(scale, "scale", tuple(scale.shape), x.device), "scale"),
+                                    _dev(out, "out"), x.numel(), _stream(x.device)))
+    return out
 
 
 def field_mse(field, target, scale=None, grad=None, loss=None):
