@@ -2,12 +2,11 @@
 // accumulation. Activations are channels-last bf16 [n][z][y][x][32]; weights bf16
 // [27][32 co][32 ci] with tap = ((dz+1)*3 + (dy+1))*3 + (dx+1); zero padding.
 //
-// conv_kernel (forward and backward-data): an implicit GEMM, out[v][co] = sum over taps
-// and ci of x[v + off(tap)][ci] W[tap][co][ci], one wave per 32 output voxels x 32
-// channels: 27 taps x 2 MFMA 32x32x16 steps. The weights sit in LDS (staged flipped and
+// conv_tile_kernel (forward and backward-data): an implicit GEMM, out[v][co] = sum over
+// taps and ci of x[v + off(tap)][ci] W[tap][co][ci], 32 output voxels x 32 channels per
+// MFMA 32x32x16 accumulator: 27 taps x 2 steps. The weights sit in LDS (staged flipped and
 // transposed for the backward-data pass, where dx[u][ci] = sum W[tap][co][ci]
-// dz[u - off(tap)][co]). The A operand (8 consecutive channels of one voxel) is one
-// 16-byte load straight from global memory.
+// dz[u - off(tap)][co]), and so does each block's input with its halo.
 // wgrad: dW[tap][co][ci] = sum_v dz[v][co] x[v + off(tap)][ci], a GEMM over the voxels on
 // channel-major copies of dz and of x (three, shifted by dx = -1, 0, +1), so that a row
 // shift is a whole number of rows and every operand an aligned 16-byte load.
@@ -21,7 +20,6 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int kC = kConvChannels;   // 32
-constexpr int kConvThreads = 256;   // 4 waves, 32 output voxels each per round
 
 __device__ __forceinline__ float bf16_to_f32(unsigned short h) {
   return __uint_as_float(static_cast<unsigned>(h) << 16);
@@ -33,90 +31,180 @@ __device__ __forceinline__ unsigned short f32_to_bf16(float f) {
   return static_cast<unsigned short>((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
+// erf by the rational approximation of Abramowitz and Stegun (Handbook of Mathematical
+// Functions, 7.1.26): erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2) with
+// t = 1 / (1 + p x) for x >= 0, odd in x; absolute error below 1.5e-7, far under the bf16
+// rounding of the activations it feeds.
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
+  const float poly = t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  const float r = 1.0f - poly * __expf(-ax * ax);
+  return copysignf(r, x);
+}
+
 __device__ __forceinline__ float gelu_f(float z) {
-  return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f));
+  return 0.5f * z * (1.0f + erf_as(z * 0.70710678118654752f));
 }
 
 __device__ __forceinline__ float gelu_grad_f(float z) {
-  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+  return 0.5f * (1.0f + erf_as(z * 0.70710678118654752f)) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
 }
 
 // MFMA 32x32 accumulator layout (wave64): element i of lane l is row
 // 8 (i / 4) + 4 (l / 32) + i % 4, column l % 32.
 __device__ __forceinline__ int acc_row(int i, int lane) { return 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3); }
 
+// conv_tile_kernel: a persistent work-group of eight waves stages the weights once, then
+// takes blocks of 2 (z) x 8 (y) x 32 (x) output voxels in turn; it loads a block's input
+// with its one-voxel halo (4 x 10 x 34 voxels, 64 bytes each) once, and every wave
+// computes two 32-voxel rows (two accumulators sharing each weight fragment) reading its
+// A operands from that halo for all 27 taps. The halo's 16-byte chunks are XOR-swizzled
+// by voxel, chunk c of voxel v at c ^ ((v >> 2) & 3), so that any 16 consecutive voxels
+// a fragment reads (256 bytes, one pass over the 64 banks) hit distinct banks; the weights' fragments are laid out with the
+// lanes' columns consecutive for the same reason.
+constexpr int kBz = 2, kBy = 8, kBx = 32;
+constexpr int kHz = kBz + 2, kHy = kBy + 2, kHx = kBx + 2;
+constexpr int kHaloVox = kHz * kHy * kHx;          // 1360 voxels, 87,040 bytes
+constexpr int kTileConvThreads = 512;              // eight waves, two output rows each
+
+__device__ __forceinline__ int halo_slot(int v, int c) {   // in 16-byte chunks
+  return v * 4 + (c ^ ((v >> 2) & 3));
+}
+
 template <bool BACKWARD>
-__global__ void __launch_bounds__(kConvThreads) conv_kernel(const ConvArgs a) {
-  // B operand: Bs[tap][half][column][16 k], k contiguous (forward: column co, k = ci;
-  // backward: column ci, k = co, taps mirrored)
-  __shared__ __attribute__((aligned(16))) unsigned short Bs[27 * 2 * kC * 16];
+__global__ void __launch_bounds__(kTileConvThreads) conv_tile_kernel(const ConvArgs a) {
+  // weights: fragment (tap, half h, k-group g) of column col at chunk ((tap * 2 + h) * 2 + g) * 32 + col
+  __shared__ __attribute__((aligned(16))) u16x8 Bs[27 * 2 * 2 * kC];
+  __shared__ __attribute__((aligned(16))) u16x8 Hs[kHaloVox * 4];
   const int tid = static_cast<int>(threadIdx.x), lane = tid & 63, wave = tid >> 6;
-  const unsigned short* W = static_cast<const unsigned short*>(a.w);
-  for (int i = tid; i < 27 * kC * kC; i += kConvThreads) {
-    const int tap = i / (kC * kC), col = (i / kC) % kC, k = i % kC;
-    // forward: W[tap][co = col][ci = k]; backward: W[26 - tap][co = k][ci = col]
-    const unsigned short v = BACKWARD ? W[((26 - tap) * kC + k) * kC + col] : W[(tap * kC + col) * kC + k];
-    Bs[((tap * 2 + (k >> 4)) * kC + col) * 16 + (k & 15)] = v;
+  const u16x8* W8 = static_cast<const u16x8*>(a.w);   // W[tap][co][ci] as 16-byte chunks of ci
+  // (all of a thread's loads are issued before any is stored, so that their latencies
+  // overlap instead of adding up)
+  constexpr int kWChunks = 27 * 2 * 2 * kC;
+  constexpr int kWIters = (kWChunks + kTileConvThreads - 1) / kTileConvThreads;
+  u16x8 wv[kWIters];
+  if constexpr (!BACKWARD) {
+    // forward fragment (tap, h, g, col = co) is W[tap][co][16 h + 8 g ..]: one chunk
+#pragma unroll
+    for (int q = 0; q < kWIters; ++q) {
+      const int i = tid + q * kTileConvThreads;
+      const int col = i % kC, g = (i / kC) % 2, h = (i / (2 * kC)) % 2, tap = i / (4 * kC);
+      if (i < kWChunks) wv[q] = W8[(tap * kC + col) * 4 + h * 2 + g];
+    }
+#pragma unroll
+    for (int q = 0; q < kWIters; ++q)
+      if (tid + q * kTileConvThreads < kWChunks) Bs[tid + q * kTileConvThreads] = wv[q];
+  } else {
+    // backward fragment (tap, h, g, col = ci) is W[26 - tap][16 h + 8 g ..][ci]: a column,
+    // transposed through LDS (the halo's space, before the halo is loaded)
+    const unsigned short* Wraw = reinterpret_cast<const unsigned short*>(Hs);
+#pragma unroll
+    for (int q = 0; q < kWIters; ++q)
+      if (tid + q * kTileConvThreads < kWChunks) wv[q] = W8[tid + q * kTileConvThreads];
+#pragma unroll
+    for (int q = 0; q < kWIters; ++q)
+      if (tid + q * kTileConvThreads < kWChunks) Hs[tid + q * kTileConvThreads] = wv[q];
+    __syncthreads();
+    for (int i = tid; i < 27 * 2 * 2 * kC; i += kTileConvThreads) {
+      const int col = i % kC, g = (i / kC) % 2, h = (i / (2 * kC)) % 2, tap = i / (4 * kC);
+      u16x8 v;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) v[e] = Wraw[((26 - tap) * kC + h * 16 + g * 8 + e) * kC + col];
+      Bs[i] = v;
+    }
+  }
+  const int D = a.d, H = a.h, Wd = a.w_dim;
+  const int nbx = (Wd + kBx - 1) / kBx, nby = (H + kBy - 1) / kBy, nbz = (D + kBz - 1) / kBz;
+  const long long nblocks = static_cast<long long>(a.n) * nbz * nby * nbx;
+  const u16x8* X = static_cast<const u16x8*>(a.x);
+  // Work-group i runs on XCD i mod kXcds: each XCD takes a contiguous range of blocks (a
+  // slab of the volume), so that neighbouring blocks' halos meet in its L2.
+  const long long per_xcd = (nblocks + kXcds - 1) / kXcds;
+  const int xcd = static_cast<int>(blockIdx.x) % kXcds;
+  const long long groups_per_xcd = (gridDim.x + kXcds - 1) / kXcds;
+  for (long long j = blockIdx.x / kXcds; j < per_xcd; j += groups_per_xcd) {
+  const long long blk = xcd * per_xcd + j;
+  if (blk >= nblocks) break;
+  long long b = blk;
+  const int bx = static_cast<int>(b % nbx) * kBx;
+  b /= nbx;
+  const int by = static_cast<int>(b % nby) * kBy;
+  b /= nby;
+  const int bz = static_cast<int>(b % nbz) * kBz;
+  const long long n = b / nbz;
+  __syncthreads();   // the weights are staged, and every wave is done with the previous halo
+  // the block's input with its halo, zero outside the volume: all of a thread's loads are
+  // issued before any is stored
+  constexpr int kHaloIters = (kHaloVox * 4 + kTileConvThreads - 1) / kTileConvThreads;
+  u16x8 hval[kHaloIters];
+#pragma unroll
+  for (int q = 0; q < kHaloIters; ++q) {
+    const int i = tid + q * kTileConvThreads;
+    const int c = i & 3, v = i >> 2;
+    const int hx = v % kHx, hy = (v / kHx) % kHy, hz = v / (kHx * kHy);
+    const int x = bx - 1 + hx, y = by - 1 + hy, z = bz - 1 + hz;
+    hval[q] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    if (i < kHaloVox * 4 && x >= 0 && x < Wd && y >= 0 && y < H && z >= 0 && z < D)
+      hval[q] = X[(((n * D + z) * H + y) * static_cast<long long>(Wd) + x) * 4 + c];
+  }
+#pragma unroll
+  for (int q = 0; q < kHaloIters; ++q) {
+    const int i = tid + q * kTileConvThreads;
+    if (i < kHaloVox * 4) Hs[halo_slot(i >> 2, i & 3)] = hval[q];
   }
   __syncthreads();
 
-  const unsigned short* X = static_cast<const unsigned short*>(a.x);
-  const int D = a.d, H = a.h, Wd = a.w_dim;
-  const long long nvox = static_cast<long long>(a.n) * D * H * Wd;
-  const int r = lane & 31, kg = lane >> 5;
-  const int co = lane & 31;   // this lane's output column
-  for (long long blk = (static_cast<long long>(blockIdx.x) * 4 + wave) * 32; blk < nvox;
-       blk += static_cast<long long>(gridDim.x) * 4 * 32) {
-    // this lane's A row: voxel blk + r
-    const long long v = blk + r;
-    const bool vin = v < nvox;
-    long long t = vin ? v : 0;
-    const int x = static_cast<int>(t % Wd); t /= Wd;
-    const int y = static_cast<int>(t % H); t /= H;
-    const int z = static_cast<int>(t % D);
-    const long long nbase = t / D * D;
-    f32x16 acc;
+  const int r = lane & 31, g = lane >> 5, col = lane & 31;
+  const int lz = wave >> 2, ly0 = (wave & 3) * 2;   // this wave's rows: (lz, ly0) and (lz, ly0 + 1)
+  f32x16 acc[2];
 #pragma unroll
-    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[m][i] = 0.0f;
 #pragma unroll 3
-    for (int tap = 0; tap < 27; ++tap) {
-      const int oz = tap / 9 - 1, oy = (tap / 3) % 3 - 1, ox = tap % 3 - 1;
-      const int zz = z + oz, yy = y + oy, xx = x + ox;
-      const bool in = vin && zz >= 0 && zz < D && yy >= 0 && yy < H && xx >= 0 && xx < Wd;
-      const long long nb = ((nbase + zz) * H + yy) * Wd + xx;
-      u16x8 a0 = {0, 0, 0, 0, 0, 0, 0, 0}, a1 = {0, 0, 0, 0, 0, 0, 0, 0};
-      if (in) {
-        const u16x8* src = reinterpret_cast<const u16x8*>(X + nb * kC);
-        a0 = src[kg];
-        a1 = src[2 + kg];
-      }
-      const u16x8 b0 = *reinterpret_cast<const u16x8*>(&Bs[((tap * 2 + 0) * kC + co) * 16 + kg * 8]);
-      const u16x8 b1 = *reinterpret_cast<const u16x8*>(&Bs[((tap * 2 + 1) * kC + co) * 16 + kg * 8]);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a0), __builtin_bit_cast(bf16x8, b0), acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a1), __builtin_bit_cast(bf16x8, b1), acc, 0, 0, 0);
+  for (int tap = 0; tap < 27; ++tap) {
+    const int oz = tap / 9, oy = (tap / 3) % 3, ox = tap % 3;   // halo offsets (tap offset + 1)
+    const u16x8 b0 = Bs[((tap * 2 + 0) * 2 + g) * kC + col];
+    const u16x8 b1 = Bs[((tap * 2 + 1) * 2 + g) * kC + col];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      const int hv = ((lz + oz) * kHy + (ly0 + m + oy)) * kHx + (r + ox);
+      const u16x8 a0 = Hs[halo_slot(hv, g)];
+      const u16x8 a1 = Hs[halo_slot(hv, 2 + g)];
+      acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a0), __builtin_bit_cast(bf16x8, b0), acc[m], 0, 0, 0);
+      acc[m] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a1), __builtin_bit_cast(bf16x8, b1), acc[m], 0, 0, 0);
     }
-    // epilogue: lane holds column co of rows acc_row(i, lane)
+  }
+  // epilogue: lane holds column col of rows acc_row(i, lane), row = voxel x offset in the tile
+  const float bcol = (!BACKWARD && a.bias) ? a.bias[col] : 0.0f;
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const int z = bz + lz, y = by + ly0 + m;
+    if (z >= D || y >= H) continue;
+    const long long rowbase = ((n * D + z) * H + y) * static_cast<long long>(Wd);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-      const long long vo = blk + acc_row(i, lane);
-      if (vo >= nvox) continue;
-      const long long e = vo * kC + co;
-      float s = acc[i];
+      const int x = bx + acc_row(i, lane);
+      if (x >= Wd) continue;
+      const long long e = (rowbase + x) * kC + col;
+      float sv = acc[m][i];
       if constexpr (!BACKWARD) {
-        if (a.bias) s += a.bias[co];
-        if (a.z) a.z[e] = s;
-        float y_out = a.gelu ? gelu_f(s) : s;
+        sv += bcol;
+        if (a.z) a.z[e] = sv;
+        float y_out = a.gelu ? gelu_f(sv) : sv;
         if (a.residual) y_out += bf16_to_f32(static_cast<const unsigned short*>(a.residual)[e]);
         static_cast<unsigned short*>(a.y)[e] = f32_to_bf16(y_out);
       } else {
-        if (a.residual_f32) s += a.residual_f32[e];
-        if (a.dh) a.dh[e] = s;
+        if (a.residual_f32) sv += a.residual_f32[e];
+        if (a.dh) a.dh[e] = sv;
         if (a.y) {
-          const float g = a.zprev ? s * gelu_grad_f(a.zprev[e]) : s;
-          static_cast<unsigned short*>(a.y)[e] = f32_to_bf16(g);
+          const float gg = a.zprev ? sv * gelu_grad_f(a.zprev[e]) : sv;
+          static_cast<unsigned short*>(a.y)[e] = f32_to_bf16(gg);
         }
       }
     }
+  }
   }
 }
 
@@ -317,10 +405,21 @@ int grid_for(long long work, int per_block) {
 }  // namespace
 
 hipError_t launch_conv(const ConvArgs& a, bool backward, hipStream_t s) {
-  const long long nvox = static_cast<long long>(a.n) * a.d * a.h * a.w_dim;
-  const int grid = grid_for(nvox, 4 * 32 * 4);   // about four rounds of 128 voxels per group
-  if (backward) hipLaunchKernelGGL(conv_kernel<true>, dim3(grid), dim3(kConvThreads), 0, s, a);
-  else hipLaunchKernelGGL(conv_kernel<false>, dim3(grid), dim3(kConvThreads), 0, s, a);
+  // a persistent grid of one work-group per compute unit (the LDS holds one), each staging
+  // the weights once and then taking blocks in turn
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    cus = (hipGetDevice(&dev) == hipSuccess &&
+           hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ? v : 256;
+  }
+  const long long blocks = static_cast<long long>(a.n) * ((a.d + kBz - 1) / kBz) * ((a.h + kBy - 1) / kBy) *
+                           ((a.w_dim + kBx - 1) / kBx);
+  // (a multiple of the XCD count, so that every XCD's block range has its work-groups)
+  const long long want = blocks < cus ? blocks : cus;
+  const unsigned grid = static_cast<unsigned>((want + kXcds - 1) / kXcds * kXcds);
+  if (backward) hipLaunchKernelGGL(conv_tile_kernel<true>, dim3(grid), dim3(kTileConvThreads), 0, s, a);
+  else hipLaunchKernelGGL(conv_tile_kernel<false>, dim3(grid), dim3(kTileConvThreads), 0, s, a);
   return hipGetLastError();
 }
 
