@@ -37,7 +37,7 @@ int32_t rtmi_peak_gather(int64_t footprint, int32_t iters, int32_t reps, double*
 
 /* LDS atomic adds with distinct addresses per lane (512-lane work-groups, three per
  * compute unit as in the tile pass): kind 0 = binary64 (ds_add_f64), 1 = 64-bit integer
- * (ds_add_u64). Adds per second. */
+ * (ds_add_u64), 2 = binary32 (ds_add_f32). Adds per second. */
 int32_t rtmi_peak_lds_atomic(int32_t kind, int32_t iters, int32_t reps, double* rate,
                              double* bytes_or_ops);
 

@@ -178,7 +178,7 @@ int32_t rtmi_peak_gather(int64_t footprint, int32_t iters, int32_t reps, double*
 }
 
 int32_t rtmi_peak_lds_atomic(int32_t kind, int32_t iters, int32_t reps, double* rate, double* bytes_or_ops) {
-  if (!rate || (kind != 0 && kind != 1) || iters < kLdsRounds || iters % kLdsRounds) return -1;
+  if (!rate || kind < 0 || kind > 2 || iters < kLdsRounds || iters % kLdsRounds) return -1;
   const int grid = compute_units() * 3;
   Buffers B;
   if (hipMalloc(&B.p[0], static_cast<size_t>(grid) * kLdsThreads * 8) != hipSuccess) return -4;
@@ -187,6 +187,9 @@ int32_t rtmi_peak_lds_atomic(int32_t kind, int32_t iters, int32_t reps, double* 
     if (kind == 0)
       hipLaunchKernelGGL(lds_atomic_kernel<double>, dim3(grid), dim3(kLdsThreads), 0, nullptr, iters,
                          static_cast<double*>(B.p[0]));
+    else if (kind == 2)
+      hipLaunchKernelGGL(lds_atomic_kernel<float>, dim3(grid), dim3(kLdsThreads), 0, nullptr, iters,
+                         static_cast<float*>(B.p[0]));
     else
       hipLaunchKernelGGL(lds_atomic_kernel<unsigned long long>, dim3(grid), dim3(kLdsThreads), 0, nullptr, iters,
                          static_cast<unsigned long long*>(B.p[0]));

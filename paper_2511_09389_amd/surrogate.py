@@ -68,10 +68,11 @@ class SurrogateNet:
             h = y
         return h, cache
 
-    def backward(self, cache, dz_last):
-        """Gradients (dW list, db list) of the loss whose dL/dy (channel 0) seeds dz_last."""
-        dw = [torch.zeros_like(w) for w in self.w]
-        db = [torch.zeros_like(b) for b in self.b]
+    def backward(self, cache, dz_last, dw=None, db=None):
+        """Gradients (dW list, db list) of the loss whose dL/dy (channel 0) seeds dz_last,
+        added into dw, db when given (accumulation over a batch)."""
+        dw = [torch.zeros_like(w) for w in self.w] if dw is None else dw
+        db = [torch.zeros_like(b) for b in self.b] if db is None else db
         dz, dh = dz_last, None
         for l in range(LAYERS - 1, -1, -1):
             h_in, _ = cache[l]
@@ -119,13 +120,14 @@ class SurrogateNet:
             self.wb[l].copy_(self.w[l].to(torch.bfloat16))
 
 
-def make_sample(seed, device, n=64, n_src=16, num_rays=4096, ds=0.5, c=64.0, dt=1.0):
+def make_sample(seed, device, n=64, n_src=16, num_rays=4096, ds=0.5, c=64.0, dt=1.0,
+                cheap_divisor=CHEAP_DIVISOR):
     """(j, kappa, cheap field, full field) of one seeded turbulent sample, on the device."""
     w = inputs.surrogate_sample(seed, n=n, n_src=n_src, num_rays=num_rays, ds=ds, c=c, dt=dt)
     j = torch.from_numpy(w.j_map).to(device)
     k = torch.from_numpy(w.kappa_map).to(device)
     full = rtmi.trace_multi(j, k, w.source_pos, w.num_rays, w.step_size, w.radiation_velocity, w.time_step)
-    cheap = rtmi.trace_multi(j, k, w.source_pos, np.maximum(w.num_rays // CHEAP_DIVISOR, 1), w.step_size,
+    cheap = rtmi.trace_multi(j, k, w.source_pos, np.maximum(w.num_rays // cheap_divisor, 1), w.step_size,
                              w.radiation_velocity, w.time_step)
     return w, j, k, cheap, full
 
@@ -133,8 +135,9 @@ def make_sample(seed, device, n=64, n_src=16, num_rays=4096, ds=0.5, c=64.0, dt=
 class Surrogate:
     """A trained network with its input statistics and calibrated acceptance threshold."""
 
-    def __init__(self, net, stats, threshold=0.0):
+    def __init__(self, net, stats, threshold=0.0, cheap_divisor=CHEAP_DIVISOR):
         self.net, self.stats, self.threshold = net, np.asarray(stats, np.float32), float(threshold)
+        self.cheap_divisor = int(cheap_divisor)
 
     @property
     def floor(self):
@@ -143,14 +146,15 @@ class Surrogate:
     def save(self, path):
         """Checkpoint: the network's state_dict, the input statistics and the threshold."""
         torch.save({"net": self.net.state_dict(), "stats": torch.from_numpy(self.stats.copy()),
-                    "threshold": torch.tensor(self.threshold, dtype=torch.float64)}, path)
+                    "threshold": torch.tensor(self.threshold, dtype=torch.float64),
+                    "cheap_divisor": torch.tensor(self.cheap_divisor, dtype=torch.int64)}, path)
 
     @classmethod
     def load(cls, path, device):
         sd = torch.load(path, map_location="cpu", weights_only=True)
         net = SurrogateNet(device)
         net.load_state_dict(sd["net"])
-        return cls(net, sd["stats"].numpy(), float(sd["threshold"]))
+        return cls(net, sd["stats"].numpy(), float(sd["threshold"]), int(sd.get("cheap_divisor", CHEAP_DIVISOR)))
 
     def features(self, j, k, cheap):
         """(x, scale_sums) of one sample."""
@@ -173,7 +177,7 @@ class Surrogate:
     def run(self, w, j, k):
         """Field of one problem: the surrogate when its check passes, else the full march.
         Returns (field, used_surrogate)."""
-        cheap = rtmi.trace_multi(j, k, w.source_pos, np.maximum(w.num_rays // CHEAP_DIVISOR, 1), w.step_size,
+        cheap = rtmi.trace_multi(j, k, w.source_pos, np.maximum(w.num_rays // self.cheap_divisor, 1), w.step_size,
                                  w.radiation_velocity, w.time_step)
         field, check = self.predict(j, k, cheap)
         if check <= self.threshold:
@@ -196,10 +200,26 @@ def rel_l2(a, b):
     return float((a - b).norm() / b.norm())
 
 
-def train(train_samples, device, epochs=4, lr=2e-3, seed=0, log=None):
-    """Train on [(w, j, k, cheap, full)]; returns (Surrogate, losses per epoch)."""
+def learning_rate(lr, step, total, warmup, schedule):
+    """Base rate lr after a linear warm-up of `warmup` steps, then constant, halved at every
+    third of the run ("step"), or on a cosine to zero ("cosine")."""
+    if warmup > 0 and step < warmup:
+        return lr * (step + 1) / warmup
+    if schedule == "cosine":
+        frac = (step - warmup) / max(total - warmup, 1)
+        return lr * 0.5 * (1.0 + math.cos(math.pi * min(frac, 1.0)))
+    if schedule == "step":
+        return lr * 0.5 ** (3 * step // max(total, 1))
+    return lr
+
+
+def train(train_samples, device, epochs=4, lr=2e-3, seed=0, log=None, batch=1, warmup=0, schedule="step",
+          cheap_divisor=CHEAP_DIVISOR):
+    """Train on [(w, j, k, cheap, full)] with Adam on the mean over `batch` samples of the
+    loss (their weight gradients accumulate before each step); returns (Surrogate, losses
+    per epoch)."""
     net = SurrogateNet(device, seed=seed)
-    model = Surrogate(net, input_stats(train_samples))
+    model = Surrogate(net, input_stats(train_samples), cheap_divisor=cheap_divisor)
     feats, targets = [], []
     for s in train_samples:
         x, sums = model.features(s[1], s[2], s[3])
@@ -209,16 +229,24 @@ def train(train_samples, device, epochs=4, lr=2e-3, seed=0, log=None):
     losses = []
     order = np.arange(len(train_samples))
     rng = np.random.default_rng(seed)
+    steps_per_epoch = (len(order) + batch - 1) // batch
+    total = epochs * steps_per_epoch
+    step = 0
     for ep in range(epochs):
         rng.shuffle(order)
         loss_buf.zero_()
-        for i in order:
-            y, cache = net.forward(feats[i], keep=True)
-            dz = torch.empty_like(y)
-            rtmi.mse_loss(y, targets[i], 1.0 / targets[i].numel(), dz, loss_buf)
-            dw, db = net.backward(cache, dz)
-            net.apply(dw, db, lr * (0.5 ** (ep * 3 // max(epochs, 1))))
-        losses.append(float(loss_buf.item()) / len(order))
+        for b0 in range(0, len(order), batch):
+            idx = order[b0:b0 + batch]
+            dw = [torch.zeros_like(w) for w in net.w]
+            db = [torch.zeros_like(b) for b in net.b]
+            for i in idx:
+                y, cache = net.forward(feats[i], keep=True)
+                dz = torch.empty_like(y)
+                rtmi.mse_loss(y, targets[i], 1.0 / (targets[i].numel() * len(idx)), dz, loss_buf)
+                net.backward(cache, dz, dw=dw, db=db)
+            net.apply(dw, db, learning_rate(lr, step, total, warmup, schedule))
+            step += 1
+        losses.append(float(loss_buf.item()) / steps_per_epoch)
         if log:
             log(f"epoch {ep}: mean squared log-error {losses[-1]:.3e}")
     return model, losses
@@ -261,10 +289,20 @@ def evaluate(model, eval_samples, reps=3):
             rtmi.trace_multi(j, k, w.source_pos, w.num_rays, w.step_size, w.radiation_velocity, w.time_step)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    # the network's own path (cheap march, features, six convolutions, output), no fallback
+    for _ in range(reps):
+        for w, j, k, _, _ in eval_samples:
+            cheap = rtmi.trace_multi(j, k, w.source_pos, np.maximum(w.num_rays // model.cheap_divisor, 1),
+                                     w.step_size, w.radiation_velocity, w.time_step)
+            x, sums = model.features(j, k, cheap)
+            y, _ = model.net.forward(x)
+            rtmi.surrogate_output(y, cheap, sums)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     n = reps * len(eval_samples)
     return {"max_err": max(errs), "mean_err": float(np.mean(errs)), "accepted": int(sum(used)),
             "samples": len(eval_samples), "surrogate_fields_per_s": n / (t1 - t0),
-            "march_fields_per_s": n / (t2 - t1)}
+            "march_fields_per_s": n / (t2 - t1), "network_path_fields_per_s": n / (t3 - t2)}
 
 
 def main(argv=None):
@@ -280,17 +318,23 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=3)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--target", type=float, default=0.01)
+    ap.add_argument("--batch", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--schedule", choices=("step", "cosine", "constant"), default="step")
+    ap.add_argument("--cheap-divisor", type=int, default=CHEAP_DIVISOR)
+    ap.add_argument("--save", default=None, help="checkpoint path for the trained, calibrated surrogate")
     args = ap.parse_args(argv)
     dev = torch.device("cuda:0")
     t0 = time.perf_counter()
-    train_s = [make_sample(s, dev) for s in range(args.train)]
-    val_s = [make_sample(5000 + s, dev) for s in range(args.val)]
-    eval_s = [make_sample(10000 + s, dev) for s in range(args.eval)]
+    cd = args.cheap_divisor
+    train_s = [make_sample(s, dev, cheap_divisor=cd) for s in range(args.train)]
+    val_s = [make_sample(5000 + s, dev, cheap_divisor=cd) for s in range(args.val)]
+    eval_s = [make_sample(10000 + s, dev, cheap_divisor=cd) for s in range(args.eval)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     print(f"samples ready in {t1 - t0:.1f} s", flush=True)
-    model, losses = train(train_s, dev, epochs=args.epochs, lr=args.lr,
-                          log=lambda m: print(m, flush=True))
+    model, losses = train(train_s, dev, epochs=args.epochs, lr=args.lr, batch=args.batch, warmup=args.warmup,
+                          schedule=args.schedule, cheap_divisor=cd, log=lambda m: print(m, flush=True))
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     thr, pairs = calibrate(model, val_s, target=args.target)
@@ -298,7 +342,10 @@ def main(argv=None):
     checks = np.array([p[0] for p in pairs])
     errs = np.array([p[1] for p in pairs])
     cheap = [rel_l2(s[3], s[4]) for s in eval_s]
-    out = {"train_samples": args.train, "epochs": args.epochs, "train_s": t2 - t1,
+    if args.save:
+        model.save(args.save)
+    out = {"train_samples": args.train, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+           "warmup": args.warmup, "schedule": args.schedule, "cheap_divisor": cd, "train_s": t2 - t1,
            "train_samples_per_s": args.train * args.epochs / (t2 - t1), "losses": losses,
            "threshold": thr, "val_error_median": float(np.median(errs)), "val_error_min": float(errs.min()),
            "val_check_median": float(np.median(checks)), "cheap_error_mean": float(np.mean(cheap)),
