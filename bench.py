@@ -17,7 +17,8 @@ Prints one JSON line: ray-substeps/s; the roofline position of each march kernel
 launch durations from HIP events recorded on the launch stream, against peaks measured in
 the same run by the microbenchmarks of librtmi_peaks.so, with counter-derived L2/HBM bytes
 from the committed rocprofv3 summary while it matches the kernel sources); the 128^3
-turbulent workload as a second key; and the FP64 CPU oracle timed on this host.
+turbulent workload as a second key; the learned surrogate's fields/s at <= 1 % against
+the plain march's; and the FP64 CPU oracle timed on this host.
 """
 
 import argparse
@@ -68,7 +69,7 @@ def workload_units(w, n_s):
 class Setup:
     """Device inputs, output and a tuned plan of one workload."""
 
-    def __init__(self, name, tune_reps=3):
+    def __init__(self, name, tune_reps=3, knobs=None):
         import torch
         from paper_2511_09389_amd import autotune, rtmi
         self.name = name
@@ -82,7 +83,9 @@ class Setup:
         for n in sorted(set(int(v) for v in w.num_rays)):
             rtmi.prepare(n)
         self.tuned, self.tune_ms = dict(autotune.DEFAULTS), {}
-        if tune_reps > 0:
+        if knobs:   # fixed knobs (e.g. to profile the configuration another run tuned)
+            self.tuned.update({k: int(v) for k, v in knobs.items()})
+        elif tune_reps > 0:
             import tempfile
             os.environ.setdefault("RTMI_TUNE_CACHE", os.path.join(tempfile.gettempdir(), "rtmi_bench_tune.json"))
             self.tuned, self.tune_ms = autotune.tune(
@@ -237,9 +240,9 @@ def contract_roofline(rl, counters_doc):
             "kernel": dom, "kernel_avg_ms": r["avg_ms"]}
 
 
-def measure(name, steps, warmup, peaks, tune_reps=3):
+def measure(name, steps, warmup, peaks, tune_reps=3, knobs=None):
     import torch
-    s = Setup(name, tune_reps=tune_reps)
+    s = Setup(name, tune_reps=tune_reps, knobs=knobs)
     elapsed = time_graph(s, steps, warmup)
     eager_elapsed, kern = time_kernels(s.execute, steps, warmup)
     stateless_elapsed, _ = time_kernels(s.stateless, steps, warmup)
@@ -259,6 +262,36 @@ def measure(name, steps, warmup, peaks, tune_reps=3):
     del s
     torch.cuda.empty_cache()
     return res
+
+
+def surrogate_rates(n_train=300, n_val=30, n_eval=30):
+    """The learned surrogate with the march as fallback (64^3 turbulent samples, 16 sources x
+    4096 rays, 128 substeps): a short training on the GPU by the library's kernels, the 1 %
+    calibration, then fields/s of the surrogate path (with its fallbacks), of the network's
+    own path and of the plain march, and how many fields the surrogate itself returned."""
+    import torch
+    from paper_2511_09389_amd import surrogate as sg
+    dev = torch.device("cuda:0")
+    cd = 4
+    train = [sg.make_sample(s, dev, cheap_divisor=cd) for s in range(n_train)]
+    val = [sg.make_sample(5000 + s, dev, cheap_divisor=cd) for s in range(n_val)]
+    ev = [sg.make_sample(10000 + s, dev, cheap_divisor=cd) for s in range(n_eval)]
+    model, losses = sg.train(train, dev, epochs=6, lr=2e-3, batch=4, warmup=20, schedule="cosine",
+                             cheap_divisor=cd)
+    thr, pairs = sg.calibrate(model, val, target=0.01)
+    res = sg.evaluate(model, ev)
+    errs = sorted(p[1] for p in pairs)
+    out = {"metric": "fields/s at <= 1% rel L2 (surrogate with fallback) vs the plain march",
+           "surrogate_fields_per_s": res["surrogate_fields_per_s"], "plain_fields_per_s": res["march_fields_per_s"],
+           "network_path_fields_per_s": res["network_path_fields_per_s"], "accepted": res["accepted"],
+           "samples": res["samples"], "max_returned_error": res["max_err"], "threshold": thr,
+           "validation_error_median": errs[len(errs) // 2], "validation_error_best": errs[0],
+           "training": f"{n_train} samples, 6 epochs, batch 4, cheap march N_Omega/{cd}",
+           "note": "a short training inside the benchmark; the 2000-sample runs are summarised in "
+                   "profiles/surrogate_c5_64_training.md"}
+    del train, val, ev
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_info():
@@ -316,13 +349,14 @@ def cpu_baseline(name):
                  "blob32_full_value": blob_rate}, **cpu_info())
 
 
-def counters_run(name, known_out):
-    """A short run for rocprofv3 counter passes: a few plan executions of the workload, then
-    the calibration kernels of known size (device copy, L2-resident line gather)."""
+def counters_run(name, known_out, executions=2, knobs=None):
+    """A short run for rocprofv3 counter passes and kernel traces: a few plan executions of
+    the workload (default or given knobs), then the calibration kernels of known size
+    (device copy, L2-resident line gather)."""
     import torch
     from paper_2511_09389_amd import peaks
-    s = Setup(name, tune_reps=0)
-    for _ in range(2):
+    s = Setup(name, tune_reps=0, knobs=knobs)
+    for _ in range(executions):
         s.execute()
     torch.cuda.synchronize()
     s.close()
@@ -330,7 +364,7 @@ def counters_run(name, known_out):
     _, moved = peaks.copy(copy_bytes, reps=1)
     _, gathered = peaks.gather(2 << 20, iters=64, reps=1)
     known = {"copy_read_bytes": moved / 2, "copy_write_bytes": moved / 2, "gather_bytes": gathered,
-             "ray_substeps_per_step": s.units, "executions": 2}
+             "ray_substeps_per_step": s.units, "executions": executions}
     os.makedirs(os.path.dirname(known_out) or ".", exist_ok=True)
     with open(known_out, "w") as fh:
         json.dump(known, fh)
@@ -345,16 +379,21 @@ def main():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="uneven")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-second", action="store_true", help="skip the 128^3 turbulent key")
+    ap.add_argument("--no-surrogate", action="store_true", help="skip the surrogate fields/s key")
     ap.add_argument("--counters-run", metavar="KNOWN_JSON", default=None,
                     help="only run a short profiling sequence (for rocprofv3 --pmc passes)")
+    ap.add_argument("--executions", type=int, default=2, help="plan executions of --counters-run")
+    ap.add_argument("--knobs", default=None,
+                    help='fixed plan knobs instead of the autotuner, as JSON (e.g. \'{"tile_item_chunks": 2048}\')')
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
               "(the design of the source-sharded version is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
+    knobs = json.loads(args.knobs) if args.knobs else None
     if args.counters_run:
-        counters_run(args.workload, args.counters_run)
+        counters_run(args.workload, args.counters_run, args.executions, knobs)
         return
 
     from paper_2511_09389_amd import peaks as peaks_lib
@@ -362,7 +401,7 @@ def main():
     peaks = peaks_lib.measure_all()
     print(f"[bench] {args.workload}: plan + graph, {args.warmup} warm-up and {args.steps} timed steps",
           file=sys.stderr, flush=True)
-    main_res = measure(args.workload, args.steps, args.warmup, peaks)
+    main_res = measure(args.workload, args.steps, args.warmup, peaks, knobs=knobs)
     second = None
     if args.workload == "uneven" and not args.no_second:
         print("[bench] turbulent 128^3 as the second key", file=sys.stderr, flush=True)
@@ -384,6 +423,9 @@ def main():
         result["turbulent_128"] = second
     if args.workload == "peaks":
         result["paper_context"] = dict(PAPER_CONTEXT, this_run_s=main_res["ms_per_step"] / 1e3)
+    if not args.no_surrogate:
+        print("[bench] surrogate (short training, calibration, evaluation)", file=sys.stderr, flush=True)
+        result["surrogate"] = surrogate_rates()
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle", file=sys.stderr, flush=True)
         result["cpu_baseline"] = cpu_baseline(args.workload)
