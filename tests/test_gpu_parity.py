@@ -100,6 +100,23 @@ def test_ragged_multi_source_parity(rt, dev, shape, rays, caps, path):
     assert_parity(got, want)
 
 
+@pytest.mark.parametrize("gather", [1, 2])
+def test_ragged_parity_each_gather_source(rt, dev, gather):
+    """The tiled path's record pass gathering j and kappa from the 64-byte table (1) and
+    from the maps (2), on a ragged grid with sources outside the box (samples clamped on
+    every face)."""
+    rng = np.random.default_rng(8)
+    shape, rays, caps = (23, 41, 30), [300, 129, 64], [0, 0, 17]
+    kap = inputs.lognormal_kappa(max(shape), 0.05, 1.0, rng)[:shape[0], :shape[1], :shape[2]].copy()
+    centres = np.array([[-3.0, 20.0, 15.5], [11.2, 43.0, -1.5], [22.5, 0.2, 29.9]], np.float32)
+    j = rng.random(shape).astype(np.float32)
+    note(f"ragged {shape} rays={rays} caps={caps} gather_table={gather}")
+    got = multi(rt, to_dev(j, dev), to_dev(kap, dev), centres, rays, 0.5, 30.0, 1.0, caps=caps,
+                gather_table=gather).cpu().numpy()
+    want = oracle.trace_multi(j, kap, centres, rays, 0.5, 30.0, 1.0, caps=caps)
+    assert_parity(got, want)
+
+
 @pytest.fixture(scope="module")
 def turbulent_case():
     w = inputs.turbulent()
