@@ -102,7 +102,8 @@ class Setup:
         from paper_2511_09389_amd import rtmi
         w = self.w
         rtmi.trace_bins(self.j, self.k, w.source_pos, w.num_rays, w.step_size, w.radiation_velocity,
-                        w.time_step, kappa_scale=w.kappa_scale, substep_cap=w.substep_cap, out=self.out)
+                        w.time_step, kappa_scale=w.kappa_scale, substep_cap=w.substep_cap, out=self.out,
+                        **self.tuned)
 
     def close(self):
         self.plan.close()

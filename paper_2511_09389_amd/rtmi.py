@@ -236,14 +236,14 @@ def trace_multi(j_map, kappa_map, source_pos, num_rays, step_size, radiation_vel
 def trace_bins(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
                time_step, kappa_scale=None, substep_cap=None, out=None, deterministic=False,
                directions=None, ray_weight=0.0, path=PATH_TILED, tile_item_chunks=0, record_capacity=0,
-               gather_table=0, sources_per_launch=0):
+               gather_table=0, sources_per_launch=0, tile_groups_per_cu=0):
     """Frequency bins as a batch axis. j_maps / kappa_maps are 3-D (shared by all bins) or
     4-D [B][nx][ny][nz]; a 3-D kappa with kappa_scale gives kappa_b = kappa * scale[b].
     Returns a [B][nx][ny][nz] float32 tensor."""
     return _bins_call(lib.rtmi_trace_bins, j_maps, kappa_maps, source_pos, num_rays, step_size,
                       radiation_velocity, time_step, kappa_scale, substep_cap, out, deterministic,
                       directions, ray_weight, path, tile_item_chunks, record_capacity, gather_table,
-                      sources_per_launch)
+                      sources_per_launch, tile_groups_per_cu)
 
 
 def trace_bins_static(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
@@ -264,7 +264,7 @@ def static_scratch_bytes():
 
 def _bins_call(entry, j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity,
                time_step, kappa_scale, substep_cap, out, deterministic, directions, ray_weight, path,
-               tile_item_chunks, record_capacity, gather_table=0, sources_per_launch=0):
+               tile_item_chunks, record_capacity, gather_table=0, sources_per_launch=0, tile_groups_per_cu=0):
     grid = tuple(j_maps.shape[-3:])
     if tuple(kappa_maps.shape[-3:]) != grid:
         raise ValueError("j and kappa grids differ")
@@ -290,7 +290,7 @@ def _bins_call(entry, j_maps, kappa_maps, source_pos, num_rays, step_size, radia
         _same(out, "out", (n_bins,) + grid, j_maps.device)
     opts = Options(ACCUM_DETERMINISTIC if deterministic else ACCUM_ATOMIC, None, float(ray_weight),
                    int(path), int(tile_item_chunks), int(record_capacity), int(gather_table),
-                   int(sources_per_launch))
+                   int(sources_per_launch), int(tile_groups_per_cu))
     dirs = None
     if directions is not None:
         dirs = _host_f32(directions, 3)
