@@ -195,6 +195,7 @@ def rooflines(setup, kern, peaks, counters_doc):
             adds = DEPOSITS * units_launch
             r.update(bound="lds_atomic", algorithmic_adds=adds, adds_per_s=adds / t,
                      frac_adds_vs_lds_f64_peak=adds / t / peaks["lds_add_f64_per_s"],
+                     frac_adds_vs_lds_f64_random_peak=adds / t / peaks["lds_add_f64_random_per_s"],
                      algorithmic_bytes=DEPOSIT_VALUE_BYTES * units_launch + 4 * int(w.j_map.size))
         else:
             cells = int(w.j_map.size)
@@ -229,7 +230,8 @@ def contract_roofline(rl, counters_doc):
         return {"bound": "lds_atomic", "achieved": r["adds_per_s"] / 1e9, "peak": r["adds_per_s"] / 1e9 /
                 r["frac_adds_vs_lds_f64_peak"], "unit": "G LDS f64 adds/s", "frac": r["frac_adds_vs_lds_f64_peak"],
                 "traffic": traffic, "kernel": dom, "kernel_avg_ms": r["avg_ms"],
-                "units_per_launch": r["ray_substeps_per_launch"], "per_unit": f"{DEPOSITS} deposits"}
+                "units_per_launch": r["ray_substeps_per_launch"], "per_unit": f"{DEPOSITS} deposits",
+                "frac_vs_random_address_peak": r["frac_adds_vs_lds_f64_random_peak"]}
     if dom == "record":
         return {"bound": "l2", "achieved": r["gather_Bps"] / 1e9, "peak": r["gather_Bps"] / 1e9 /
                 r["frac_gather_vs_l2_peak"], "unit": "GB/s", "frac": r["frac_gather_vs_l2_peak"],
@@ -308,10 +310,15 @@ def cpu_info():
     return {"cpu_model": model, "os_cpu_count": os.cpu_count(), "affinity": len(os.sched_getaffinity(0))}
 
 
+CPU_SECONDS_PER_CLASS = 2.5
+
+
 def cpu_baseline(name):
     """The FP64 oracle as it stands, one process, on this host. The uneven workload is
-    sampled: one source per N_Omega class, bin 0, timed in full and extrapolated linearly in
-    ray-substeps (per class) to every source and bin; the 32^3 blob runs in full."""
+    sampled: per N_Omega class, whole sources of that class (bin 0) until about
+    CPU_SECONDS_PER_CLASS seconds of oracle time, extrapolated linearly in ray-substeps (per
+    class) to every source and bin (the bins differ only in kappa's scale, which costs
+    nothing); the 32^3 blob runs in full."""
     import numpy as np
     import oracle
     w = load_workload(name)
@@ -321,18 +328,24 @@ def cpu_baseline(name):
     caps = w.substep_cap if w.substep_cap is not None else np.zeros(w.n_src, np.int32)
     rate_by_rays = {}
     sampled_work, sampled_s = 0, 0.0
+    n_sampled = 0
     for nr in sorted(set(int(v) for v in w.num_rays)):
-        s = next(i for i in range(w.n_src) if int(w.num_rays[i]) == nr)
-        t0 = time.perf_counter()
-        oracle.trace_single(w.j_map, w.kappa_map, w.source_pos[s], nr, w.step_size, w.radiation_velocity,
-                            w.time_step, cap=int(caps[s]))
-        dt = time.perf_counter() - t0
-        rate_by_rays[nr] = nr * subs[s] / dt
-        sampled_work += nr * subs[s]
-        sampled_s += dt
+        work, spent = 0, 0.0
+        for s in (i for i in range(w.n_src) if int(w.num_rays[i]) == nr):
+            t0 = time.perf_counter()
+            oracle.trace_single(w.j_map, w.kappa_map, w.source_pos[s], nr, w.step_size, w.radiation_velocity,
+                                w.time_step, cap=int(caps[s]))
+            spent += time.perf_counter() - t0
+            work += nr * subs[s]
+            n_sampled += 1
+            if spent >= CPU_SECONDS_PER_CLASS:
+                break
+        rate_by_rays[nr] = work / spent
+        sampled_work += work
+        sampled_s += spent
     total_s = sum(int(nr) * ns / rate_by_rays[int(nr)] for nr, ns in zip(w.num_rays, subs)) * w.n_bins
     units = workload_units(w, n_s)
-    exact = w.n_src == len(rate_by_rays) and w.n_bins == 1
+    exact = n_sampled == w.n_src and w.n_bins == 1
     blob = load_workload("blob")
     t0, reps = time.perf_counter(), 0
     while time.perf_counter() - t0 < 1.0:
@@ -342,8 +355,9 @@ def cpu_baseline(name):
     blob_rate = reps * int(blob.num_rays[0]) * rtmi.num_substeps(blob.step_size, blob.radiation_velocity,
                                                                   blob.time_step) / (time.perf_counter() - t0)
     return dict({"value": units / total_s, "unit": "ray-substeps/s", "cores": 1, "kind": "oracle",
-                 "sample": (f"{'full workload' if exact else 'extrapolated'}: one source per N_Omega class "
-                            f"({sorted(rate_by_rays)}), bin 0, {sampled_work} ray-substeps in {sampled_s:.1f} s, "
+                 "sample": (f"{'full workload' if exact else 'extrapolated'}: {n_sampled} whole sources over the "
+                            f"N_Omega classes {sorted(rate_by_rays)} (about {CPU_SECONDS_PER_CLASS:g} s each), bin 0, "
+                            f"{sampled_work} ray-substeps in {sampled_s:.1f} s, "
                             f"scaled per class to all {w.n_src} sources x {w.n_bins} bins "
                             f"({units} ray-substeps, {total_s:.0f} s estimated); NumPy FP64, one process "
                             f"(elementwise NumPy runs on one thread)"),

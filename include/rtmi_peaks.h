@@ -35,9 +35,11 @@ int32_t rtmi_peak_copy(int64_t bytes, int32_t reps, double* rate, double* bytes_
 int32_t rtmi_peak_gather(int64_t footprint, int32_t iters, int32_t reps, double* rate,
                          double* bytes_or_ops);
 
-/* LDS atomic adds with distinct addresses per lane (512-lane work-groups, three per
- * compute unit as in the tile pass): kind 0 = binary64 (ds_add_f64), 1 = 64-bit integer
- * (ds_add_u64), 2 = binary32 (ds_add_f32). Adds per second. */
+/* LDS atomic adds (512-lane work-groups, three per compute unit as in the tile pass), the
+ * lanes of an instruction on consecutive slots: kind 0 = binary64 (ds_add_f64), 1 = 64-bit
+ * integer (ds_add_u64), 2 = binary32 (ds_add_f32); kind 3 = binary64 with every lane on a
+ * pseudo-random slot of a 48 KB array (bank conflicts and occasional shared addresses, as
+ * when lanes deposit along unrelated rays). Adds per second. */
 int32_t rtmi_peak_lds_atomic(int32_t kind, int32_t iters, int32_t reps, double* rate,
                              double* bytes_or_ops);
 

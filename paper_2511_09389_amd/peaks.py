@@ -54,8 +54,9 @@ def gather(footprint, iters=64, reps=5):
 
 
 def lds_atomic(kind="f64", iters=1200, reps=5):
-    """LDS atomic adds, distinct addresses: (adds/s, adds per launch)."""
-    return _run(lib.rtmi_peak_lds_atomic, {"f64": 0, "u64": 1, "f32": 2}[kind], int(iters), int(reps))
+    """LDS atomic adds (kinds: f64, u64, f32 on consecutive slots; f64_random on random
+    slots): (adds/s, adds per launch)."""
+    return _run(lib.rtmi_peak_lds_atomic, {"f64": 0, "u64": 1, "f32": 2, "f64_random": 3}[kind], int(iters), int(reps))
 
 
 def global_atomic(footprint=64 << 20, scattered=False, iters=64, reps=5):
@@ -73,6 +74,7 @@ def measure_all():
     out["lds_add_f64_per_s"] = lds_atomic("f64")[0]
     out["lds_add_u64_per_s"] = lds_atomic("u64")[0]
     out["lds_add_f32_per_s"] = lds_atomic("f32")[0]
+    out["lds_add_f64_random_per_s"] = lds_atomic("f64_random")[0]
     out["global_atomic_f32_coalesced_per_s"] = global_atomic(scattered=False)[0]
     out["global_atomic_f32_scattered_per_s"] = global_atomic(scattered=True)[0]
     return out
