@@ -36,6 +36,7 @@ HBM_PEAK_DATASHEET = 8.0e12
 GATHER_BYTES = 36        # per lane-substep: 8 j corners + the nearest kappa (shared by a lane's bins)
 DEPOSIT_VALUE_BYTES = 4  # per ray-substep: the recorded deposit value, written once, read back once
 DEPOSITS = 8             # per ray-substep: trilinear corners
+ROW_JK_BYTES = 8         # per lane-substep with the gather pass: (j, kappa) written once, read back once
 COUNTER_FILES = {"uneven": "profiles/march_uneven256_counters.json",
                  "turbulent": "profiles/march_turbulent128_counters.json"}
 WORKLOADS = {
@@ -148,7 +149,8 @@ def time_kernels(run, steps, warmup):
         run()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    kinds = {"record": rtmi.KERNEL_RECORD, "tile": rtmi.KERNEL_TILE, "table": rtmi.KERNEL_TABLE}
+    kinds = {"record": rtmi.KERNEL_RECORD, "tile": rtmi.KERNEL_TILE, "table": rtmi.KERNEL_TABLE,
+             "gather_pass": rtmi.KERNEL_GATHER}
     out = {}
     for name, kind in kinds.items():
         ms, launches = rtmi.timing_read(kind)
@@ -185,12 +187,24 @@ def rooflines(setup, kern, peaks, counters_doc):
         t = avg_ms * 1e-3
         units_launch = units / per_step if name != "table" else 0
         r = {"avg_ms": avg_ms, "launches_per_step": per_step, "ray_substeps_per_launch": units_launch}
-        if name == "record":
+        if name == "record" and "gather_pass" in kern:
+            # (j, kappa) rows of the gather pass read back in whole pieces, deposit values written
+            read = ROW_JK_BYTES * units_launch / nb_lane
+            written = DEPOSIT_VALUE_BYTES * units_launch
+            r.update(bound="hbm", algorithmic_bytes=read + written,
+                     frac_vs_copy_peak=(read + written) / t / peaks["copy_Bps"])
+        elif name == "record":
             gathered = GATHER_BYTES * units_launch / nb_lane
             written = DEPOSIT_VALUE_BYTES * units_launch
             r.update(bound="l2", algorithmic_bytes=gathered + written,
                      gather_Bps=gathered / t, frac_gather_vs_l2_peak=gathered / t / peaks["gather_l2_Bps"],
                      frac_gather_vs_mall_peak=gathered / t / peaks["gather_mall_Bps"])
+        elif name == "gather_pass":
+            # the maps read once, one (j, kappa) pair written per lane-substep
+            cells = int(w.j_map.size)
+            moved = 8 * cells + ROW_JK_BYTES * units_launch / nb_lane
+            r.update(bound="hbm", algorithmic_bytes=moved, lane_substeps_per_launch=units_launch / nb_lane,
+                     frac_vs_copy_peak=moved / t / peaks["copy_Bps"])
         elif name == "tile":
             adds = DEPOSITS * units_launch
             r.update(bound="lds_atomic", algorithmic_adds=adds, adds_per_s=adds / t,
@@ -232,7 +246,7 @@ def contract_roofline(rl, counters_doc):
                 "traffic": traffic, "kernel": dom, "kernel_avg_ms": r["avg_ms"],
                 "units_per_launch": r["ray_substeps_per_launch"], "per_unit": f"{DEPOSITS} deposits",
                 "frac_vs_random_address_peak": r["frac_adds_vs_lds_f64_random_peak"]}
-    if dom == "record":
+    if dom == "record" and "gather_Bps" in r:
         return {"bound": "l2", "achieved": r["gather_Bps"] / 1e9, "peak": r["gather_Bps"] / 1e9 /
                 r["frac_gather_vs_l2_peak"], "unit": "GB/s", "frac": r["frac_gather_vs_l2_peak"],
                 "traffic": traffic, "kernel": dom, "kernel_avg_ms": r["avg_ms"],
@@ -240,7 +254,7 @@ def contract_roofline(rl, counters_doc):
     return {"bound": "hbm", "achieved": r["algorithmic_bytes"] / (r["avg_ms"] * 1e-3) / 1e9,
             "peak": HBM_PEAK_DATASHEET / 1e9, "unit": "GB/s",
             "frac": r["algorithmic_bytes"] / (r["avg_ms"] * 1e-3) / HBM_PEAK_DATASHEET, "traffic": traffic,
-            "kernel": dom, "kernel_avg_ms": r["avg_ms"]}
+            "kernel": dom, "kernel_avg_ms": r["avg_ms"], "frac_vs_measured_copy": r.get("frac_vs_copy_peak")}
 
 
 def measure(name, steps, warmup, peaks, tune_reps=3, knobs=None):

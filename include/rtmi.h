@@ -91,9 +91,13 @@ typedef struct rtmi_options {
   /* Tiled path with j and kappa shared by the bins: where the record pass gathers them.
    * 1: a table built per call holding, per voxel, the eight corners of j and of kappa in
    * one 64-byte line (one line per sample; 64 bytes of workspace per voxel). 2: the maps
-   * themselves (nine 4-byte loads per sample, no table). 0 picks the table. Changes the
-   * speed, and the field only by rounding (the two round the interpolation of a sample
-   * clamped on a box face differently, also in the deterministic mode). */
+   * themselves (nine 4-byte loads per sample, no table). 3: a gather pass before the
+   * record pass gathers j and kappa tile by tile (the tile's maps staged in LDS) into
+   * per-sample rows (8 bytes per ray-substep of workspace instead of the table), which the
+   * record pass reads in whole 64-byte pieces. 0 picks the table. Changes the speed, and
+   * the field only by rounding (the maps round the interpolation of a sample clamped on a
+   * box face differently from the table and the gather pass, also in the deterministic
+   * mode). */
   int32_t gather_table;
   /* Tiled path: > 0 caps the sources one record launch (and its tile passes) covers;
    * the sources are then marched in consecutive groups of at most this many, each group's
@@ -420,11 +424,13 @@ int32_t rtmi_debug_rays(const float* j_map, const float* kappa_map,
  * by a pair of HIP events recorded on its launch stream, tallied per kernel kind:
  * RTMI_KERNEL_RECORD (a record dispatch with its segment fix-up, if any),
  * RTMI_KERNEL_TILE (one tile-pass dispatch: one bin of one source launch),
- * RTMI_KERNEL_DIRECT, RTMI_KERNEL_TABLE (the gather-table build of a tiled call). Reading
+ * RTMI_KERNEL_DIRECT, RTMI_KERNEL_TABLE (the gather-table build of a tiled call),
+ * RTMI_KERNEL_GATHER (one gather-pass dispatch, gather_table = 3). Reading
  * waits for that kind's recorded events, returns the summed elapsed milliseconds and the
  * number of launches since the last enable or read of that kind, and resets them. Do
  * not enable timing while a stream is being captured. */
-enum { RTMI_KERNEL_RECORD = 0, RTMI_KERNEL_TILE = 1, RTMI_KERNEL_DIRECT = 2, RTMI_KERNEL_TABLE = 3 };
+enum { RTMI_KERNEL_RECORD = 0, RTMI_KERNEL_TILE = 1, RTMI_KERNEL_DIRECT = 2, RTMI_KERNEL_TABLE = 3,
+       RTMI_KERNEL_GATHER = 4 };
 int32_t rtmi_timing_enable(int32_t on);
 int32_t rtmi_timing_read(int32_t kind, double* total_ms, int64_t* launches);
 

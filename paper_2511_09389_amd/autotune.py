@@ -9,13 +9,13 @@ per workload signature in a JSON cache, so later plans of the same shape skip th
   with C chunks is split into ceil(C / size) items that separate work-groups take;
 * tile_groups_per_cu: resident work-groups of the persistent tile pass per compute unit
   (0 = as many as fit; fewer trade latency hiding for L2 and LDS pressure);
-* gather_table: where the record pass gathers j and kappa (1: the per-call 64-byte table,
-  2: the maps);
+* gather_table: where the record pass gets j and kappa (0: the library's choice by grid
+  size, 1: the per-call 64-byte table, 3: the rows of the gather pass, 2: the maps);
 * sources_per_launch: all sources in one record launch (0) or in groups of a cap.
 
 The search is coordinate descent from the defaults, one knob at a time, in that order.
 The launch-shape knobs do not change the field (in the deterministic mode, not a bit of
-it); the gather source changes it by rounding only (samples clamped on a box face).
+it); the gather source changes it by rounding only.
 """
 
 import hashlib
@@ -29,9 +29,9 @@ from . import rtmi
 
 CANDIDATES = (512, 768, 1024, 1536, 2048, 3072)
 GROUPS_PER_CU = (0, 2, 1)
-GATHER_TABLE = (1, 2)
+GATHER_TABLE = (0, 1, 3, 2)
 SOURCES_PER_LAUNCH = (0, 32)
-DEFAULTS = {"tile_item_chunks": 1024, "tile_groups_per_cu": 0, "gather_table": 1, "sources_per_launch": 0}
+DEFAULTS = {"tile_item_chunks": 1024, "tile_groups_per_cu": 0, "gather_table": 0, "sources_per_launch": 0}
 
 
 def cache_path():
@@ -113,7 +113,7 @@ def tune(j_maps, kappa_maps, source_pos, num_rays, step_size, radiation_velocity
     shared = j_maps.dim() == 3 and kappa_maps.dim() == 3
     n_src = np.asarray(source_pos).reshape(-1, 3).shape[0]
     space = {"tile_item_chunks": CANDIDATES, "tile_groups_per_cu": GROUPS_PER_CU,
-             "gather_table": GATHER_TABLE if shared else (1,),
+             "gather_table": GATHER_TABLE if shared else (0,),
              "sources_per_launch": SOURCES_PER_LAUNCH if n_src > 32 else (0,)}
     space.update(candidates or {})
     out = torch.empty((n_bins,) + grid, dtype=torch.float32, device=j_maps.device)

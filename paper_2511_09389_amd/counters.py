@@ -29,7 +29,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 KERNEL_SOURCES = ["paper_2511_09389_amd/csrc/tiled.hip", "paper_2511_09389_amd/csrc/common.h",
                   "paper_2511_09389_amd/csrc/device_common.h", "paper_2511_09389_amd/csrc/api.hip"]
 # kernel-name fragment -> short name
-KERNELS = {"record_kernel": "record", "tile_kernel": "tile", "cell_table_kernel": "table",
+KERNELS = {"record_kernel": "record", "tile_kernel": "tile", "cell_table_kernel": "table", "gather_pass_kernel": "gather_pass",
            "copy_kernel": "copy", "gather_kernel": "gather", "lds_atomic_kernel": "lds_atomic"}
 L2_REQUEST_BYTES = 64
 

@@ -398,7 +398,7 @@ int32_t static_scratch(char** out) {
 std::mutex g_tmu;
 bool g_timing = false;
 using EventPair = std::pair<hipEvent_t, hipEvent_t>;
-std::vector<EventPair> g_pending[4];  // recorded, not yet read
+std::vector<EventPair> g_pending[5];  // recorded, not yet read
 std::vector<EventPair> g_free;
 
 struct TimedLaunch {
@@ -509,8 +509,8 @@ int32_t validate(const Problem& p, Plan* plan, bool maps_given = true) {
     if (p.opts->record_capacity < 0)
       return fail(RTMI_ERR_INVALID_ARG, "record_capacity must be >= 0");
     plan->record_capacity = p.opts->record_capacity;
-    if (p.opts->gather_table < 0 || p.opts->gather_table > 2)
-      return fail(RTMI_ERR_INVALID_ARG, "gather_table must be 0, 1 or 2 (got %d)", p.opts->gather_table);
+    if (p.opts->gather_table < 0 || p.opts->gather_table > 3)
+      return fail(RTMI_ERR_INVALID_ARG, "gather_table must be 0, 1, 2 or 3 (got %d)", p.opts->gather_table);
     plan->gather_table = p.opts->gather_table;
     if (p.opts->sources_per_launch < 0)
       return fail(RTMI_ERR_INVALID_ARG, "sources_per_launch must be >= 0 (got %d)", p.opts->sources_per_launch);
@@ -658,9 +658,12 @@ int64_t row_stride(int32_t nsub) { return (int64_t(nsub) + kRowAlign - 1) / kRow
 
 // Source groups of the tiled path: runs of consecutive sources that one record launch
 // and one tile pass per bin cover. A group ends where its deposit rows would pass
-// kGroupRowBytes (so the workspace stays bounded for thousands of sources) or at
-// kMaxSrcPerTiledLaunch sources (or the caller's sources_per_launch).
+// kGroupRowBytes (so the workspace stays bounded for thousands of sources), where the
+// gather pass's (j, kappa) rows would pass kGroupJkBytes (the reach of its stores' 32-bit
+// byte offsets), or at kMaxSrcPerTiledLaunch sources (or the caller's sources_per_launch).
 constexpr int64_t kGroupRowBytes = int64_t(4) << 30;
+constexpr int64_t kGroupJkBytes = (int64_t(4) << 30) - 256;
+bool use_gather_pass(const Plan& plan);
 
 struct SourceGroup {
   int32_t s0 = 0, ns = 0;
@@ -668,18 +671,23 @@ struct SourceGroup {
 
 std::vector<SourceGroup> source_groups(const Problem& p, const Plan& plan) {
   const int64_t nb = std::min(kMaxBinsPerLaunch, p.n_bins);
+  const bool jk = p.j_stride == 0 && p.k_stride == 0 && use_gather_pass(plan);
   std::vector<SourceGroup> g;
-  int64_t bytes = 0;
+  int64_t bytes = 0, jk_bytes = 0;
   for (int32_t s = 0; s < p.n_src; ++s) {
-    const int64_t b = plan.nsub[s] > 0 ? int64_t(p.nrays[s]) * row_stride(plan.nsub[s]) * nb * 4 : 0;
+    const int64_t e = plan.nsub[s] > 0 ? int64_t(p.nrays[s]) * row_stride(plan.nsub[s]) : 0;
+    const int64_t b = e * nb * 4, bj = jk ? e * 8 : 0;
     const int32_t cap = plan.sources_per_launch > 0 ? std::min(plan.sources_per_launch, rtmi::kMaxSrcPerTiledLaunch)
                                                     : rtmi::kMaxSrcPerTiledLaunch;
-    if (g.empty() || (g.back().ns > 0 && bytes + b > kGroupRowBytes) || g.back().ns >= cap) {
+    if (g.empty() || (g.back().ns > 0 && (bytes + b > kGroupRowBytes || jk_bytes + bj > kGroupJkBytes)) ||
+        g.back().ns >= cap) {
       g.push_back({s, 0});
       bytes = 0;
+      jk_bytes = 0;
     }
     g.back().ns += 1;
     bytes += b;
+    jk_bytes += bj;
   }
   return g;
 }
@@ -690,7 +698,8 @@ std::vector<SourceGroup> source_groups(const Problem& p, const Plan& plan) {
 struct TiledLayout {
   int tiles_x = 0, tiles_y = 0, tiles_z = 0, tiles = 0;
   int n_launch = 0;
-  bool interleaved = false;
+  bool interleaved = false;   // the 64-byte gather table
+  bool jk_rows = false;       // or the gather pass's (j, kappa) rows
   size_t corner = 0, srcs = 0, sched = 0, med = 0, v = 0, p = 0, segtot = 0, recs = 0, total = 0;   // byte offsets / size
   size_t sched_bytes = 0;
   int pair_blocks = 0;        // most pair blocks of any launch
@@ -731,6 +740,16 @@ bool use_gather_table(const Plan& plan) {
   return true;
 }
 
+// The gather pass (option 3): j and kappa of every sample gathered tile by tile into rows
+// that the record pass reads in whole 64-byte pieces. By default it replaces the 64-byte
+// table once the table outgrows the 256 MB Infinity Cache (the record pass then reads
+// the table from HBM several times over: 256^3, 4.94 -> 4.24 ms per uneven step), and
+// not below (128^3: the table, 0.33 ms per step, beats the pass, 0.35 ms).
+bool use_gather_pass(const Plan& plan) {
+  if (plan.gather_table != 0) return plan.gather_table == 3;
+  return plan.cells * 64 > (int64_t(256) << 20);
+}
+
 TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_launch, bool shared_records) {
   TiledLayout L;
   L.tiles_x = (p.nx + kTile - 1) / kTile;
@@ -767,13 +786,15 @@ TiledLayout tiled_layout(const Problem& p, const Plan& plan, bool sched_per_laun
   L.n_launch = static_cast<int>(L.groups.size()) * ((p.n_bins + kMaxBinsPerLaunch - 1) / kMaxBinsPerLaunch);
   const int32_t nb_max = std::min(kMaxBinsPerLaunch, p.n_bins);
   // a shared j and a shared (scaled) kappa are gathered from one interleaved copy
-  L.interleaved = p.j_stride == 0 && p.k_stride == 0 && use_gather_table(plan);
+  L.jk_rows = p.j_stride == 0 && p.k_stride == 0 && use_gather_pass(plan);
+  L.interleaved = p.j_stride == 0 && p.k_stride == 0 && !L.jk_rows && use_gather_table(plan);
   L.sched_bytes = TileSchedule::bytes(L.tiles, L.pair_blocks);
   L.corner = 0;
   L.srcs = 2 * kCornerBytes;
   L.sched = L.srcs + align256(size_t(p.n_src) * sizeof(rtmi::SrcRec));
   L.med = L.sched + L.sched_bytes * (sched_per_launch ? L.n_launch : 1);
-  L.v = L.med + (L.interleaved ? align256(size_t(plan.cells) * 4 * sizeof(float4)) : 0);
+  L.v = L.med + (L.interleaved ? align256(size_t(plan.cells) * 4 * sizeof(float4))
+                                : L.jk_rows ? align256(size_t(v_elems_max) * sizeof(float2)) : 0);
   L.p = L.v + align256(size_t(v_elems_max) * nb_max * sizeof(float));
   L.segtot = L.p + align256(size_t(p_elems_max) * nb_max * sizeof(float));
   L.recs = L.segtot + align256(size_t(t_elems_max) * nb_max * sizeof(float2));
@@ -967,6 +988,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
   float* corner = reinterpret_cast<float*>(ws + L.corner);
   unsigned long long* corner_q = reinterpret_cast<unsigned long long*>(ws + L.corner + kCornerBytes);
   float4* med = L.interleaved ? reinterpret_cast<float4*>(ws + L.med) : nullptr;
+  float2* jk = L.jk_rows ? reinterpret_cast<float2*>(ws + L.med) : nullptr;
   float* V = reinterpret_cast<float*>(ws + L.v);
   float* Prow = reinterpret_cast<float*>(ws + L.p);
   float2* segtot = reinterpret_cast<float2*>(ws + L.segtot);
@@ -1009,6 +1031,11 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       r.P = seg_len > 0 ? Prow : nullptr;
       r.segtot = seg_len > 0 ? segtot : nullptr;
       r.med = med;
+      r.jk = jk;
+      t.gj = p.j;
+      t.gk = p.kap;
+      t.jk = jk;
+      t.jk_bytes = jk ? T.v_elems * int64_t(sizeof(float2)) : 0;
       r.j = p.j ? p.j + b0 * p.j_stride : nullptr;
       r.j_stride = p.j_stride;
       r.kap = p.kap ? p.kap + b0 * p.k_stride : nullptr;
@@ -1092,10 +1119,29 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
     if (e != hipSuccess) return hip_fail(e, "fill");
   }
   bool joined = sched_st == st || fill_ahead;
+  // this launch's chunk records, written before its tile passes (and, with the gather
+  // pass, before its record pass)
+  auto records_ready = [&](size_t li) -> hipError_t {
+    hipError_t err = hipSuccess;
+    if (!joined) {
+      if ((err = hipStreamWaitEvent(st, side.done, 0)) != hipSuccess) return err;
+      joined = true;
+    }
+    if (fill_ahead) return hipStreamWaitEvent(st, filled[li], 0);
+    if (fill_each) return rtmi::launch_tile_fill(launches[li].t, L.tiles, st);
+    return err;
+  };
   for (size_t li = 0; li < launches.size(); ++li) {
     const LaunchArgs& l = launches[li];
     if ((e = rtmi::launch_fill_zero(corner, 2 * kCornerBytes / sizeof(float), st)) != hipSuccess)
       return hip_fail(e, "fill");
+    if (L.jk_rows) {
+      if ((e = records_ready(li)) != hipSuccess) return hip_fail(e, "tile records");
+      TimedLaunch tl;
+      if ((e = timed_begin(st, RTMI_KERNEL_GATHER, &tl, !plan.no_alloc)) != hipSuccess) return hip_fail(e, "timing");
+      if ((e = rtmi::launch_gather_pass(l.t, st)) != hipSuccess) return hip_fail(e, "gather pass");
+      if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
+    }
     if (l.blocks > 0) {
       TimedLaunch tl;
       if ((e = timed_begin(st, RTMI_KERNEL_RECORD, &tl, !plan.no_alloc)) != hipSuccess) return hip_fail(e, "timing");
@@ -1105,15 +1151,7 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
         return hip_fail(e, "record fixup launch");
       if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
     }
-    if (!joined) {
-      if ((e = hipStreamWaitEvent(st, side.done, 0)) != hipSuccess) return hip_fail(e, "side stream");
-      joined = true;
-    }
-    if (fill_ahead) {
-      if ((e = hipStreamWaitEvent(st, filled[li], 0)) != hipSuccess) return hip_fail(e, "side stream");
-    } else if (fill_each && (e = rtmi::launch_tile_fill(l.t, L.tiles, st)) != hipSuccess) {
-      return hip_fail(e, "tile records");
-    }
+    if (!L.jk_rows && (e = records_ready(li)) != hipSuccess) return hip_fail(e, "tile records");
     for (int32_t b = 0; b < l.nb; ++b) {   // one tile pass (one kernel dispatch) per bin
       TimedLaunch tl;
       if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl, !plan.no_alloc)) != hipSuccess) return hip_fail(e, "timing");
@@ -1982,7 +2020,7 @@ int32_t rtmi_timing_enable(int32_t on) {
 
 int32_t rtmi_timing_read(int32_t kind, double* total_ms, int64_t* launches) {
   if (!total_ms || !launches) return fail(RTMI_ERR_INVALID_ARG, "null output pointer");
-  if (kind < 0 || kind > 3) return fail(RTMI_ERR_INVALID_ARG, "unknown kernel kind %d", kind);
+  if (kind < 0 || kind > 4) return fail(RTMI_ERR_INVALID_ARG, "unknown kernel kind %d", kind);
   std::lock_guard<std::mutex> lock(g_tmu);
   double sum = 0.0;
   for (auto& ev : g_pending[kind]) {

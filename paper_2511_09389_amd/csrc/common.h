@@ -78,6 +78,7 @@ constexpr int kMaxSrcPerTiledLaunch = 1 << 13;   // the chunk records hold 13 bi
 // Phase 1 of the two-phase march: per-ray recurrence, deposit values to the workspace.
 struct RecordArgs {
   const float4* med;          // gather table (8 corners of j, then of kappa, per voxel), or null
+  const float2* jk;           // or: (j_k, kappa_k) rows of the gather pass, shaped like bin 0's V rows
   const float* j;
   long long j_stride;
   const float* kap;
@@ -142,6 +143,12 @@ struct TileArgs {
   int* item_done;                 // work-groups finished (the last one rewinds the counters)
   int item_chunks;                // target chunk records per work item
   int groups_per_cu;              // persistent tile grid: work-groups per compute unit (0: all that fit)
+  // Gather pass: j (trilinear) and kappa (nearest voxel) of every sample from the shared
+  // maps, written to rows shaped like bin 0's V rows.
+  const float* gj;
+  const float* gk;
+  float2* jk;
+  long long jk_bytes;             // bytes of the launch's rows (< 4 GiB: the stores take 32-bit offsets)
 };
 
 // Adjoint of the march: per-ray reverse sweep with checkpointed recomputation.
@@ -189,7 +196,10 @@ hipError_t launch_debug(const DebugArgs& a, hipStream_t s);
 // Deposit values of the runs after the first (segment mode): one wave per run.
 hipError_t launch_fixup(const RecordArgs& a, int n_bins, bool deterministic, int waves, hipStream_t s);
 hipError_t launch_record(const RecordArgs& a, int n_bins, bool shared_j, bool deterministic,
-                         int n_blocks, hipStream_t s);   // uses a.med when it is not null
+                         int n_blocks, hipStream_t s);   // uses a.jk, else a.med, when not null
+// Gather pass over the launch's chunk records (a.gj, a.gk -> a.jk); shares the tile pass's
+// schedule and work-item counters (and rewinds them).
+hipError_t launch_gather_pass(const TileArgs& a, hipStream_t s);
 // Surrogate network: 3x3x3 convolutions over channels-last bf16 activations.
 constexpr int kConvChannels = 32;
 

@@ -58,8 +58,11 @@ __global__ void cell_table_kernel(const float* __restrict__ j, const float* __re
   }
 }
 
-// MED: j and kappa come from the gather table a.med (one 64-byte line per sample).
-template <int NB, bool SHARED_J, bool DET, bool MED>
+// MED == 1: j and kappa come from the gather table a.med (one 64-byte line per sample).
+// MED == 2: from the rows of the gather pass, a.jk (8 bytes per sample, a ray's chunk in
+// one 64-byte piece); a sample collapsed onto a box-corner voxel, which no tile lists,
+// reads that voxel of the maps.
+template <int NB, bool SHARED_J, bool DET, int MED>
 __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
   constexpr int C = SHARED_J ? 8 : 4;
   __shared__ float ctail[NB][8];
@@ -133,6 +136,16 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
       float kv[C][NB];
       float fx[C], fy[C], fz[C];
       int cid[C];
+      float2 rowjk[C];
+      if constexpr (MED == 2) {   // (k0 is a multiple of 8 and rows are padded to whole chunks)
+        const float4* q = reinterpret_cast<const float4*>(a.jk + row_slot(vb, vn, ray, k0));
+#pragma unroll
+        for (int h = 0; h < C / 2; ++h) {
+          const float4 f = q[h];
+          rowjk[2 * h] = make_float2(f.x, f.y);
+          rowjk[2 * h + 1] = make_float2(f.z, f.w);
+        }
+      }
       // issue every gather of the chunk before using any of them
 #pragma unroll
       for (int t = 0; t < C; ++t) {
@@ -147,7 +160,15 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
         const int ox[2] = {X.lo * nyz, X.hi * nyz};
         const int oy[2] = {Y.lo * nz, Y.hi * nz};
         const int oz[2] = {Z.lo, Z.hi};
-        if constexpr (MED) {
+        if constexpr (MED == 2) {
+          float2 q = rowjk[t];
+          if (axis_clamped(x, nx) && axis_clamped(y, ny) && axis_clamped(z, nz)) {
+            const int v = X.lo * nyz + Y.lo * nz + Z.lo;
+            q = make_float2(a.j[v], a.kap[v]);
+          }
+          jv[t][0][0] = q.x;
+          kv[t][0] = q.y;
+        } else if constexpr (MED == 1) {
           const float4* line = a.med + 4ll * (static_cast<long long>(X.lo) * nyz + Y.lo * nz + Z.lo);
           const float4 j0 = line[0], j1 = line[1], k0v = line[2], k1v = line[3];
           jv[t][0][0] = j0.x;
@@ -180,9 +201,9 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
           }
         }
         // (the gather table's upper corner of a collapsed axis may be another voxel)
-        fx[t] = (MED && X.lo == X.hi) ? 0.0f : X.w1;
-        fy[t] = (MED && Y.lo == Y.hi) ? 0.0f : Y.w1;
-        fz[t] = (MED && Z.lo == Z.hi) ? 0.0f : Z.w1;
+        fx[t] = (MED != 0 && X.lo == X.hi) ? 0.0f : X.w1;
+        fy[t] = (MED != 0 && Y.lo == Y.hi) ? 0.0f : Y.w1;
+        fz[t] = (MED != 0 && Z.lo == Z.hi) ? 0.0f : Z.w1;
         const bool out3 = axis_clamped(x, nx) && axis_clamped(y, ny) && axis_clamped(z, nz);
         cid[t] = out3 ? ((x >= 0.0f ? 4 : 0) | (y >= 0.0f ? 2 : 0) | (z >= 0.0f ? 1 : 0)) : -1;
       }
@@ -213,11 +234,15 @@ __global__ void __launch_bounds__(kBlock) record_kernel(const RecordArgs a) {
 #pragma unroll
         for (int b = 0; b < NB; ++b) {
           const int bj = SHARED_J ? 0 : b;
-          float acc = 0.0f;
+          if constexpr (MED == 2) {
+            jk[b] = jv[t][0][0];
+          } else {
+            float acc = 0.0f;
 #pragma unroll
-          for (int c = 0; c < 8; ++c)
-            acc += (wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1] * jv[t][bj][c];
-          jk[b] = acc;
+            for (int c = 0; c < 8; ++c)
+              acc += (wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1] * jv[t][bj][c];
+            jk[b] = acc;
+          }
         }
         const bool live = (k0 + t) < nsub;
         const bool collapsed = tails_here && live && cid[t] >= 0;
@@ -1077,6 +1102,182 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
   }
 }
 
+// Gather pass: the samples of a launch gathered tile by tile instead of ray by ray. A work
+// item stages its tile's j and kappa with a one-voxel upper halo (17^3 voxels, indices
+// clamped to the box as the corners of the 64-byte gather table are) in LDS, then takes
+// its share of the tile's chunk records: every sample whose lower stencil corner lies in
+// the tile gets j (trilinear, as three rounds of linear interpolation; a collapsed axis
+// weighs its lower corner 1 and its upper corner 0, as the gather table does) and kappa at
+// its nearest voxel (always one of the staged corners), written to the sample's slot of
+// rows shaped like bin 0's deposit
+// rows. A sample's lower corner lies in one tile, whose records list it (they list every
+// sample that can reach the tile), so each slot is written once; samples collapsed onto a
+// box-corner voxel are left to the record pass. The record pass then reads one 64-byte
+// piece per ray and 8 substeps instead of one random 64-byte table line per sample.
+constexpr int kGEdge = kTile + 1;
+constexpr int kGatherMerge = 4;   // work items of one tile per staging
+constexpr int kGPlane = kGEdge * kGEdge;
+constexpr int kGVox = kGEdge * kGPlane;
+
+__global__ void __launch_bounds__(kTileThreads) gather_pass_kernel(const TileArgs a) {
+  constexpr int kThreads = kTileThreads;
+  __shared__ float sj[kGVox], sk[kGVox];
+  __shared__ int2 claimed;
+  const int tid = static_cast<int>(threadIdx.x);
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const float ds = a.ds;
+  const int n_items = *a.item_total;
+  const int merge = max(1, min(kGatherMerge, n_items / (4 * static_cast<int>(gridDim.x))));
+  // The rows are written through a buffer resource: its stores take a 32-bit byte offset
+  // (the launch's rows stay below 4 GiB), and whole 16-byte pairs go out as one store
+  // (the compiler would otherwise split a pair into the two 8-byte stores of the partial
+  // case). Stores past the rows' end would be dropped by the hardware.
+  const __amdgpu_buffer_rsrc_t jk_rsrc =
+      __builtin_amdgcn_make_buffer_rsrc(a.jk, 0, static_cast<int>(a.jk_bytes), 0x00020000);
+  typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+  typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+  for (;;) {
+    if (tid == 0) {
+      const int item = atomicAdd(a.item_next, 1);
+      claimed = item < n_items ? a.item_map[item] : make_int2(-1, 0);
+    }
+    __syncthreads();
+    const int2 c = claimed;
+    __syncthreads();   // (read by every lane before lane 0 claims again)
+    const int t = c.x;
+    if (t < 0) {
+      // the last work-group out rewinds the claim counters for the tile passes
+      if (tid == 0 && atomicAdd(a.item_done, 1) == static_cast<int>(gridDim.x) - 1) {
+        atomicExch(a.item_next, 0);
+        atomicExch(a.item_done, 0);
+      }
+      break;
+    }
+    // A tile's items are consecutive in the item map; with several items per work-group
+    // this pass takes them `merge` at a time (one staging of the tile per `merge` shares of
+    // its records) and lets the claims of the other parts go by.
+    const int part = c.y & 0xffff, parts = c.y >> 16;
+    if (part % merge != 0) continue;
+    const int part_end = min(part + merge, parts);
+    const TileGeom g = tile_geom(a, t);
+    const int x0 = g.x0, y0 = g.y0, z0 = g.z0, ex = g.ex, ey = g.ey, ez = g.ez;
+    {   // (each lane keeps one z of rows kRowsPerPass apart)
+      constexpr int kRowsPerPass = kThreads / kGEdge;
+      const int lz = tid % kGEdge;
+      const int gz = min(z0 + lz, nz - 1);
+      for (int r = tid / kGEdge; r < kGPlane && tid < kRowsPerPass * kGEdge; r += kRowsPerPass) {
+        const int lx = r / kGEdge, ly = r - lx * kGEdge;
+        const long long v = (static_cast<long long>(min(x0 + lx, nx - 1)) * ny + min(y0 + ly, ny - 1)) * nz + gz;
+        sj[r * kGEdge + lz] = a.gj[v];
+        sk[r * kGEdge + lz] = a.gk[v];
+      }
+    }
+    __syncthreads();
+
+    const long long rbegin = a.tile_begin[t], rcount = a.tile_count[t];
+    long long rend = rbegin + rcount * part_end / parts;
+    rend = min(rend, min(a.tile_fill[t], a.rec_capacity));
+    for (long long i = rbegin + rcount * part / parts + tid; i < rend; i += kThreads) {
+      const uint2 rec = a.recs[i];
+      const int s = static_cast<int>((rec.x >> kRecRayBits) | ((rec.y >> kRecChunkEnd) << 8));
+      const int ray = static_cast<int>(rec.x & ((1u << kRecRayBits) - 1u));
+      if (s >= a.n_src) continue;   // (not produced by the fill pass)
+      const SrcRec* sr = a.src + s;
+      const int nrays = sr->nrays;
+      if (ray >= nrays) continue;
+      const int kblk = static_cast<int>((rec.y >> 6) & ((1u << (kRecChunkEnd - 6)) - 1u)) * kChunk;
+      const int kbeg = kblk + static_cast<int>((rec.y >> 3) & 7u), kend = kblk + static_cast<int>(rec.y & 7u);
+      const float4 dd = sr->dirs[ray];
+      const float sx = sr->sx, sy = sr->sy, sz = sr->sz;
+      // (byte offset below 4 GiB, carried as the 32-bit pattern the store takes)
+      const unsigned row = static_cast<unsigned>(row_slot(sr->vbase, nrays, ray, kblk) * static_cast<long long>(sizeof(float2)));
+      // (INNER: a tile that touches no box face, where a sample with its lower corner
+      // inside is clamped on no axis, as in the tile kernel)
+      auto samples = [&](auto inner_tag) {
+        constexpr bool INNER = decltype(inner_tag)::value;
+        // sample u of the chunk: false if this tile does not own it, else its (j, kappa)
+        auto one = [&](int u, float2& res) -> bool {
+          const int k = kblk + u;
+          if (INNER && ((k < kbeg) | (k > kend))) return false;
+          const float dist = sample_distance(k, ds);
+          const float x = sample_axis(sx, dist, dd.x);
+          const float y = sample_axis(sy, dist, dd.y);
+          const float z = sample_axis(sz, dist, dd.z);
+          float wx[2], wy[2], wz[2];   // (only the upper weights are used)
+          int lx, ly, lz, nxl, nyl, nzl;
+          if constexpr (INNER) {
+            const float fx = floorf(x), fy = floorf(y), fz = floorf(z);
+            lx = static_cast<int>(fminf(fmaxf(fx, -1.0f), static_cast<float>(nx))) - x0;
+            ly = static_cast<int>(fminf(fmaxf(fy, -1.0f), static_cast<float>(ny))) - y0;
+            lz = static_cast<int>(fminf(fmaxf(fz, -1.0f), static_cast<float>(nz))) - z0;
+            wx[1] = x - fx;
+            wy[1] = y - fy;
+            wz[1] = z - fz;
+            // the nearest voxel: the lower corner, or the upper one past the midpoint (rint's
+            // halfway cases round to even; no clamp reaches a sample this tile owns)
+            nxl = lx + static_cast<int>(rintf(x) - fx);
+            nyl = ly + static_cast<int>(rintf(y) - fy);
+            nzl = lz + static_cast<int>(rintf(z) - fz);
+          } else {
+            const int clamped = static_cast<int>(axis_clamped(x, nx)) + static_cast<int>(axis_clamped(y, ny)) +
+                                static_cast<int>(axis_clamped(z, nz));
+            if ((k < kbeg) | (k > kend) | (clamped == 3)) return false;
+            const Axis X = axis_stencil(x, nx);
+            const Axis Y = axis_stencil(y, ny);
+            const Axis Z = axis_stencil(z, nz);
+            lx = X.lo - x0;
+            ly = Y.lo - y0;
+            lz = Z.lo - z0;
+            wx[1] = X.lo == X.hi ? 0.0f : X.w1;
+            wy[1] = Y.lo == Y.hi ? 0.0f : Y.w1;
+            wz[1] = Z.lo == Z.hi ? 0.0f : Z.w1;
+            nxl = X.nearest - x0;
+            nyl = Y.nearest - y0;
+            nzl = Z.nearest - z0;
+          }
+          if ((static_cast<unsigned>(lx) >= static_cast<unsigned>(ex)) |
+              (static_cast<unsigned>(ly) >= static_cast<unsigned>(ey)) |
+              (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
+            return false;
+          // trilinear j as three rounds of linear interpolation, z then y then x (a + w (b - a);
+          // a collapsed axis has w = 0 and takes its lower corner)
+          const int base = lx * kGPlane + ly * kGEdge + lz;
+          float e[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int o = base + (q >> 1) * kGPlane + (q & 1) * kGEdge;
+            const float a0 = sj[o], a1 = sj[o + 1];
+            e[q] = a0 + wz[1] * (a1 - a0);
+          }
+          const float f0 = e[0] + wy[1] * (e[1] - e[0]), f1 = e[2] + wy[1] * (e[3] - e[2]);
+          res = make_float2(f0 + wx[1] * (f1 - f0), sk[nxl * kGPlane + nyl * kGEdge + nzl]);
+          return true;
+        };
+        // two samples per 16-byte store where this tile owns both (a whole chunk: four
+        // stores filling its 64 bytes), else one 8-byte store per owned sample
+#pragma unroll
+        for (int h = 0; h < kChunk / 2; ++h) {
+          float2 r0, r1;
+          const bool m0 = one(2 * h, r0), m1 = one(2 * h + 1, r1);
+          if (m0 & m1) {
+            const u32x4 q = {__float_as_uint(r0.x), __float_as_uint(r0.y), __float_as_uint(r1.x), __float_as_uint(r1.y)};
+            __builtin_amdgcn_raw_buffer_store_b128(q, jk_rsrc, static_cast<int>(row + 16u * h), 0, 0);
+          } else {
+            if (m0) __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(r0.x), __float_as_uint(r0.y)}, jk_rsrc,
+                                                          static_cast<int>(row + 16u * h), 0, 0);
+            if (m1) __builtin_amdgcn_raw_buffer_store_b64(u32x2{__float_as_uint(r1.x), __float_as_uint(r1.y)}, jk_rsrc,
+                                                          static_cast<int>(row + 16u * h + 8u), 0, 0);
+          }
+        }
+      };
+      if (g.interior) samples(std::true_type{});
+      else samples(std::false_type{});
+    }
+    __syncthreads();   // the staged tile is replaced by the next item's
+  }
+}
+
 template <int NB>
 hipError_t launch_record_nb(const RecordArgs& a, bool shared_j, bool det, int, hipStream_t s) {
   // kXcds work-groups per round, one per XCD group, as many rounds as the largest group has blocks
@@ -1084,15 +1285,18 @@ hipError_t launch_record_nb(const RecordArgs& a, bool shared_j, bool det, int, h
   for (int x = 0; x < kXcds; ++x) rounds = max(rounds, a.xcd_blocks[x]);
   if (rounds == 0) return hipSuccess;
   const dim3 grid(rounds * kXcds), block(kBlock);
-  if (a.med) {
-    if (det) hipLaunchKernelGGL((record_kernel<NB, true, true, true>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((record_kernel<NB, true, false, true>), grid, block, 0, s, a);
+  if (a.jk) {
+    if (det) hipLaunchKernelGGL((record_kernel<NB, true, true, 2>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((record_kernel<NB, true, false, 2>), grid, block, 0, s, a);
+  } else if (a.med) {
+    if (det) hipLaunchKernelGGL((record_kernel<NB, true, true, 1>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((record_kernel<NB, true, false, 1>), grid, block, 0, s, a);
   } else if (shared_j) {
-    if (det) hipLaunchKernelGGL((record_kernel<NB, true, true, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((record_kernel<NB, true, false, false>), grid, block, 0, s, a);
+    if (det) hipLaunchKernelGGL((record_kernel<NB, true, true, 0>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((record_kernel<NB, true, false, 0>), grid, block, 0, s, a);
   } else {
-    if (det) hipLaunchKernelGGL((record_kernel<NB, false, true, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((record_kernel<NB, false, false, false>), grid, block, 0, s, a);
+    if (det) hipLaunchKernelGGL((record_kernel<NB, false, true, 0>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((record_kernel<NB, false, false, 0>), grid, block, 0, s, a);
   }
   return hipGetLastError();
 }
@@ -1197,6 +1401,13 @@ hipError_t launch_cell_table(const float* j, const float* kap, float4* table, in
   blocks = blocks < 1 ? 1 : (blocks > 16384 ? 16384 : blocks);
   hipLaunchKernelGGL(cell_table_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, j, kap, table,
                      nx, ny, nz);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_pass(const TileArgs& a, hipStream_t s) {
+  static int cache[kCacheDevices] = {0};
+  const int groups = resident_groups(gather_pass_kernel, kTileThreads, cache);
+  hipLaunchKernelGGL(gather_pass_kernel, dim3(groups), dim3(kTileThreads), 0, s, a);
   return hipGetLastError();
 }
 

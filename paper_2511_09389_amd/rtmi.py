@@ -30,6 +30,7 @@ KERNEL_RECORD = 0
 KERNEL_TILE = 1
 KERNEL_DIRECT = 2
 KERNEL_TABLE = 3
+KERNEL_GATHER = 4
 
 
 class RtmiError(RuntimeError):

@@ -100,11 +100,11 @@ def test_ragged_multi_source_parity(rt, dev, shape, rays, caps, path):
     assert_parity(got, want)
 
 
-@pytest.mark.parametrize("gather", [1, 2])
+@pytest.mark.parametrize("gather", [1, 2, 3])
 def test_ragged_parity_each_gather_source(rt, dev, gather):
-    """The tiled path's record pass gathering j and kappa from the 64-byte table (1) and
-    from the maps (2), on a ragged grid with sources outside the box (samples clamped on
-    every face)."""
+    """The tiled path's record pass gathering j and kappa from the 64-byte table (1), from
+    the maps (2) and from the rows of the gather pass (3), on a ragged grid with sources
+    outside the box (samples clamped on every face and collapsed onto box corners)."""
     rng = np.random.default_rng(8)
     shape, rays, caps = (23, 41, 30), [300, 129, 64], [0, 0, 17]
     kap = inputs.lognormal_kappa(max(shape), 0.05, 1.0, rng)[:shape[0], :shape[1], :shape[2]].copy()

@@ -8,8 +8,9 @@ per-voxel relative error <= 1e-4 wherever the oracle exceeds 1e-6 of its maximum
   8192 rays with the largest cap, 502); the whole field of every bin is compared, from the
   stateless call on both paths (the tiled one as one record launch over all 36 sources,
   and capped at 32 sources per launch, so that a second record launch, the alternating
-  chunk-record buffers and the side-stream refills run on the full 256^3 grid) and from an
-  autotuned plan replayed as a HIP graph;
+  chunk-record buffers and the side-stream refills run on the full 256^3 grid; each with
+  the gather table and with the gather pass) and from an autotuned plan replayed as a HIP
+  graph;
 * the whole batch, all 64 sources, run exactly as the benchmark runs it (an autotuned
   plan captured in a HIP graph and replayed), checked voxel by voxel at sampled interior
   voxels with oracle.trace_voxels, which marches only the rays that can reach them.
@@ -80,7 +81,8 @@ def subset(uneven):
     return picks, want
 
 
-@pytest.mark.parametrize("path", ["tiled", "tiled_two_launches", "direct"])
+@pytest.mark.parametrize("path", ["tiled", "tiled_two_launches", "tiled_gather_pass",
+                                  "tiled_gather_pass_two_launches", "direct"])
 def test_subset_full_field(rt, uneven, subset, path):
     w, j, k = uneven
     picks, want = subset
@@ -89,7 +91,8 @@ def test_subset_full_field(rt, uneven, subset, path):
     got = rt.trace_bins(j, k, w.source_pos[picks], w.num_rays[picks], w.step_size, w.radiation_velocity,
                         w.time_step, kappa_scale=w.kappa_scale, substep_cap=w.substep_cap[picks],
                         path=rt.PATH_DIRECT if path == "direct" else rt.PATH_TILED,
-                        sources_per_launch=32 if path == "tiled_two_launches" else 0).cpu().numpy()
+                        sources_per_launch=32 if path.endswith("two_launches") else 0,
+                        gather_table=3 if "gather_pass" in path else 1).cpu().numpy()
     for b in range(w.n_bins):
         err, mx = assert_parity(got[b], want[b])
         note(f"  bin {b}: rel L2 {err:.2e}, max per-voxel {mx:.2e}")

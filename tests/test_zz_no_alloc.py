@@ -87,14 +87,15 @@ def test_static_equals_trace_bins_twice(rt, dev, deterministic, path):
 
 def test_static_errors_before_enqueue(rt, dev):
     assert rt.static_scratch_bytes() == 384 << 20
-    # a grid whose gather table alone (64 bytes per voxel) exceeds the static array
+    # a grid whose gather table alone (64 bytes per voxel) exceeds the static array (the
+    # table is asked for: at this size the default is the gather pass, which fits)
     n = 256
     j = torch.zeros((n, n, n), dtype=torch.float32, device=dev)
     k = torch.zeros_like(j)
     out = torch.full((1, n, n, n), 7.0, dtype=torch.float32, device=dev)
     rt.prepare(256)
     with pytest.raises(rt.RtmiError) as e:
-        rt.trace_bins_static(j, k, [[128.0, 128.0, 128.0]], [256], 0.5, 8.0, 1.0, out=out)
+        rt.trace_bins_static(j, k, [[128.0, 128.0, 128.0]], [256], 0.5, 8.0, 1.0, out=out, gather_table=1)
     assert e.value.code == rt.ERR_RANGE and "static scratch" in str(e.value)
     # an N_Omega without a prepared direction table
     js = torch.zeros((8, 8, 8), dtype=torch.float32, device=dev)
