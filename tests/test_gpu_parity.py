@@ -225,6 +225,22 @@ def test_deterministic_mode_is_bitwise_repeatable(rt, dev, path):
     assert_parity(a[0].cpu().numpy(), want)
 
 
+def test_deterministic_gather_pass_is_bitwise_repeatable(rt, dev):
+    """The gather pass in the deterministic mode: repeatable bit for bit, independent of the
+    order of the sources and of how they are split into launches, and within the field
+    tolerance of the oracle."""
+    w = inputs.small_turbulent(n=40, n_src=6, num_rays=700, c=30.0)
+    jd, kd = to_dev(w.j_map, dev), to_dev(w.kappa_map, dev)
+    note("deterministic accumulation with the gather pass, 6 sources x 700 rays on 40^3")
+    run = lambda src, **kw: rt.trace_bins(jd, kd, src, 700, 0.5, 30.0, 1.0, deterministic=True, gather_table=3, **kw)
+    a, b = run(w.source_pos), run(w.source_pos)
+    assert torch.equal(a, b)
+    assert torch.equal(a, run(w.source_pos[::-1].copy()))
+    assert torch.equal(a, run(w.source_pos, sources_per_launch=4))
+    want = oracle.trace_multi(w.j_map, w.kappa_map, w.source_pos, 700, 0.5, 30.0, 1.0)
+    assert_parity(a[0].cpu().numpy(), want)
+
+
 @pytest.mark.parametrize("path", sorted(PATHS))
 def test_axis_ray_closed_form_on_gpu(rt, dev, path):
     """One ray along +x with weight 4 pi: J[s+m] = 4 pi 1.5 j0 ds e^{-kappa m}(1 + cosh(kappa ds))."""

@@ -59,9 +59,12 @@ CASES = [
 
 
 @pytest.mark.parametrize("deterministic", [False, True])
-@pytest.mark.parametrize("path", ["tiled", "direct"])
+@pytest.mark.parametrize("path", ["tiled", "tiled_gather_pass", "direct"])
 def test_static_equals_trace_bins_twice(rt, dev, deterministic, path):
-    p = rt.PATH_TILED if path == "tiled" else rt.PATH_DIRECT
+    """(tiled_gather_pass: the gather pass's rows live in the static array too, and the
+    second call's rows must come from its own gather pass, not the first call's.)"""
+    p = rt.PATH_DIRECT if path == "direct" else rt.PATH_TILED
+    gather = 3 if path == "tiled_gather_pass" else 0
     for i, (n, n_src, choice, caps_range, scale) in enumerate(CASES):
         note(f"call {i}: {n}^3, {n_src} sources, bins {len(scale)}, det {deterministic}, path {path}")
         w, rays, caps, sc, j, k = case(dev, n, n_src, choice, caps_range, scale, seed=50 + i)
@@ -70,9 +73,10 @@ def test_static_equals_trace_bins_twice(rt, dev, deterministic, path):
         out = torch.full((len(sc),) + w.shape, float("nan"), dtype=torch.float32, device=dev)
         got = rt.trace_bins_static(j, k, w.source_pos, rays, w.step_size, w.radiation_velocity,
                                    w.time_step, kappa_scale=sc, substep_cap=caps, out=out,
-                                   deterministic=deterministic, path=p)
+                                   deterministic=deterministic, path=p, gather_table=gather)
         want = rt.trace_bins(j, k, w.source_pos, rays, w.step_size, w.radiation_velocity, w.time_step,
-                             kappa_scale=sc, substep_cap=caps, deterministic=deterministic, path=p)
+                             kappa_scale=sc, substep_cap=caps, deterministic=deterministic, path=p,
+                             gather_table=gather)
         torch.cuda.synchronize()
         assert got.data_ptr() == out.data_ptr()
         assert torch.isfinite(got).all()
