@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ray-substeps/s per GPU + L2/atomic roofline %; surrogate fields/s at ≤1% rel L2"
 HBM_PEAK_DATASHEET = 8.0e12
+CUS, CLOCK_HZ = 256, 2.4e9   # MI355X compute units and peak engine clock
 GATHER_BYTES = 36        # per lane-substep: 8 j corners + the nearest kappa (shared by a lane's bins)
 DEPOSIT_VALUE_BYTES = 4  # per ray-substep: the recorded deposit value, written once, read back once
 DEPOSITS = 8             # per ray-substep: trilinear corners
@@ -228,9 +229,14 @@ def rooflines(setup, kern, peaks, counters_doc):
                 l2 = c["l2_read_request_bytes"] + c.get("l2_write_request_bytes", 0.0)
                 r["counters"].update(l2_request_bytes_per_launch=l2, l2_Bps=l2 / t,
                                      frac_l2_vs_gather_l2_peak=l2 / t / peaks["gather_l2_Bps"])
-            lds = c.get("counters", {}).get("SQ_INSTS_LDS_ATOMIC")
-            if lds:
-                r["counters"]["lds_atomic_wave_instructions"] = lds
+            sq = c.get("counters", {})
+            if sq.get("SQ_INSTS_LDS_ATOMIC"):
+                r["counters"]["lds_atomic_wave_instructions"] = sq["SQ_INSTS_LDS_ATOMIC"]
+            if sq.get("SQ_INSTS_VALU"):
+                # a SIMD issues one wave64 VALU instruction per 4 cycles (256 CUs x 4 SIMDs, 2.4 GHz)
+                r["counters"]["valu_issue_frac"] = sq["SQ_INSTS_VALU"] / (CUS * 4 * CLOCK_HZ * t / 4)
+            if sq.get("SQ_WAVE_CYCLES") and "SQ_WAIT_ANY" in sq:
+                r["counters"]["wave_wait_frac"] = sq["SQ_WAIT_ANY"] / sq["SQ_WAVE_CYCLES"]
         out[name] = r
     return out
 
