@@ -1178,8 +1178,13 @@ __global__ void __launch_bounds__(kTileThreads) gather_pass_kernel(const TileArg
     const long long rbegin = a.tile_begin[t], rcount = a.tile_count[t];
     long long rend = rbegin + rcount * part_end / parts;
     rend = min(rend, min(a.tile_fill[t], a.rec_capacity));
-    for (long long i = rbegin + rcount * part / parts + tid; i < rend; i += kThreads) {
-      const uint2 rec = a.recs[i];
+    // (the lane's next record is fetched while this one is processed: the pass waits on
+    // the chain record -> source -> direction more than on anything else)
+    const long long rfirst = rbegin + rcount * part / parts + tid;
+    uint2 rec_next = rfirst < rend ? a.recs[rfirst] : make_uint2(0u, 0u);
+    for (long long i = rfirst; i < rend; i += kThreads) {
+      const uint2 rec = rec_next;
+      if (i + kThreads < rend) rec_next = a.recs[i + kThreads];
       const int s = static_cast<int>((rec.x >> kRecRayBits) | ((rec.y >> kRecChunkEnd) << 8));
       const int ray = static_cast<int>(rec.x & ((1u << kRecRayBits) - 1u));
       if (s >= a.n_src) continue;   // (not produced by the fill pass)

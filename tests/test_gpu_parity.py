@@ -261,36 +261,40 @@ def test_axis_ray_closed_form_on_gpu(rt, dev, path):
     assert np.count_nonzero(got) == n - s[0]
 
 
-@pytest.mark.parametrize("path", sorted(PATHS))
+@pytest.mark.parametrize("path", sorted(PATHS) + ["tiled_gather_pass"])
 def test_edge_cases(rt, dev, path):
     w = inputs.small_turbulent(n=10, n_src=2, num_rays=33, c=6.0)
     jd, kd = to_dev(w.j_map, dev), to_dev(w.kappa_map, dev)
+    kw = dict(path=PATHS.get(path, 0), gather_table=3 if path == "tiled_gather_pass" else 0)
     # zero substeps: the output is overwritten with zeros
     out = torch.full((1,) + w.shape, 7.0, device=dev)
-    rt.trace_bins(jd, kd, w.source_pos[:1], 33, 0.5, 6.0, 0.0, out=out, path=PATHS[path])
+    rt.trace_bins(jd, kd, w.source_pos[:1], 33, 0.5, 6.0, 0.0, out=out, **kw)
     assert not out.any()
     # a 1x1x1 grid: every deposit lands on the one voxel
     one = torch.ones((1, 1, 1), device=dev)
-    f = multi(rt, one, one * 0.1, (0.0, 0.0, 0.0), 5, 0.5, 2.0, 1.0, path=PATHS[path]).item()
+    f = multi(rt, one, one * 0.1, (0.0, 0.0, 0.0), 5, 0.5, 2.0, 1.0, **kw).item()
     want = oracle.trace_single(np.ones((1, 1, 1)), np.full((1, 1, 1), 0.1, np.float32), (0, 0, 0), 5,
                                0.5, 2.0, 1.0).item()
     assert abs(f - want) <= 1e-6 * want
     # a source outside the box, and a single ray
     for src, nr in [((-5.5, 3.0, 12.25), 64), ((4.0, 4.0, 4.0), 1), ((-3.0, -4.0, -2.5), 300)]:
-        got = multi(rt, jd, kd, src, nr, 0.5, 6.0, 1.0, path=PATHS[path]).cpu().numpy()
+        got = multi(rt, jd, kd, src, nr, 0.5, 6.0, 1.0, **kw).cpu().numpy()
         want = oracle.trace_single(w.j_map, w.kappa_map, src, nr, 0.5, 6.0, 1.0)
         assert_parity(got, want)
 
 
-def test_long_march_piles_up_on_box_corners(rt, dev):
+@pytest.mark.parametrize("gather", [0, 3])
+def test_long_march_piles_up_on_box_corners(rt, dev, gather):
     """Rays that leave the box through a corner octant end up clamped onto the corner voxel
-    for the rest of the march; those samples take the record kernel's per-corner sums."""
+    for the rest of the march; those samples take the record kernel's per-corner sums (and,
+    with the gather pass, which no tile lists them for, read j and kappa from the maps)."""
     rng = np.random.default_rng(9)
     shape = (12, 10, 14)
     j = rng.random(shape).astype(np.float32)
     kap = (0.02 * rng.random(shape)).astype(np.float32)
     src = np.array([[1.5, 1.5, 1.5], [10.0, 8.5, 12.0], [6.0, 0.2, 13.0]], np.float32)
-    got = multi(rt, to_dev(j, dev), to_dev(kap, dev), src, [500, 257, 64], 0.5, 60.0, 1.0).cpu().numpy()
+    got = multi(rt, to_dev(j, dev), to_dev(kap, dev), src, [500, 257, 64], 0.5, 60.0, 1.0,
+                gather_table=gather).cpu().numpy()
     want = oracle.trace_multi(j, kap, src, [500, 257, 64], 0.5, 60.0, 1.0)
     assert_parity(got, want)
     corners = [want[x, y, z] for x in (0, -1) for y in (0, -1) for z in (0, -1)]
