@@ -311,7 +311,8 @@ def surrogate_rates(n_train=300, n_val=30, n_eval=30):
            "validation_error_median": errs[len(errs) // 2], "validation_error_best": errs[0],
            "training": f"{n_train} samples, 6 epochs, batch 4, cheap march N_Omega/{cd}",
            "note": "a short training inside the benchmark; the 2000-sample runs are summarised in "
-                   "profiles/surrogate_c5_64_training.md"}
+                   "profiles/surrogate_c5_64_training.md",
+           "conv_kernels_64": sg.conv_rates(dev)}
     del train, val, ev
     torch.cuda.empty_cache()
     return out

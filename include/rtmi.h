@@ -314,8 +314,9 @@ int32_t rtmi_conv3d_backward_data(const void* dz, const void* w, const float* re
 
 /* backward-weight: dw[tap][co][ci] += sum_v dz[v][co] x[v + off(tap)][ci] and
  *   db[co] += sum_v dz[v][co] (fp32; the caller zeroes them). Needs w_dim a multiple of
- *   16, else RTMI_ERR_UNSUPPORTED. Uses 256 bytes per voxel of scratch from the library's
- *   stream-ordered pool. */
+ *   16, else RTMI_ERR_UNSUPPORTED. Uses about 110 KB of scratch per compute unit from the
+ *   library's stream-ordered pool (per-work-group partial sums, added up in a fixed order,
+ *   so the result is the same bits on every call). */
 int32_t rtmi_conv3d_backward_weight(const void* x, const void* dz, int32_t n, int32_t d,
                                     int32_t h, int32_t w_dim, float* dw, float* db,
                                     void* stream);

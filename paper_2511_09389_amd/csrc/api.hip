@@ -1942,11 +1942,9 @@ int32_t rtmi_conv3d_backward_weight(const void* x, const void* dz, int32_t n, in
   a.h = h;
   a.w_dim = w_dim;
   const hipStream_t st = static_cast<hipStream_t>(stream);
-  const size_t nvox = size_t(n) * d * h * w_dim;
-  Scratch held;   // channel-major copies: x three times, dz once
-  if (int32_t rc = acquire_scratch(nvox * rtmi::kConvChannels * 4 * 2, st, kSlotConv, &held)) return rc;
-  unsigned short* scratch = reinterpret_cast<unsigned short*>(held.ptr);
-  hipError_t e = rtmi::launch_wgrad(a, scratch, scratch + nvox * rtmi::kConvChannels * 3, st);
+  Scratch held;   // the work-groups' partial sums
+  if (int32_t rc = acquire_scratch(rtmi::wgrad_scratch_bytes(a), st, kSlotConv, &held)) return rc;
+  hipError_t e = rtmi::launch_wgrad(a, reinterpret_cast<float*>(held.ptr), st);
   if (e != hipSuccess) return hip_fail(e, "conv backward-weight launch");
   if ((e = held.release(st)) != hipSuccess) return hip_fail(e, "workspace release");
   g_error.clear();

@@ -233,8 +233,9 @@ hipError_t launch_features(const float* j, const float* kap, const float* cheap,
 hipError_t launch_surrogate_output(const unsigned short* y, const float* cheap, long long cells,
                                    const float* sums, float* field, float* check, hipStream_t s);
 hipError_t launch_conv(const ConvArgs& a, bool backward, hipStream_t s);
-// Weight gradient; xc (3 * 32 * voxels) and dzc (32 * voxels) bf16 are scratch.
-hipError_t launch_wgrad(const ConvArgs& a, unsigned short* xc, unsigned short* dzc, hipStream_t s);
+// Weight gradient (adds into a.dw and a.db); `part` is scratch of wgrad_scratch_bytes(a).
+size_t wgrad_scratch_bytes(const ConvArgs& a);
+hipError_t launch_wgrad(const ConvArgs& a, float* part, hipStream_t s);
 hipError_t launch_mse(const unsigned short* y, const float* target, long long nvox, float scale,
                       unsigned short* dz, float* loss, hipStream_t s);
 hipError_t launch_adam(float* w, float* m, float* v, const float* g, unsigned short* w_bf16,

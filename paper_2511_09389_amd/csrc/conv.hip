@@ -8,8 +8,8 @@
 // transposed for the backward-data pass, where dx[u][ci] = sum W[tap][co][ci]
 // dz[u - off(tap)][co]), and so does each block's input with its halo.
 // wgrad: dW[tap][co][ci] = sum_v dz[v][co] x[v + off(tap)][ci], a GEMM over the voxels on
-// channel-major copies of dz and of x (three, shifted by dx = -1, 0, +1), so that a row
-// shift is a whole number of rows and every operand an aligned 16-byte load.
+// channel-major LDS copies of dz and of x (three, shifted by dx = -1, 0, +1), so that a
+// row shift is a whole number of rows and every operand an aligned 16-byte read.
 #include "common.h"
 
 namespace rtmi {
@@ -208,91 +208,194 @@ __global__ void __launch_bounds__(kTileConvThreads) conv_tile_kernel(const ConvA
   }
 }
 
-// Weight gradient, dW[tap][co][ci] = sum_v dz[v][co] x[v + off(tap)][ci]: a GEMM whose K
-// dimension is the voxels, while the matrix cores want eight consecutive K values per
-// lane. So dz and x are first copied channel-major (x three times, shifted by dx = -1, 0,
-// +1 within its row, zero past the row's ends); a row shift by (dz, dy) is then a whole
-// number of rows and every operand is one aligned 16-byte load.
-constexpr int kTrVox = 64;      // voxels per transpose block
-constexpr int kTrThreads = 256;
+// Weight gradient, dW[tap][co][ci] = sum_v dz[v][co] x[v + off(tap)][ci]: 27 GEMMs of 32 x 32
+// whose K dimension is the voxels, while the matrix cores want eight consecutive K values
+// per lane for one channel. wgrad_tile_kernel: a persistent work-group of eight waves takes
+// blocks of 1 (z) x 4 (y) x 32 (x) voxels in turn and stages them channel-major in LDS: dz
+// once, and x with its one-voxel halo in z and y three times, shifted by dx = -1, 0, +1, so
+// that every operand of every tap is one aligned 16-byte LDS read. Wave w accumulates the
+// taps w, w + 8, w + 16 (and w + 24) over all its blocks; at the end every work-group writes
+// its partial sums (and its dz channel sums for db), and wgrad_reduce_kernel adds them up,
+// in a fixed order, into dw and db. Channel rows are padded by one 16-byte chunk (17 per dz
+// row, 73 per x plane), so that the 16 lanes of one read pass fall on distinct banks.
+constexpr int kWgY = 4, kWgX = 32;
+constexpr int kWgVox = kWgY * kWgX;                      // 128 voxels: 8 K steps of 16
+constexpr int kWgDzRow = kWgVox / 8 + 1;                 // 17 chunks per dz channel
+constexpr int kWgHz = 3, kWgHy = kWgY + 2;               // staged x rows: 3 z x 6 y of 32
+constexpr int kWgXPlane = kWgHz * kWgHy * (kWgX / 8) + 1;   // 73 chunks per (shift, channel)
+constexpr int kWgThreads = 512;
+constexpr int kWgTapsPerWave = 4;
+constexpr int kWgPartial = 27 * kC * kC + kC;            // floats of one work-group's partial sums
 
-__global__ void __launch_bounds__(kTrThreads) wgrad_transpose_kernel(
-    const unsigned short* __restrict__ x, const unsigned short* __restrict__ dz, long long nvox,
-    int w_dim, unsigned short* __restrict__ xc, unsigned short* __restrict__ dzc, float* __restrict__ db) {
-  __shared__ unsigned short tx[kTrVox + 2][kC + 2];   // voxels v0 - 1 .. v0 + 64
-  __shared__ unsigned short tz[kTrVox][kC + 2];
-  const int tid = static_cast<int>(threadIdx.x);
-  float db_part = 0.0f;
-  for (long long v0 = static_cast<long long>(blockIdx.x) * kTrVox; v0 < nvox;
-       v0 += static_cast<long long>(gridDim.x) * kTrVox) {
-    __syncthreads();
-    for (int i = tid; i < (kTrVox + 2) * kC; i += kTrThreads) {
-      const long long v = v0 - 1 + i / kC;
-      tx[i / kC][i % kC] = (v >= 0 && v < nvox) ? x[v * kC + i % kC] : 0;
-    }
-    for (int i = tid; i < kTrVox * kC; i += kTrThreads) {
-      const long long v = v0 + i / kC;
-      tz[i / kC][i % kC] = v < nvox ? dz[v * kC + i % kC] : 0;
-    }
-    __syncthreads();
-    for (int i = tid; i < kC * kTrVox; i += kTrThreads) {
-      const int c = i / kTrVox, jv = i % kTrVox;
-      const long long v = v0 + jv;
-      if (v >= nvox) continue;
-      dzc[c * nvox + v] = tz[jv][c];
-      const int xpos = static_cast<int>(v % w_dim);
-#pragma unroll
-      for (int sh = 0; sh < 3; ++sh) {
-        const int xx = xpos + sh - 1;
-        xc[(sh * kC + c) * nvox + v] = (xx >= 0 && xx < w_dim) ? tx[jv + sh][c] : 0;
-      }
-    }
-    if (tid < kC)
-      for (int jv = 0; jv < kTrVox && v0 + jv < nvox; ++jv) db_part += bf16_to_f32(tz[jv][tid]);
-  }
-  if (tid < kC && db_part != 0.0f) unsafeAtomicAdd(db + tid, db_part);
-}
-
-constexpr int kGemmThreads = 256;   // four waves; wave w owns the taps w, w + 4, ...
-constexpr int kTapsPerWave = 7;
-
-__global__ void __launch_bounds__(kGemmThreads) wgrad_gemm_kernel(
-    const unsigned short* __restrict__ xc, const unsigned short* __restrict__ dzc, long long nvox,
-    int d, int h, int w_dim, float* __restrict__ dw) {
+__global__ void __launch_bounds__(kWgThreads) wgrad_tile_kernel(const ConvArgs a, float* __restrict__ part) {
+  __shared__ __attribute__((aligned(16))) u16x8 dzT[kC * kWgDzRow];
+  __shared__ __attribute__((aligned(16))) u16x8 xS[3 * kC * kWgXPlane];
   const int tid = static_cast<int>(threadIdx.x), lane = tid & 63, wave = tid >> 6;
-  const int col = lane & 31, kg = lane >> 5;
-  f32x16 acc[kTapsPerWave];
+  const int D = a.d, H = a.h, Wd = a.w_dim;
+  const int nby = (H + kWgY - 1) / kWgY, nbx = (Wd + kWgX - 1) / kWgX;
+  const long long nblocks = static_cast<long long>(a.n) * D * nby * nbx;
+  const u16x8* X = static_cast<const u16x8*>(a.x);
+  const u16x8* DZ = static_cast<const u16x8*>(a.dz);
+  f32x16 acc[kWgTapsPerWave];
 #pragma unroll
-  for (int u = 0; u < kTapsPerWave; ++u)
+  for (int u = 0; u < kWgTapsPerWave; ++u)
 #pragma unroll
     for (int i = 0; i < 16; ++i) acc[u][i] = 0.0f;
-  const long long rows = nvox / w_dim;
-  for (long long r = blockIdx.x; r < rows; r += gridDim.x) {
-    const int y = static_cast<int>(r % h), z = static_cast<int>((r / h) % d);
-    for (int kb = 0; kb < w_dim / 16; ++kb) {
-      const long long v0 = r * w_dim + kb * 16 + kg * 8;
-      const u16x8 av = *reinterpret_cast<const u16x8*>(dzc + col * nvox + v0);
+  float dbp[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};   // a dz task: sums of its 8 channels
+  const int m = lane & 31, g = lane >> 5;
+  const int wave_s = __builtin_amdgcn_readfirstlane(wave);   // (uniform: taps in scalar registers)
+  const int taps = (27 - wave_s + 7) / 8;                     // taps wave, wave + 8, ... below 27
+
+  // Staging runs as tasks of 8 consecutive voxels x 8 channels: a task loads them (16 bytes
+  // per voxel), transposes the 8 x 8 block in registers and writes one 16-byte chunk per
+  // channel, 8 voxels of it. A task's bits are ordered (j, row, cq: x group lowest) so that
+  // the 16 lanes of one write pass fall on distinct banks. The global data of a block is
+  // fetched one block ahead, so that its latency overlaps the previous block's products.
+  constexpr int kDzTasks = kWgY * 4 * (kWgX / 8);            // 64: 4 rows x 4 channel groups x 4 x-groups
+  constexpr int kXRows = kWgHz * kWgHy;                      // 18 staged x rows
+  constexpr int kXTasks = kXRows * 4 * (kWgX / 8);           // 288
+  static_assert(kDzTasks + kXTasks <= kWgThreads, "one staging task per thread");
+  // (an x task reads voxels 8 j - 1 .. 8 j + 8 of its row: ten, for the three shifted copies)
+  u16x8 ld[10];
+  int t_row = 0, t_cq = 0, t_j = 0;
+  const bool dz_task = tid < kDzTasks, x_task = !dz_task && tid < kDzTasks + kXTasks;
+  {
+    const int t = dz_task ? tid : tid - kDzTasks;
+    t_j = t & 3;
+    t_cq = ((t >> 3) & 1) | (((t >> 4) & 1) << 1);
+    t_row = ((t >> 2) & 1) | ((t >> 5) << 1);
+  }
+  auto fetch = [&](long long blk) {
+    long long b = blk;
+    const int bx = static_cast<int>(b % nbx) * kWgX;
+    b /= nbx;
+    const int by = static_cast<int>(b % nby) * kWgY;
+    b /= nby;
+    const int bz = static_cast<int>(b % D);
+    const long long n = b / D;
 #pragma unroll
-      for (int u = 0; u < kTapsPerWave; ++u) {
-        const int tap = wave + 4 * u;
-        if (tap >= 27) continue;
-        const int oz = tap / 9 - 1, oy = (tap / 3) % 3 - 1, ox = tap % 3 - 1;
-        u16x8 bv = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (z + oz >= 0 && z + oz < d && y + oy >= 0 && y + oy < h)
-          bv = *reinterpret_cast<const u16x8*>(xc + ((ox + 1) * kC + col) * nvox + v0 +
-                                              (static_cast<long long>(oz) * h + oy) * w_dim);
-        acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av), __builtin_bit_cast(bf16x8, bv), acc[u], 0, 0, 0);
+    for (int k = 0; k < 10; ++k) ld[k] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    if (blk >= nblocks) return;
+    if (dz_task) {   // dz row t_row, voxels 8 t_j .. + 8, zero outside the volume
+      const int y = by + t_row;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const int x = bx + 8 * t_j + k;
+        if (y < H && x < Wd) ld[k] = DZ[(((n * D + bz) * H + y) * static_cast<long long>(Wd) + x) * 4 + t_cq];
+      }
+    } else if (x_task) {   // x row (z, y) = t_row (3 z x 6 y, from bz - 1, by - 1), voxels bx - 1 + 8 t_j + k
+      const int z = bz - 1 + t_row / kWgHy, y = by - 1 + t_row % kWgHy;
+      if (z >= 0 && z < D && y >= 0 && y < H) {
+#pragma unroll
+        for (int k = 0; k < 10; ++k) {
+          const int x = bx - 1 + 8 * t_j + k;
+          if (x >= 0 && x < Wd) ld[k] = X[(((n * D + z) * H + y) * static_cast<long long>(Wd) + x) * 4 + t_cq];
+        }
       }
     }
-  }
-  // rows co (acc_row), columns ci (this lane's col)
+  };
+  // the 8 x 8 transpose: channel e of voxels ld[base .. base + 8)
+  auto column = [&](int base, int e) -> u16x8 {
+    u16x8 c;
 #pragma unroll
-  for (int u = 0; u < kTapsPerWave; ++u) {
-    const int tap = wave + 4 * u;
+    for (int k = 0; k < 8; ++k) c[k] = ld[base + k][e];
+    return c;
+  };
+  fetch(blockIdx.x);
+  for (long long blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+    __syncthreads();   // every wave is done with the previous block
+    if (dz_task) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const u16x8 c = column(0, e);
+        dzT[(8 * t_cq + e) * kWgDzRow + t_row * 4 + t_j] = c;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) dbp[e] += bf16_to_f32(c[k]);
+      }
+    } else if (x_task) {
+      // copy s holds x[bx + xi + s - 1] at xi: for xi = 8 t_j + k that is ld[k + s]
+#pragma unroll
+      for (int sh = 0; sh < 3; ++sh)
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          xS[(sh * kC + 8 * t_cq + e) * kWgXPlane + t_row * 4 + t_j] = column(sh, e);
+    }
+    __syncthreads();
+    fetch(blk + gridDim.x);   // (past the last block: nothing read)
+
+    // Two K steps at a time: all their operands are read before the products that use them
+    // (the fourth tap of the waves that have only three reads a valid slot and is not used).
+#pragma unroll
+    for (int step = 0; step < kWgVox / 16; step += 2) {
+      u16x8 av[2], bv[2][kWgTapsPerWave];
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int r = (step + q) >> 1, h = (step + q) & 1;
+        av[q] = dzT[m * kWgDzRow + r * 4 + 2 * h + g];
+#pragma unroll
+        for (int u = 0; u < kWgTapsPerWave; ++u) {
+          const int tap = min(wave_s + 8 * u, 26);
+          const int oz = tap / 9, oy = (tap / 3) % 3, ox = tap % 3;   // offsets + 1
+          bv[q][u] = xS[(ox * kC + m) * kWgXPlane + (oz * kWgHy + r + oy) * 4 + 2 * h + g];
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int u = 0; u < kWgTapsPerWave; ++u)
+          if (u < taps)
+            acc[u] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, av[q]),
+                                                             __builtin_bit_cast(bf16x8, bv[q][u]), acc[u], 0, 0, 0);
+    }
+  }
+  // partial sums: rows co (acc_row), columns ci (this lane's column); then the dz channel sums
+  float* mine = part + static_cast<long long>(blockIdx.x) * kWgPartial;
+#pragma unroll
+  for (int u = 0; u < kWgTapsPerWave; ++u) {
+    const int tap = wave + 8 * u;
     if (tap >= 27) continue;
 #pragma unroll
-    for (int i = 0; i < 16; ++i)
-      if (acc[u][i] != 0.0f) unsafeAtomicAdd(dw + (tap * kC + acc_row(i, lane)) * kC + col, acc[u][i]);
+    for (int i = 0; i < 16; ++i) mine[(tap * kC + acc_row(i, lane)) * kC + m] = acc[u][i];
+  }
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(xS);   // (the staging space, free now): [dz task][8]
+  if (dz_task) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) red[tid * 8 + e] = dbp[e];
+  }
+  __syncthreads();
+  if (tid < kC) {   // channel tid = 8 cq + e: the dz tasks of channel group cq, in task order
+    float sdb = 0.0f;
+    for (int t = 0; t < kDzTasks; ++t) {
+      const int cq = ((t >> 3) & 1) | (((t >> 4) & 1) << 1);
+      if (cq == tid / 8) sdb += red[t * 8 + tid % 8];
+    }
+    mine[27 * kC * kC + tid] = sdb;
+  }
+}
+
+// dw[i] += sum over the work-groups' partials of element i (and db), in a fixed order: 16
+// lanes per element each sum the partials of every 16th work-group, then the 16 sums are
+// added in lane order. (Many short independent sums keep enough loads in flight.)
+constexpr int kRedSlices = 16, kRedElems = 16;
+
+__global__ void __launch_bounds__(kRedSlices * kRedElems) wgrad_reduce_kernel(const float* __restrict__ part,
+                                                                             int groups, float* __restrict__ dw,
+                                                                             float* __restrict__ db) {
+  __shared__ float sums[kRedSlices][kRedElems];
+  const int e = static_cast<int>(threadIdx.x) % kRedElems, slice = static_cast<int>(threadIdx.x) / kRedElems;
+  const int i = static_cast<int>(blockIdx.x) * kRedElems + e;
+  float s = 0.0f;
+  if (i < kWgPartial)
+    for (int q = slice; q < groups; q += kRedSlices) s += part[static_cast<long long>(q) * kWgPartial + i];
+  sums[slice][e] = s;
+  __syncthreads();
+  if (slice == 0 && i < kWgPartial) {
+    float t = 0.0f;
+#pragma unroll
+    for (int q = 0; q < kRedSlices; ++q) t += sums[q][e];
+    if (i < 27 * kC * kC) dw[i] += t;
+    else db[i - 27 * kC * kC] += t;
   }
 }
 
@@ -423,16 +526,24 @@ hipError_t launch_conv(const ConvArgs& a, bool backward, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_wgrad(const ConvArgs& a, unsigned short* xc, unsigned short* dzc, hipStream_t s) {
-  const long long nvox = static_cast<long long>(a.n) * a.d * a.h * a.w_dim;
-  const int tgrid = grid_for(nvox, kTrVox);
-  hipLaunchKernelGGL(wgrad_transpose_kernel, dim3(tgrid), dim3(kTrThreads), 0, s,
-                     static_cast<const unsigned short*>(a.x), static_cast<const unsigned short*>(a.dz), nvox,
-                     a.w_dim, xc, dzc, a.db);
-  const long long rows = nvox / a.w_dim;
-  const int ggrid = static_cast<int>(rows < 256 ? rows : 256);
-  hipLaunchKernelGGL(wgrad_gemm_kernel, dim3(ggrid), dim3(kGemmThreads), 0, s, xc, dzc, nvox, a.d, a.h,
-                     a.w_dim, a.dw);
+int wgrad_groups(const ConvArgs& a) {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    cus = (hipGetDevice(&dev) == hipSuccess &&
+           hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) ? v : 256;
+  }
+  const long long blocks = static_cast<long long>(a.n) * a.d * ((a.h + kWgY - 1) / kWgY) * ((a.w_dim + kWgX - 1) / kWgX);
+  return static_cast<int>(blocks < cus ? blocks : cus);
+}
+
+size_t wgrad_scratch_bytes(const ConvArgs& a) { return size_t(wgrad_groups(a)) * kWgPartial * sizeof(float); }
+
+hipError_t launch_wgrad(const ConvArgs& a, float* part, hipStream_t s) {
+  const int groups = wgrad_groups(a);
+  hipLaunchKernelGGL(wgrad_tile_kernel, dim3(groups), dim3(kWgThreads), 0, s, a, part);
+  hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((kWgPartial + kRedElems - 1) / kRedElems), dim3(kRedSlices * kRedElems), 0,
+                     s, part, groups, a.dw, a.db);
   return hipGetLastError();
 }
 

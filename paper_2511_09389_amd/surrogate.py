@@ -305,6 +305,58 @@ def evaluate(model, eval_samples, reps=3):
             "march_fields_per_s": n / (t2 - t1), "network_path_fields_per_s": n / (t3 - t2)}
 
 
+def conv_rates(dev, n=64, reps=20):
+    """Milliseconds and TFLOP/s of the four convolution kernels on one n^3 sample with 32
+    channels (55,296 flop per voxel and layer), HIP events on the current stream over
+    `reps` launches each after warm-up: the forward pass with and without the binary32
+    pre-activation kept, the data gradient and the weight gradient (with its transposes).
+    Also the bytes each moves at least (bf16 activations, binary32 pre-activations) and
+    the resulting HBM rate."""
+    g = torch.Generator(device="cpu").manual_seed(0)
+    shape = (1, n, n, n, rtmi.CONV_CHANNELS)
+    x = (torch.randn(shape, generator=g) * 0.5).to(torch.bfloat16).to(dev)
+    w = (torch.randn(rtmi.WEIGHT_SHAPE, generator=g) * 0.05).to(torch.bfloat16).to(dev)
+    bias = torch.zeros(rtmi.CONV_CHANNELS, device=dev)
+    z = torch.empty(shape, dtype=torch.float32, device=dev)
+    y = torch.empty_like(x)
+    dh = torch.empty_like(z)
+    dzp = torch.empty_like(x)
+    dw = torch.zeros(rtmi.WEIGHT_SHAPE, device=dev)
+    db = torch.zeros(rtmi.CONV_CHANNELS, device=dev)
+    vox = n ** 3
+    flop = 2 * 27 * rtmi.CONV_CHANNELS * rtmi.CONV_CHANNELS * vox
+    a16, a32 = 2 * rtmi.CONV_CHANNELS * vox, 4 * rtmi.CONV_CHANNELS * vox   # one activation tensor, bytes
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            fn()
+        end.record()
+        end.synchronize()
+        return start.elapsed_time(end) / reps
+
+    kernels = {
+        # x and the residual read, y and z written
+        "forward": (lambda: rtmi.conv3d_forward(x, w, bias=bias, residual=x, gelu=True, z=z, y=y), 2 * a16 + a16 + a32),
+        "forward_no_preactivation": (lambda: rtmi.conv3d_forward(x, w, bias=bias, residual=x, gelu=True, y=y),
+                                     3 * a16),
+        # dz and the next layer's pre-activation read, dh and dz_prev written
+        "backward_data": (lambda: rtmi.conv3d_backward_data(x, w, residual=z, zprev=z, dh=dh, dz_prev=dzp),
+                          a16 + a32 + a32 + a16),
+        # x and dz read (then their channel-major copies: x three times)
+        "backward_weight": (lambda: rtmi.conv3d_backward_weight(x, x, dw, db), 2 * a16),
+    }
+    out = {}
+    for name, (fn, nbytes) in kernels.items():
+        ms = timed(fn)
+        out[name] = {"ms": ms, "tflops": flop / (ms * 1e-3) / 1e12, "min_bytes": nbytes,
+                     "min_bytes_TBps": nbytes / (ms * 1e-3) / 1e12}
+    return {"grid": n, "flop_per_layer": flop, "kernels": out}
+
+
 def main(argv=None):
     """Train, calibrate and evaluate the surrogate on seeded 64^3 turbulent samples (16
     sources, 4096 rays, 128 substeps; training seeds 0.., validation 5000.., evaluation
@@ -323,8 +375,12 @@ def main(argv=None):
     ap.add_argument("--schedule", choices=("step", "cosine", "constant"), default="step")
     ap.add_argument("--cheap-divisor", type=int, default=CHEAP_DIVISOR)
     ap.add_argument("--save", default=None, help="checkpoint path for the trained, calibrated surrogate")
+    ap.add_argument("--conv-bench", action="store_true", help="only time the convolution kernels at 64^3")
     args = ap.parse_args(argv)
     dev = torch.device("cuda:0")
+    if args.conv_bench:
+        print(json.dumps(conv_rates(dev)), flush=True)
+        return
     t0 = time.perf_counter()
     cd = args.cheap_divisor
     train_s = [make_sample(s, dev, cheap_divisor=cd) for s in range(args.train)]

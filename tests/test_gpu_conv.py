@@ -102,6 +102,24 @@ def test_backward_weight_matches_oracle(rt, dev, shape):
     np.testing.assert_allclose(db.cpu().numpy(), want_b, rtol=1e-5, atol=1e-4)
 
 
+def test_backward_weight_accumulates_in_a_fixed_order(rt, dev):
+    """dw and db are added to, and the per-work-group partial sums are summed in a fixed
+    order: a second call on the same inputs adds exactly the same bits again."""
+    rng = np.random.default_rng(15)
+    shape = (1, 24, 20, 48)
+    x, _, _ = case(rng, dev, shape)
+    dz = bf16(rng.normal(size=shape + (C,)), dev)
+    dw = torch.zeros((27, C, C), dtype=torch.float32, device=dev)
+    db = torch.zeros(C, dtype=torch.float32, device=dev)
+    rt.conv3d_backward_weight(x, dz, dw, db)
+    once_w, once_b = dw.clone(), db.clone()
+    rt.conv3d_backward_weight(x, dz, dw, db)
+    assert torch.equal(dw, 2.0 * once_w) and torch.equal(db, 2.0 * once_b)
+    want_w, _ = S.conv3_grad_weight(f64(x), f64(dz))
+    bound_w, _ = S.conv3_grad_weight(np.abs(f64(x)), np.abs(f64(dz)))
+    assert (np.abs(once_w.cpu().numpy() - want_w) <= 1e-5 * bound_w + 1e-30).all()
+
+
 def test_backward_weight_rejects_odd_rows(rt, dev):
     x = torch.zeros((1, 2, 2, 13, C), dtype=torch.bfloat16, device=dev)
     dw = torch.zeros((27, C, C), device=dev)
