@@ -917,7 +917,15 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
     const long long rbegin = a.tile_begin[t], rcount = a.tile_count[t];
     long long rend = rbegin + rcount * (part + 1) / parts;
     rend = min(rend, min(a.tile_fill[t], a.rec_capacity));
-    for (long long i = rbegin + rcount * part / parts + tid; i < rend; i += kThreads) {
+    // Lanes take the item's records in blocks of kThreads, each wave 8 runs of 8 consecutive
+    // records 64 apart (a run: one or two rays' consecutive chunks), not 64 consecutive ones:
+    // neighbouring rays of a patch deposit into the same or nearby cells at the same
+    // substep, and the LDS adds of one instruction then collide more often (uneven 256^3
+    // tile pass 0.71 -> 0.67 ms, turbulent 128^3 0.14 -> 0.13 ms).
+    const int lane_rec = (tid % 8) * (kThreads / 8) + tid / 8;
+    for (long long i0 = rbegin + rcount * part / parts; i0 < rend; i0 += kThreads) {
+      const long long i = i0 + lane_rec;
+      if (i >= rend) continue;
       const uint2 rec = a.recs[i];
       const int s = static_cast<int>((rec.x >> kRecRayBits) | ((rec.y >> kRecChunkEnd) << 8));
       const int ray = static_cast<int>(rec.x & ((1u << kRecRayBits) - 1u));
