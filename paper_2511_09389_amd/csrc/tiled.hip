@@ -872,6 +872,32 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
   }
 }
 
+// Axes on which a tile touches a box face: bit 4, 2, 1 for x, y, z.
+__device__ __forceinline__ int tile_faces(const TileGeom& g, int nx, int ny, int nz) {
+  return (g.x0 > 0 && g.x0 + g.ex < nx ? 0 : 4) | (g.y0 > 0 && g.y0 + g.ey < ny ? 0 : 2) |
+         (g.z0 > 0 && g.z0 + g.ez < nz ? 0 : 1);
+}
+
+// One axis of a sample's stencil in a tile with origin o: the lower corner's padded index
+// (halo at 0), and the corners' weights. FACE: the tile touches a box face on this axis,
+// so the sample may be clamped there (a collapsed axis carries its whole weight on the
+// lower corner); otherwise it is not clamped if its stencil reaches the tile, and the
+// index is only bounded before the conversion (the bound never passes the reach test).
+template <bool FACE>
+__device__ __forceinline__ int tile_axis(float x, int n, int o, float (&w)[2]) {
+  if constexpr (FACE) {
+    const Axis A = axis_stencil(x, n);
+    w[0] = A.lo == A.hi ? 1.0f : A.w0;
+    w[1] = A.lo == A.hi ? 0.0f : A.w1;
+    return A.lo - o + 1;
+  } else {
+    const float f = floorf(x);
+    w[1] = x - f;
+    w[0] = 1.0f - w[1];
+    return static_cast<int>(fminf(fmaxf(f, -1.0f), static_cast<float>(n))) - o + 1;
+  }
+}
+
 // One bin per launch, 512 lanes per work-group, three work-groups per compute unit.
 // The tile is accumulated in binary64 (or 64-bit fixed point in the deterministic mode):
 // a voxel next to a source collects thousands of deposits, and binary32 running sums of
@@ -911,6 +937,7 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
     const int part = claimed.y & 0xffff, parts = claimed.y >> 16;
     const TileGeom g = tile_geom(a, t);
     const int x0 = g.x0, y0 = g.y0, z0 = g.z0, ex = g.ex, ey = g.ey, ez = g.ez;
+    const int faces = tile_faces(g, nx, ny, nz);
 
     // The item's share of the tile's chunk records; only records below the fill cursor
     // and inside the buffer were written.
@@ -961,25 +988,35 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
                                           typename std::conditional<NEAREST, double, float>::type>::type;
       int cell = -1;   // padded slot of the current lower corner (nearest voxel)
       R run[kCorners];
-      auto flush = [&]() {
+      // SKIP_ZERO: sums that are exactly zero are not added. In a tile on a box face, a
+      // sample clamped on an axis (beyond the face: four in ten samples of a march whose
+      // rays run out of the box) carries no weight on its upper corners along that axis,
+      // and the adds left out make the instruction cheaper (an LDS atomic costs about one
+      // pass per lane that shares a bank with another active lane).
+      auto flush = [&](auto skip_tag) {
+        constexpr bool SKIP_ZERO = decltype(skip_tag)::value;
         if (cell < 0) return;
 #pragma unroll
         for (int c = 0; c < kCorners; ++c)
-          atomicAdd(&acc[cell + (c >> 2) * kPadPlane + ((c >> 1) & 1) * kPadRow + (c & 1)], static_cast<T>(run[c]));
+          if (!SKIP_ZERO || run[c] != R(0))
+            atomicAdd(&acc[cell + (c >> 2) * kPadPlane + ((c >> 1) & 1) * kPadRow + (c & 1)], static_cast<T>(run[c]));
       };
-      auto move_to = [&](int slot) {
+      auto move_to = [&](int slot, auto skip_tag) {
         if (slot == cell) return;
-        flush();
+        flush(skip_tag);
         cell = slot;
 #pragma unroll
         for (int c = 0; c < kCorners; ++c) run[c] = R(0);
       };
-      // On a tile that touches no box face (INNER, uniform over the item) a sample whose
-      // stencil reaches the tile is clamped on no axis (a clamped lower corner is 0 or
-      // n - 1, outside such a tile's reach), so the clamps, the collapsed-axis weights and
-      // the box-corner test drop out of its sample loop.
-      auto samples = [&](auto inner_tag) {
-        constexpr bool INNER = decltype(inner_tag)::value;
+      // FACES (uniform over the item): bit 4, 2, 1 set for the axes x, y, z on which the
+      // tile touches a box face. On the other axes a sample whose stencil reaches the tile
+      // is never clamped (a clamped lower corner is 0 or n - 1, outside the tile's reach
+      // there), so their clamps and collapsed-axis weights drop out of the sample loop, and
+      // unless the tile touches faces on all three axes so does the box-corner test.
+      auto samples = [&](auto faces_tag) {
+        constexpr int FACES = decltype(faces_tag)::value;
+        constexpr bool INNER = FACES == 0;
+        constexpr std::integral_constant<bool, !INNER> skip_zero{};
 #pragma unroll
         for (int u = 0; u < kChunk; ++u) {
           const int k = kblk + u;
@@ -987,7 +1024,7 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
           const float x = sample_axis(src.x, dist, dd.x);
           const float y = sample_axis(src.y, dist, dd.y);
           const float z = sample_axis(src.z, dist, dd.z);
-          if constexpr (INNER) {
+          if constexpr (FACES != 7) {
             if ((k < kbeg) | (k > kend)) continue;
           } else {
             // outside this ray's range for the tile, or collapsed onto one corner voxel of
@@ -1012,45 +1049,21 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
                 (static_cast<unsigned>(ly) >= static_cast<unsigned>(ey)) |
                 (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
               continue;
-            move_to(pad_slot(lx + 1, ly + 1, lz + 1));
+            move_to(pad_slot(lx + 1, ly + 1, lz + 1), skip_zero);
             run[0] += tile_value<R>(vv[u], det_scale);
           } else {
             // some corner lies in the tile iff the lower corner is in [origin - 1, origin +
             // extent - 1] on every axis (a collapsed axis, lower = upper corner, only occurs
             // on the box faces, where the lower corner is never origin - 1)
             float wx[2], wy[2], wz[2];
-            int px, py, pz;
-            if constexpr (INNER) {
-              const float fx = floorf(x), fy = floorf(y), fz = floorf(z);
-              px = static_cast<int>(fminf(fmaxf(fx, -1.0f), static_cast<float>(nx))) - x0 + 1;
-              py = static_cast<int>(fminf(fmaxf(fy, -1.0f), static_cast<float>(ny))) - y0 + 1;
-              pz = static_cast<int>(fminf(fmaxf(fz, -1.0f), static_cast<float>(nz))) - z0 + 1;
-              wx[1] = x - fx;
-              wy[1] = y - fy;
-              wz[1] = z - fz;
-              wx[0] = 1.0f - wx[1];
-              wy[0] = 1.0f - wy[1];
-              wz[0] = 1.0f - wz[1];
-            } else {
-              const Axis X = axis_stencil(x, nx);
-              const Axis Y = axis_stencil(y, ny);
-              const Axis Z = axis_stencil(z, nz);
-              px = X.lo - x0 + 1;
-              py = Y.lo - y0 + 1;
-              pz = Z.lo - z0 + 1;
-              // a collapsed axis carries its whole weight on the lower corner
-              wx[0] = X.lo == X.hi ? 1.0f : X.w0;
-              wx[1] = X.lo == X.hi ? 0.0f : X.w1;
-              wy[0] = Y.lo == Y.hi ? 1.0f : Y.w0;
-              wy[1] = Y.lo == Y.hi ? 0.0f : Y.w1;
-              wz[0] = Z.lo == Z.hi ? 1.0f : Z.w0;
-              wz[1] = Z.lo == Z.hi ? 0.0f : Z.w1;
-            }
+            const int px = tile_axis<(FACES & 4) != 0>(x, nx, x0, wx);
+            const int py = tile_axis<(FACES & 2) != 0>(y, ny, y0, wy);
+            const int pz = tile_axis<(FACES & 1) != 0>(z, nz, z0, wz);
             if ((static_cast<unsigned>(px) > static_cast<unsigned>(ex)) |
                 (static_cast<unsigned>(py) > static_cast<unsigned>(ey)) |
                 (static_cast<unsigned>(pz) > static_cast<unsigned>(ez)))
               continue;
-            move_to(pad_slot(px, py, pz));
+            move_to(pad_slot(px, py, pz), skip_zero);
             if constexpr (DET) {
 #pragma unroll
               for (int c = 0; c < 8; ++c) {
@@ -1064,10 +1077,15 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
             }
           }
         }
+        flush(skip_zero);
       };
-      if (g.interior) samples(std::true_type{});
-      else samples(std::false_type{});
-      flush();
+      switch (faces) {
+        case 0: samples(std::integral_constant<int, 0>{}); break;
+        case 4: samples(std::integral_constant<int, 4>{}); break;
+        case 2: samples(std::integral_constant<int, 2>{}); break;
+        case 1: samples(std::integral_constant<int, 1>{}); break;
+        default: samples(std::integral_constant<int, 7>{}); break;   // (edges and corners of the box)
+      }
     }
     __syncthreads();
 
@@ -1123,6 +1141,26 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
 // box-corner voxel are left to the record pass. The record pass then reads one 64-byte
 // piece per ray and 8 substeps instead of one random 64-byte table line per sample.
 constexpr int kGEdge = kTile + 1;
+
+// One axis of a sample in the gather pass's tile with origin o: the lower corner's index in
+// the tile, the upper corner's weight and the nearest voxel's index. FACE as in tile_axis;
+// otherwise the nearest voxel is the lower corner, or the upper one past the midpoint
+// (rint's halfway cases round to even; no clamp reaches a sample that the tile owns).
+template <bool FACE>
+__device__ __forceinline__ int gather_axis(float x, int n, int o, float& w1, int& nearest) {
+  if constexpr (FACE) {
+    const Axis A = axis_stencil(x, n);
+    w1 = A.lo == A.hi ? 0.0f : A.w1;
+    nearest = A.nearest - o;
+    return A.lo - o;
+  } else {
+    const float f = floorf(x);
+    const int l = static_cast<int>(fminf(fmaxf(f, -1.0f), static_cast<float>(n))) - o;
+    w1 = x - f;
+    nearest = l + static_cast<int>(rintf(x) - f);
+    return l;
+  }
+}
 constexpr int kGatherMerge = 4;   // work items of one tile per staging
 constexpr int kGPlane = kGEdge * kGEdge;
 constexpr int kGVox = kGEdge * kGPlane;
@@ -1170,6 +1208,7 @@ __global__ void __launch_bounds__(kTileThreads) gather_pass_kernel(const TileArg
     const int part_end = min(part + merge, parts);
     const TileGeom g = tile_geom(a, t);
     const int x0 = g.x0, y0 = g.y0, z0 = g.z0, ex = g.ex, ey = g.ey, ez = g.ez;
+    const int faces = tile_faces(g, nx, ny, nz);
     {   // (each lane keeps one z of rows kRowsPerPass apart)
       constexpr int kRowsPerPass = kThreads / kGEdge;
       const int lz = tid % kGEdge;
@@ -1205,50 +1244,28 @@ __global__ void __launch_bounds__(kTileThreads) gather_pass_kernel(const TileArg
       const float sx = sr->sx, sy = sr->sy, sz = sr->sz;
       // (byte offset below 4 GiB, carried as the 32-bit pattern the store takes)
       const unsigned row = static_cast<unsigned>(row_slot(sr->vbase, nrays, ray, kblk) * static_cast<long long>(sizeof(float2)));
-      // (INNER: a tile that touches no box face, where a sample with its lower corner
-      // inside is clamped on no axis, as in the tile kernel)
-      auto samples = [&](auto inner_tag) {
-        constexpr bool INNER = decltype(inner_tag)::value;
+      // (FACES: the axes on which the tile touches a box face, as in the tile kernel; a
+      // sample this tile owns is clamped on no other axis)
+      auto samples = [&](auto faces_tag) {
+        constexpr int FACES = decltype(faces_tag)::value;
         // sample u of the chunk: false if this tile does not own it, else its (j, kappa)
         auto one = [&](int u, float2& res) -> bool {
           const int k = kblk + u;
-          if (INNER && ((k < kbeg) | (k > kend))) return false;
+          if (FACES != 7 && ((k < kbeg) | (k > kend))) return false;
           const float dist = sample_distance(k, ds);
           const float x = sample_axis(sx, dist, dd.x);
           const float y = sample_axis(sy, dist, dd.y);
           const float z = sample_axis(sz, dist, dd.z);
-          float wx[2], wy[2], wz[2];   // (only the upper weights are used)
-          int lx, ly, lz, nxl, nyl, nzl;
-          if constexpr (INNER) {
-            const float fx = floorf(x), fy = floorf(y), fz = floorf(z);
-            lx = static_cast<int>(fminf(fmaxf(fx, -1.0f), static_cast<float>(nx))) - x0;
-            ly = static_cast<int>(fminf(fmaxf(fy, -1.0f), static_cast<float>(ny))) - y0;
-            lz = static_cast<int>(fminf(fmaxf(fz, -1.0f), static_cast<float>(nz))) - z0;
-            wx[1] = x - fx;
-            wy[1] = y - fy;
-            wz[1] = z - fz;
-            // the nearest voxel: the lower corner, or the upper one past the midpoint (rint's
-            // halfway cases round to even; no clamp reaches a sample this tile owns)
-            nxl = lx + static_cast<int>(rintf(x) - fx);
-            nyl = ly + static_cast<int>(rintf(y) - fy);
-            nzl = lz + static_cast<int>(rintf(z) - fz);
-          } else {
+          if constexpr (FACES == 7) {
             const int clamped = static_cast<int>(axis_clamped(x, nx)) + static_cast<int>(axis_clamped(y, ny)) +
                                 static_cast<int>(axis_clamped(z, nz));
             if ((k < kbeg) | (k > kend) | (clamped == 3)) return false;
-            const Axis X = axis_stencil(x, nx);
-            const Axis Y = axis_stencil(y, ny);
-            const Axis Z = axis_stencil(z, nz);
-            lx = X.lo - x0;
-            ly = Y.lo - y0;
-            lz = Z.lo - z0;
-            wx[1] = X.lo == X.hi ? 0.0f : X.w1;
-            wy[1] = Y.lo == Y.hi ? 0.0f : Y.w1;
-            wz[1] = Z.lo == Z.hi ? 0.0f : Z.w1;
-            nxl = X.nearest - x0;
-            nyl = Y.nearest - y0;
-            nzl = Z.nearest - z0;
           }
+          float wx[2], wy[2], wz[2];   // (only the upper weights are used)
+          int nxl, nyl, nzl;
+          const int lx = gather_axis<(FACES & 4) != 0>(x, nx, x0, wx[1], nxl);
+          const int ly = gather_axis<(FACES & 2) != 0>(y, ny, y0, wy[1], nyl);
+          const int lz = gather_axis<(FACES & 1) != 0>(z, nz, z0, wz[1], nzl);
           if ((static_cast<unsigned>(lx) >= static_cast<unsigned>(ex)) |
               (static_cast<unsigned>(ly) >= static_cast<unsigned>(ey)) |
               (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
@@ -1284,8 +1301,13 @@ __global__ void __launch_bounds__(kTileThreads) gather_pass_kernel(const TileArg
           }
         }
       };
-      if (g.interior) samples(std::true_type{});
-      else samples(std::false_type{});
+      switch (faces) {
+        case 0: samples(std::integral_constant<int, 0>{}); break;
+        case 4: samples(std::integral_constant<int, 4>{}); break;
+        case 2: samples(std::integral_constant<int, 2>{}); break;
+        case 1: samples(std::integral_constant<int, 1>{}); break;
+        default: samples(std::integral_constant<int, 7>{}); break;
+      }
     }
     __syncthreads();   // the staged tile is replaced by the next item's
   }
