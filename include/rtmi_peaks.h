@@ -39,7 +39,10 @@ int32_t rtmi_peak_gather(int64_t footprint, int32_t iters, int32_t reps, double*
  * lanes of an instruction on consecutive slots: kind 0 = binary64 (ds_add_f64), 1 = 64-bit
  * integer (ds_add_u64), 2 = binary32 (ds_add_f32); kind 3 = binary64 with every lane on a
  * pseudo-random slot of a 48 KB array (bank conflicts and occasional shared addresses, as
- * when lanes deposit along unrelated rays). Adds per second. */
+ * when lanes deposit along unrelated rays), 4 = the same in 64-bit integers, 5, 6, 7 =
+ * kind 3 with only one lane in 2, 4 or 8 of each wavefront adding. Adds (of the lanes that
+ * add) per second; -1 for another kind or an `iters` that is not a multiple of the slots
+ * per lane. */
 int32_t rtmi_peak_lds_atomic(int32_t kind, int32_t iters, int32_t reps, double* rate,
                              double* bytes_or_ops);
 

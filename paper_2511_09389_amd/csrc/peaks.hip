@@ -72,26 +72,30 @@ __global__ void __launch_bounds__(kLdsThreads) lds_atomic_kernel(int iters, T* _
   out[blockIdx.x * kLdsThreads + tid] = s;
 }
 
-// The same adds in binary64 at pseudo-random slots of the 48 KB array (each lane draws its
-// kLdsRounds slots once, so the loop issues nothing but the adds): the bank conflicts and
-// occasional same-address collisions of lanes whose addresses are unrelated, as in a tile
-// pass whose lanes deposit along different rays.
-__global__ void __launch_bounds__(kLdsThreads) lds_atomic_random_kernel(int iters, double* __restrict__ out) {
-  __shared__ double acc[kLdsSlots];
+// The same adds at pseudo-random slots of the 48 KB array (each lane draws its kLdsRounds
+// slots once, so the loop issues nothing but the adds): the bank conflicts and occasional
+// same-address collisions of lanes whose addresses are unrelated, as in a tile pass whose
+// lanes deposit along different rays. Only one lane in EVERY of each wave adds, as in a
+// tile pass where only the lanes whose ray left a cell flush their sums.
+template <typename T, int EVERY>
+__global__ void __launch_bounds__(kLdsThreads) lds_atomic_random_kernel(int iters, T* __restrict__ out) {
+  __shared__ T acc[kLdsSlots];
   const int tid = static_cast<int>(threadIdx.x);
-  for (int i = tid; i < kLdsSlots; i += kLdsThreads) acc[i] = 0.0;
+  for (int i = tid; i < kLdsSlots; i += kLdsThreads) acc[i] = T(0);
   int slot[kLdsRounds];
 #pragma unroll
   for (int q = 0; q < kLdsRounds; ++q)
     slot[q] = static_cast<int>(seed(static_cast<unsigned>((blockIdx.x * kLdsThreads + tid) * kLdsRounds + q)) %
                                static_cast<unsigned>(kLdsSlots));
   __syncthreads();
-  for (int it = 0; it < iters; it += kLdsRounds) {
+  if ((tid & 63) % EVERY == 0) {
+    for (int it = 0; it < iters; it += kLdsRounds) {
 #pragma unroll
-    for (int q = 0; q < kLdsRounds; ++q) atomicAdd(&acc[slot[q]], 1.0);
+      for (int q = 0; q < kLdsRounds; ++q) atomicAdd(&acc[slot[q]], T(1));
+    }
   }
   __syncthreads();
-  double s = 0.0;
+  T s = T(0);
 #pragma unroll
   for (int q = 0; q < kLdsRounds; ++q) s += acc[tid + kLdsThreads * q];
   out[blockIdx.x * kLdsThreads + tid] = s;
@@ -203,7 +207,7 @@ int32_t rtmi_peak_gather(int64_t footprint, int32_t iters, int32_t reps, double*
 }
 
 int32_t rtmi_peak_lds_atomic(int32_t kind, int32_t iters, int32_t reps, double* rate, double* bytes_or_ops) {
-  if (!rate || kind < 0 || kind > 3 || iters < kLdsRounds || iters % kLdsRounds) return -1;
+  if (!rate || kind < 0 || kind > 7 || iters < kLdsRounds || iters % kLdsRounds) return -1;
   const int grid = compute_units() * 3;
   Buffers B;
   if (hipMalloc(&B.p[0], static_cast<size_t>(grid) * kLdsThreads * 8) != hipSuccess) return -4;
@@ -216,14 +220,27 @@ int32_t rtmi_peak_lds_atomic(int32_t kind, int32_t iters, int32_t reps, double* 
       hipLaunchKernelGGL(lds_atomic_kernel<float>, dim3(grid), dim3(kLdsThreads), 0, nullptr, iters,
                          static_cast<float*>(B.p[0]));
     else if (kind == 3)
-      hipLaunchKernelGGL(lds_atomic_random_kernel, dim3(grid), dim3(kLdsThreads), 0, nullptr, iters,
+      hipLaunchKernelGGL((lds_atomic_random_kernel<double, 1>), dim3(grid), dim3(kLdsThreads), 0, nullptr, iters,
+                         static_cast<double*>(B.p[0]));
+    else if (kind == 4)
+      hipLaunchKernelGGL((lds_atomic_random_kernel<unsigned long long, 1>), dim3(grid), dim3(kLdsThreads), 0,
+                         nullptr, iters, static_cast<unsigned long long*>(B.p[0]));
+    else if (kind == 5)
+      hipLaunchKernelGGL((lds_atomic_random_kernel<double, 2>), dim3(grid), dim3(kLdsThreads), 0, nullptr, iters,
+                         static_cast<double*>(B.p[0]));
+    else if (kind == 6)
+      hipLaunchKernelGGL((lds_atomic_random_kernel<double, 4>), dim3(grid), dim3(kLdsThreads), 0, nullptr, iters,
+                         static_cast<double*>(B.p[0]));
+    else if (kind == 7)
+      hipLaunchKernelGGL((lds_atomic_random_kernel<double, 8>), dim3(grid), dim3(kLdsThreads), 0, nullptr, iters,
                          static_cast<double*>(B.p[0]));
     else
       hipLaunchKernelGGL(lds_atomic_kernel<unsigned long long>, dim3(grid), dim3(kLdsThreads), 0, nullptr, iters,
                          static_cast<unsigned long long*>(B.p[0]));
   }, reps, &t);
   if (rc) return rc;
-  const double ops = static_cast<double>(grid) * kLdsThreads * iters;
+  const int every = kind == 5 ? 2 : kind == 6 ? 4 : kind == 7 ? 8 : 1;   // (adds of the active lanes)
+  const double ops = static_cast<double>(grid) * kLdsThreads * iters / every;
   *rate = ops / t;
   if (bytes_or_ops) *bytes_or_ops = ops;
   return 0;

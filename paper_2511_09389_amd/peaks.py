@@ -53,10 +53,15 @@ def gather(footprint, iters=64, reps=5):
     return _run(lib.rtmi_peak_gather, int(footprint), int(iters), int(reps))
 
 
+LDS_KINDS = {"f64": 0, "u64": 1, "f32": 2, "f64_random": 3, "u64_random": 4,
+             "f64_random_half": 5, "f64_random_quarter": 6, "f64_random_eighth": 7}
+
+
 def lds_atomic(kind="f64", iters=1200, reps=5):
-    """LDS atomic adds (kinds: f64, u64, f32 on consecutive slots; f64_random on random
-    slots): (adds/s, adds per launch)."""
-    return _run(lib.rtmi_peak_lds_atomic, {"f64": 0, "u64": 1, "f32": 2, "f64_random": 3}[kind], int(iters), int(reps))
+    """LDS atomic adds (kinds: f64, u64, f32 on consecutive slots; f64_random, u64_random
+    on random slots; f64_random_half/_quarter/_eighth with one lane in 2/4/8 adding):
+    (adds/s of the adding lanes, adds per launch)."""
+    return _run(lib.rtmi_peak_lds_atomic, LDS_KINDS[kind], int(iters), int(reps))
 
 
 def global_atomic(footprint=64 << 20, scattered=False, iters=64, reps=5):
@@ -75,6 +80,9 @@ def measure_all():
     out["lds_add_u64_per_s"] = lds_atomic("u64")[0]
     out["lds_add_f32_per_s"] = lds_atomic("f32")[0]
     out["lds_add_f64_random_per_s"] = lds_atomic("f64_random")[0]
+    out["lds_add_u64_random_per_s"] = lds_atomic("u64_random")[0]
+    out["lds_add_f64_random_half_lanes_per_s"] = lds_atomic("f64_random_half")[0]
+    out["lds_add_f64_random_quarter_lanes_per_s"] = lds_atomic("f64_random_quarter")[0]
     out["global_atomic_f32_coalesced_per_s"] = global_atomic(scattered=False)[0]
     out["global_atomic_f32_scattered_per_s"] = global_atomic(scattered=True)[0]
     return out

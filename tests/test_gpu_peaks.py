@@ -32,12 +32,16 @@ def test_copy_and_gathers(peaks):
 
 
 def test_lds_atomics(peaks):
-    rates = {k: peaks.lds_atomic(k, iters=240, reps=2) for k in ("f64", "u64", "f32", "f64_random")}
+    rates = {k: peaks.lds_atomic(k, iters=240, reps=2) for k in peaks.LDS_KINDS}
     note({k: f"{v[0] / 1e12:.3f} T/s" for k, v in rates.items()})
-    ops = {v[1] for v in rates.values()}
-    assert len(ops) == 1 and ops.pop() > 0   # the same adds per launch in every kind
+    full = {k: v[1] for k, v in rates.items() if k in ("f64", "u64", "f32", "f64_random", "u64_random")}
+    assert len(set(full.values())) == 1 and rates["f64"][1] > 0   # the same adds per launch
+    assert rates["f64_random_half"][1] * 2 == rates["f64"][1]
+    assert rates["f64_random_eighth"][1] * 8 == rates["f64"][1]
     assert all(v[0] > 0 for v in rates.values())
     assert rates["f64_random"][0] <= 1.1 * rates["f64"][0]
+    # fewer adding lanes cost less per instruction but more per add
+    assert rates["f64_random_eighth"][0] < rates["f64_random"][0]
     with pytest.raises(RuntimeError):
         peaks.lds_atomic("f64", iters=7)       # iters must be a multiple of the slots per lane
 
