@@ -446,11 +446,11 @@ __device__ __forceinline__ void clip_axis(float s, float n, float inv, float lo,
   t1 = fminf(t1, u1);
 }
 
-// Deposits reach the LDS tile one corner at a time. In the deterministic mode the tile
-// holds 64-bit fixed point: each value is scaled and rounded to an integer before the
+// Sums reach the LDS tile one corner at a time. In the deterministic mode the tile holds
+// 64-bit fixed point: each sum is scaled and rounded to an integer before the
 // (order-independent) integer add.
-template <typename T>
-__device__ __forceinline__ T tile_value(float v, double scale) {
+template <typename T, typename V>
+__device__ __forceinline__ T tile_value(V v, double scale) {
   if constexpr (std::is_same<T, unsigned long long>::value)
     return static_cast<unsigned long long>(__double2ll_rn(static_cast<double>(v) * scale));
   else
@@ -979,13 +979,15 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
       // (the nearest voxel, for NEAREST) in registers: samples less than a voxel apart
       // often do. The sums reach the tile when the ray moves on to another cell and at the
       // end of the chunk, which takes a third or more of the LDS atomics away. Such a run
-      // has at most kChunk terms, so in the float mode it is summed in binary32 (error below
-      // kChunk units in the last place of the sum of the terms' magnitudes; the terms share
-      // the sign of the ray's I, which changes only where j does) and only the tile is
-      // binary64. The nearest-voxel deposits of the adjoint mix signs: their runs stay binary64.
+      // has at most kChunk terms, so it is summed in binary32 (error below kChunk units in
+      // the last place of the sum of the terms' magnitudes; the terms share the sign of the
+      // ray's I, which changes only where j does) and only the tile is binary64 (or fixed
+      // point). The nearest-voxel deposits of the adjoint mix signs: their runs are binary64.
+      // A run holds the samples of one chunk record in their order along the ray, whatever
+      // the schedule, the source order or the launch split, so in the deterministic mode
+      // its sum, converted to fixed point when it reaches the tile, is the same on every call.
       constexpr int kCorners = NEAREST ? 1 : 8;
-      using R = typename std::conditional<DET, unsigned long long,
-                                          typename std::conditional<NEAREST, double, float>::type>::type;
+      using R = typename std::conditional<NEAREST, double, float>::type;
       int cell = -1;   // padded slot of the current lower corner (nearest voxel)
       R run[kCorners];
       // SKIP_ZERO: sums that are exactly zero are not added. In a tile on a box face, a
@@ -999,7 +1001,8 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
 #pragma unroll
         for (int c = 0; c < kCorners; ++c)
           if (!SKIP_ZERO || run[c] != R(0))
-            atomicAdd(&acc[cell + (c >> 2) * kPadPlane + ((c >> 1) & 1) * kPadRow + (c & 1)], static_cast<T>(run[c]));
+            atomicAdd(&acc[cell + (c >> 2) * kPadPlane + ((c >> 1) & 1) * kPadRow + (c & 1)],
+                      tile_value<T>(run[c], det_scale));
       };
       auto move_to = [&](int slot, auto skip_tag) {
         if (slot == cell) return;
@@ -1050,7 +1053,7 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
                 (static_cast<unsigned>(lz) >= static_cast<unsigned>(ez)))
               continue;
             move_to(pad_slot(lx + 1, ly + 1, lz + 1), skip_zero);
-            run[0] += tile_value<R>(vv[u], det_scale);
+            run[0] += static_cast<R>(vv[u]);
           } else {
             // some corner lies in the tile iff the lower corner is in [origin - 1, origin +
             // extent - 1] on every axis (a collapsed axis, lower = upper corner, only occurs
@@ -1064,17 +1067,10 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
                 (static_cast<unsigned>(pz) > static_cast<unsigned>(ez)))
               continue;
             move_to(pad_slot(px, py, pz), skip_zero);
-            if constexpr (DET) {
+            // v (wx wy) wz as (wx wy)(v wz): 14 products instead of 20
+            const float vz[2] = {vv[u] * wz[0], vv[u] * wz[1]};
 #pragma unroll
-              for (int c = 0; c < 8; ++c) {
-                const float w = (wx[c >> 2] * wy[(c >> 1) & 1]) * wz[c & 1];
-                run[c] += tile_value<R>(vv[u] * w, det_scale);
-              }
-            } else {   // v (wx wy) wz as (wx wy)(v wz): 14 products instead of 20
-              const float vz[2] = {vv[u] * wz[0], vv[u] * wz[1]};
-#pragma unroll
-              for (int c = 0; c < 8; ++c) run[c] += (wx[c >> 2] * wy[(c >> 1) & 1]) * vz[c & 1];
-            }
+            for (int c = 0; c < 8; ++c) run[c] += (wx[c >> 2] * wy[(c >> 1) & 1]) * vz[c & 1];
           }
         }
         flush(skip_zero);
