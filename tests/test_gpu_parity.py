@@ -413,3 +413,31 @@ def test_dropped_chunk_records_are_reported(rt, dev):
     want = oracle.trace_multi(w.j_map, w.kappa_map, w.source_pos, 256, 0.5, 20.0, 1.0)
     assert_parity(full.cpu().numpy(), want)
     assert float(short.sum()) < float(full.sum())   # the lost deposits are missing, nothing else
+
+
+@pytest.mark.parametrize("deterministic", [False, True])
+@pytest.mark.parametrize("gather_table", [0, 3])
+def test_rays_beyond_every_face(rt, dev, deterministic, gather_table):
+    """Rays that leave the box keep marching with clamped positions and deposit on the face
+    planes. A 40x36x44 grid (three tiles per axis, the last ones partial) holds tiles that
+    touch no face, one face axis, and two or three (the sample loops of the tile and gather
+    passes are specialised by those axes; face tiles leave zero sums out), and the sources
+    sit near each of the six faces with paths about twice the box."""
+    rng = np.random.default_rng(31)
+    shape = (40, 36, 44)
+    j = rng.random(shape).astype(np.float32)
+    kap = (0.02 * rng.random(shape)).astype(np.float32)
+    src = np.array([[0.7, 17.0, 21.0], [38.6, 15.5, 23.0], [20.0, 0.4, 19.5],
+                    [18.5, 35.2, 24.0], [21.0, 16.0, 0.2], [19.0, 18.5, 43.3]], np.float32)
+    rays = [256, 300, 128, 200, 96, 512]
+    note(f"rays beyond every face, {shape}, det {deterministic}, gather_table {gather_table}")
+    want = oracle.trace_multi(j, kap, src, rays, 0.5, 80.0, 1.0)
+    got = multi(rt, to_dev(j, dev), to_dev(kap, dev), src, rays, 0.5, 80.0, 1.0, path=PATHS["tiled"],
+                deterministic=deterministic, gather_table=gather_table).cpu().numpy()
+    err, rel = assert_parity(got, want)
+    faces = np.zeros(shape, bool)
+    faces[[0, -1], :, :] = faces[:, [0, -1], :] = faces[:, :, [0, -1]] = True
+    share = want[faces].sum() / want.sum()
+    note(f"rel L2 {err:.2e}, per voxel {rel:.2e}; the face planes hold {share:.0%} of the field")
+    assert share > 0.2   # the clamped deposits really are exercised
+    assert_parity(got[faces], want[faces])
