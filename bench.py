@@ -424,8 +424,9 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(the design of the source-sharded version is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (a source-sharded "
+              "version would give each GPU a share of the sources and sum the partial fields with one "
+              "all-reduce)", file=sys.stderr)
         sys.exit(2)
     knobs = json.loads(args.knobs) if args.knobs else None
     if args.counters_run:
