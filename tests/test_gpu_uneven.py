@@ -13,7 +13,8 @@ per-voxel relative error <= 1e-4 wherever the oracle exceeds 1e-6 of its maximum
   graph;
 * the whole batch, all 64 sources, run exactly as the benchmark runs it (an autotuned
   plan captured in a HIP graph and replayed), checked voxel by voxel at sampled interior
-  voxels with oracle.trace_voxels, which marches only the rays that can reach them.
+  voxels with oracle.trace_voxels, which marches only the rays that can reach them;
+* the whole batch in the deterministic mode, against the float mode's field.
 
 The oracle work is spread over host processes (fields add over sources).
 """
@@ -180,3 +181,23 @@ def test_full_batch_as_benchmarked_sampled_voxels(rt, uneven):
         assert rel.max() <= PER_VOXEL, f"bin {b}: per-voxel {rel.max():.3e}"
         # voxels below the floor must still be small, not wrong by orders of magnitude
         assert np.all(np.abs(g - want[b]) <= PER_VOXEL * np.maximum(want[b], FLOOR * vmax))
+
+
+def test_deterministic_full_batch(rt, uneven):
+    """The deterministic mode on the whole batch (64 sources, 4 bins, paths that leave the
+    box): bitwise the same on a second call, and within the field tolerances of the float
+    mode (whose field the oracle checks above), so its fixed-point scale, chosen from the
+    worst-case per-voxel sum, leaves enough resolution at this size."""
+    w, j, k = uneven
+    kw = dict(kappa_scale=w.kappa_scale, substep_cap=w.substep_cap)
+    f = rt.trace_bins(j, k, w.source_pos, w.num_rays, w.step_size, w.radiation_velocity, w.time_step, **kw)
+    d = rt.trace_bins(j, k, w.source_pos, w.num_rays, w.step_size, w.radiation_velocity, w.time_step,
+                      deterministic=True, **kw)
+    d2 = rt.trace_bins(j, k, w.source_pos, w.num_rays, w.step_size, w.radiation_velocity, w.time_step,
+                       deterministic=True, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(d.view(torch.int32), d2.view(torch.int32))
+    f, d = f.cpu().numpy(), d.cpu().numpy()
+    for b in range(w.n_bins):
+        err, mx = assert_parity(d[b], f[b].astype(np.float64))
+        note(f"  bin {b}: deterministic vs float, rel L2 {err:.2e}, max per-voxel {mx:.2e}")
