@@ -531,6 +531,17 @@ __device__ __forceinline__ int pair_source(const TileArgs& a, int p) {
   return lo;
 }
 
+// The same search over the sources' first pairs staged in LDS.
+__device__ __forceinline__ int pair_source(const int* first, int n_src, int p) {
+  int lo = 0, hi = n_src;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (first[mid] <= p) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // Can a ray of patch `patch` of source s reach the tile? The bounding box of the patch's
 // segments [0, tmax] (its direction bounds are exact), then, for interior tiles, the
 // cone holding the patch's directions against the sphere around the widened tile.
@@ -773,6 +784,11 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
     rec_end = rec_end < a.rec_capacity ? rec_end : a.rec_capacity;
   }
   unsigned long long sum = 0;
+  // With few sources their first pairs sit in LDS for the searches of pair_source (its
+  // chain of dependent loads measured a tenth of the count pass).
+  __shared__ int first_pair[kCostThreads];
+  const bool staged = a.n_src <= kCostThreads;
+  if (staged && tid < a.n_src) first_pair[tid] = a.src[tid].pbegin;
   // (blocks beyond the grid's y extent, 65535, are taken in turn)
   for (int q0 = static_cast<int>(blockIdx.y); q0 < nblocks; q0 += static_cast<int>(gridDim.y)) {
     __syncthreads();
@@ -785,8 +801,8 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
       if constexpr (FILL) {   // only the pairs the count pass found chunks for
         if ((block_mask[tid >> 5] >> (tid & 31)) & 1u) list[atomicAdd(&count, 1)] = p;
       } else {
-        const int s = pair_source(a, p);
-        if (pair_reaches(a, g, s, p - a.src[s].pbegin)) list[atomicAdd(&count, 1)] = p;
+        const int s = staged ? pair_source(first_pair, a.n_src, p) : pair_source(a, p);
+        if (pair_reaches(a, g, s, p - (staged ? first_pair[s] : a.src[s].pbegin))) list[atomicAdd(&count, 1)] = p;
       }
     }
     __syncthreads();
@@ -804,8 +820,8 @@ __global__ void __launch_bounds__(kCostThreads) tile_pairs_kernel(const TileArgs
         ray[u] = 0;
         if (i < count) {
           const int q = list[i];
-          src[u] = pair_source(a, q);
-          ray[u] = (q - a.src[src[u]].pbegin) * kPatch + lane;
+          src[u] = staged ? pair_source(first_pair, a.n_src, q) : pair_source(a, q);
+          ray[u] = (q - (staged ? first_pair[src[u]] : a.src[src[u]].pbegin)) * kPatch + lane;
           float4 d;
           ray_range(a, g, src[u], ray[u], ka[u], kb[u], d);
         }
