@@ -1152,10 +1152,10 @@ int32_t run_tiled(const Problem& p, const Plan& plan, unsigned long long* out_q,
       if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
     }
     if (!L.jk_rows && (e = records_ready(li)) != hipSuccess) return hip_fail(e, "tile records");
-    for (int32_t b = 0; b < l.nb; ++b) {   // one tile pass (one kernel dispatch) per bin
+    if (l.nb > 0) {   // one tile pass over every bin of the launch
       TimedLaunch tl;
       if ((e = timed_begin(st, RTMI_KERNEL_TILE, &tl, !plan.no_alloc)) != hipSuccess) return hip_fail(e, "timing");
-      if ((e = rtmi::launch_tile_bin(l.t, b, plan.det, false, st)) != hipSuccess) return hip_fail(e, "tile launch");
+      if ((e = rtmi::launch_tile_bins(l.t, l.nb, plan.det, false, st)) != hipSuccess) return hip_fail(e, "tile launch");
       if ((e = timed_end(st, tl)) != hipSuccess) return hip_fail(e, "timing");
     }
     if (fill_ahead && li + 2 < launches.size()) {   // launch li + 2 reuses this launch's buffer

@@ -120,6 +120,7 @@ struct TileArgs {
   unsigned long long* out_q;
   const double* det_scale;
   long long out_stride;
+  int n_bins = 1;                 // tile kernel: bins of one launch (V, out and corner strided)
   int nx, ny, nz;
   int tiles_x, tiles_y, tiles_z;
   float ds;
@@ -252,6 +253,9 @@ hipError_t launch_tile_run(const TileArgs& a, int n_bins, bool deterministic, bo
                            hipStream_t s);
 // The tile pass of one bin of a launch (launch_tile_run runs every bin's in turn).
 hipError_t launch_tile_bin(const TileArgs& a, int bin, bool deterministic, bool nearest, hipStream_t s);
+// All n_bins bins of the launch in one persistent kernel: its work-groups claim (item, bin)
+// pairs, the bins of an item one after another.
+hipError_t launch_tile_bins(const TileArgs& a, int n_bins, bool deterministic, bool nearest, hipStream_t s);
 hipError_t launch_adjoint_record(const AdjointArgs& a, int n_blocks, hipStream_t s);
 // out[i] = (float) in[i], i < n (the scale gradients, summed in binary64)
 hipError_t launch_f64_to_f32(const double* in, float* out, int n, hipStream_t s);

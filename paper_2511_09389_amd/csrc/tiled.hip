@@ -926,17 +926,22 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
   constexpr int kThreads = kTileThreads;
   __shared__ T acc[kPadVox];
   __shared__ int2 claimed;
+  __shared__ int claimed_bin;
   const int tid = static_cast<int>(threadIdx.x);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const float ds = a.ds;
   double det_scale = 0.0;
   if constexpr (DET) det_scale = *a.det_scale;
-  const int n_items = *a.item_total;
+  // claims run over (item, bin): the bins of one item are taken one after another, so
+  // every bin's heavy items come first and a launch drains once, not once per bin
+  const int n_bins = a.n_bins;
+  const int n_claims = *a.item_total * n_bins;
 
   for (;;) {
     if (tid == 0) {
       const int item = atomicAdd(a.item_next, 1);
-      claimed = item < n_items ? a.item_map[item] : make_int2(-1, 0);
+      claimed = item < n_claims ? a.item_map[item / n_bins] : make_int2(-1, 0);
+      claimed_bin = item < n_claims ? item % n_bins : 0;
     }
     for (int i = tid; i < kPadVox; i += kThreads) acc[i] = T(0);
     __syncthreads();
@@ -951,6 +956,8 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
       break;
     }
     const int part = claimed.y & 0xffff, parts = claimed.y >> 16;
+    const int bin = claimed_bin;
+    const float* const V = a.V + bin * a.v_bin_stride;
     const TileGeom g = tile_geom(a, t);
     const int x0 = g.x0, y0 = g.y0, z0 = g.z0, ex = g.ex, ey = g.ey, ez = g.ez;
     const int faces = tile_faces(g, nx, ny, nz);
@@ -980,7 +987,7 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
       const int kbeg = kblk + static_cast<int>((rec.y >> 3) & 7u), kend = kblk + static_cast<int>(rec.y & 7u);
       const float4 dd = sr->dirs[ray];
       const float4 src = make_float4(sr->sx, sr->sy, sr->sz, 0.0f);
-      const float* vrow = a.V + row_slot(sr->vbase, nrays, ray, kblk);
+      const float* vrow = V + row_slot(sr->vbase, nrays, ray, kblk);
       // the chunk's recorded values, fetched before any of them is needed
       float vv[kChunk];
 #pragma unroll
@@ -1114,8 +1121,8 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
         for (int c = 0; c < 8; ++c) {
           const int vx = (c & 4) ? nx - 1 : 0, vy = (c & 2) ? ny - 1 : 0, vz = (c & 1) ? nz - 1 : 0;
           if (vx == gx && vy == gy && vz == gz) {
-            if constexpr (DET) val += a.corner_q[c];
-            else val += a.corner[c];
+            if constexpr (DET) val += a.corner_q[bin * 8 + c];
+            else val += a.corner[bin * 8 + c];
           }
         }
       }
@@ -1123,13 +1130,13 @@ __global__ void __launch_bounds__(kTileThreads) tile_kernel(const TileArgs a) {
       // with a plain read-modify-write; items sharing a tile add atomically (consecutive
       // lanes hold consecutive z, so the adds of a wave coalesce).
       if constexpr (DET) {
-        unsigned long long* o = a.out_q + voxel;
+        unsigned long long* o = a.out_q + bin * a.out_stride + voxel;
         if (val != 0ull) {
           if (parts > 1) atomicAdd(o, val);
           else *o += val;
         }
       } else {
-        float* o = a.out + voxel;
+        float* o = a.out + bin * a.out_stride + voxel;
         if (val != 0.0) {
           if (parts > 1) unsafeAtomicAdd(o, static_cast<float>(val));
           else *o = static_cast<float>(static_cast<double>(*o) + val);
@@ -1484,6 +1491,14 @@ hipError_t launch_tile_bin(const TileArgs& a, int bin, bool det, bool nearest, h
   if (a.out_q) b.out_q = a.out_q + bin * a.out_stride;
   b.corner = a.corner + bin * 8;
   b.corner_q = a.corner_q + bin * 8;
+  b.n_bins = 1;
+  return launch_tile_one_bin(b, det, nearest, s);
+}
+
+hipError_t launch_tile_bins(const TileArgs& a, int n_bins, bool det, bool nearest, hipStream_t s) {
+  if (n_bins < 1 || n_bins > kMaxBinsPerLaunch) return hipErrorInvalidValue;
+  TileArgs b = a;
+  b.n_bins = n_bins;
   return launch_tile_one_bin(b, det, nearest, s);
 }
 
