@@ -914,7 +914,8 @@ __device__ __forceinline__ int tile_axis(float x, int n, int o, float (&w)[2]) {
   }
 }
 
-// One bin per launch, 512 lanes per work-group, three work-groups per compute unit.
+// Every bin of a launch (claimed item by item), 512 lanes per work-group, three
+// work-groups per compute unit.
 // The tile is accumulated in binary64 (or 64-bit fixed point in the deterministic mode):
 // a voxel next to a source collects thousands of deposits, and binary32 running sums of
 // that length drift by more than the binary32 field is allowed to differ from the exact one.
