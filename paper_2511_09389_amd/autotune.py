@@ -27,7 +27,7 @@ import torch
 
 from . import rtmi
 
-CANDIDATES = (512, 768, 1024, 1536, 2048, 3072)
+CANDIDATES = (512, 768, 1024, 1536, 2048, 3072, 4096, 6144, 8192)
 GROUPS_PER_CU = (0, 2, 1)
 GATHER_TABLE = (0, 1, 3, 2)
 SOURCES_PER_LAUNCH = (0, 32)
